@@ -1,0 +1,337 @@
+"""Seeded synthetic inputs: meshes, fibre fields, heat sources, fixed sets, materials.
+
+This module only *generates inputs*.  It holds none of the method's arithmetic
+(no shape-function derivatives, volumes, lumping, stresses or time stepping):
+both the GPU library and the CPU oracle receive exactly the arrays built here.
+
+Workloads (stand-ins for the paper's meshes, which are not reproducible: the
+verification geometry of Fig. 3 and the liver mesh of Section 6.3 are absent):
+
+* ``cube_t4``      -- 0.04 m cube, 10^3 cells split into 6 Kuhn tetrahedra
+                      (6000 T4, 1331 nodes), Gaussian source, bottom face fixed.
+* ``cube_h8``      -- 0.1 m cube of n^3 reduced-integration hexahedra (64^3 at
+                      full size), smooth random fibre field, T-dependent shear
+                      modulus, 1/r^2 point source on for 60 s then off.
+* ``ellipsoid_t4`` -- noisy ellipsoid 0.2 x 0.15 x 0.1 m voxelised and split
+                      into Kuhn tetrahedra (about 1.0M T4 / 180k nodes at full
+                      size), jittered interior nodes, randomly permuted nodes
+                      and elements, two Prony terms, shrinkage above 323 K,
+                      20 mm line source with 1/r^4 fall-off.
+
+Material parameters follow Table 5 of the paper where the workload takes them
+(transversely isotropic neo-Hookean with eta_a = 2 mu, fibre along x) with the
+values of the workload definitions (E = 3 kPa, nu = 0.45, ...).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+T_BODY = 310.15  # K
+
+# H8 local node order: (xi, eta, zeta) signs (---),(+--),(++-),(-+-),(--+),(+-+),(+++),(-++)
+H8_CORNERS = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                       [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], dtype=np.int64)
+
+# Kuhn split of a unit cube: one tetrahedron per axis permutation, along the
+# main diagonal (0,0,0) -> (1,1,1).  Odd permutations get their last two
+# vertices swapped so that every tetrahedron is positively oriented.
+_PERMS = [(0, 1, 2, False), (0, 2, 1, True), (1, 0, 2, True),
+          (1, 2, 0, False), (2, 0, 1, False), (2, 1, 0, True)]
+
+
+def _kuhn_corner_lists():
+    tets = []
+    for a, b, c, odd in _PERMS:
+        v0 = np.zeros(3, dtype=np.int64)
+        v1 = v0.copy(); v1[a] = 1
+        v2 = v1.copy(); v2[b] = 1
+        v3 = np.ones(3, dtype=np.int64)
+        vs = [v0, v1, v2, v3]
+        if odd:
+            vs = [v0, v1, v3, v2]
+        tets.append([int(v[0] + 2 * v[1] + 4 * v[2]) for v in vs])
+    return np.array(tets, dtype=np.int64)  # 6 x 4 corner codes (bit0 = x, bit1 = y, bit2 = z)
+
+
+KUHN_TETS = _kuhn_corner_lists()
+
+
+def youngs_to_lame(E: float, nu: float):
+    """Shear and bulk moduli from Young's modulus and Poisson's ratio."""
+    return E / (2.0 * (1.0 + nu)), E / (3.0 * (1.0 - 2.0 * nu))
+
+
+def base_material(E: float = 3000.0, nu: float = 0.45) -> dict:
+    mu, kappa = youngs_to_lame(E, nu)
+    return dict(
+        rho=1000.0, mu=mu, kappa=kappa, eta=2.0 * mu, alpha=1e-4, alpha_m=1e-4,
+        T0=T_BODY, k=0.512, k_m=0.512, c=3600.0, wbcb=4e4, T_art=T_BODY, Q_met=0.0,
+        g=[0.5], tau=[0.5], n_prony=1, hg_coef=0.1,
+        muT_on=0, muT_lo=310.0, muT_hi=370.0, muT_drop=0.3,
+        shrink_on=0, shrink_T=323.0, shrink_width=5.0, shrink_eps=-0.05,
+        ckT_on=0, ckT_lo=310.15, ckT_hi=363.15, c_hi=4300.0, k_hi=0.75,
+        expan_mode=0, cond_mode=0,
+    )
+
+
+def paper_table1_material() -> dict:
+    """Isotropic neo-Hookean verification material of Table 1 (alpha as in Table 5)."""
+    m = base_material()
+    m.update(rho=1060.0, c=3700.0, k=0.518, k_m=0.518, mu=1190.476, kappa=19444.444, eta=0.0,
+             g=[], tau=[], n_prony=0, wbcb=0.0, alpha=1e-4, alpha_m=1e-4)
+    return m
+
+
+def paper_table5_material() -> dict:
+    """Liver material of Table 5 (T-dependent c and k from 37 C to 90 C)."""
+    m = base_material()
+    m.update(rho=1060.0, c=3600.0, k=0.53, k_m=0.53, mu=1190.476, kappa=19444.444,
+             eta=2 * 1190.476, alpha=1e-4, alpha_m=1e-4, g=[0.5], tau=[0.58], n_prony=1,
+             wbcb=26.6 * 3617.0, T_art=310.15, T0=310.15, Q_met=33800.0,
+             ckT_on=1, ckT_lo=310.15, ckT_hi=363.15, c_hi=4300.0, k_hi=0.75)
+    return m
+
+
+@dataclass
+class Problem:
+    """Everything a solver needs; arrays are float64 / int32 / uint8."""
+
+    name: str
+    npe: int
+    X: np.ndarray            # nn x 3
+    conn: np.ndarray         # ne x npe
+    params: dict
+    a0: np.ndarray | None = None      # ne x 3
+    q: np.ndarray | None = None       # ne, W/m^3
+    fix: np.ndarray | None = None     # nn uint8 (bit0..2 u, bit3 T)
+    Tfix: np.ndarray | None = None    # nn
+    t_on: float = 0.0
+    t_off: float = math.inf
+    gamma: float = 80.0
+    cfl: float = 0.8
+    nsteps: int = 1000
+    h: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nn(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def ne(self) -> int:
+        return int(self.conn.shape[0])
+
+
+# --------------------------------------------------------------------------
+# Meshes
+# --------------------------------------------------------------------------
+
+def _grid_nodes(n: tuple, h: float, origin=(0.0, 0.0, 0.0)):
+    nx, ny, nz = n
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    ijk = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    X = ijk.astype(np.float64) * h + np.asarray(origin, dtype=np.float64)
+    return ijk, X
+
+
+def _cells_to_mesh(cells: np.ndarray, n: tuple, h: float, origin, kind: str):
+    """cells: m x 3 active cell indices; returns compact nodes X and connectivity."""
+    nx, ny, nz = n
+    stride = np.array([(ny + 1) * (nz + 1), nz + 1, 1], dtype=np.int64)
+    corners = np.array([[b & 1, (b >> 1) & 1, (b >> 2) & 1] for b in range(8)], dtype=np.int64)
+    gid = ((cells[:, None, :] + corners[None, :, :]) * stride).sum(-1)  # m x 8 by corner code
+    if kind == "t4":
+        conn = gid[:, KUHN_TETS].reshape(-1, 4)
+    else:
+        code = H8_CORNERS[:, 0] + 2 * H8_CORNERS[:, 1] + 4 * H8_CORNERS[:, 2]
+        conn = gid[:, code]
+    used, inv = np.unique(conn.ravel(), return_inverse=True)
+    conn = inv.reshape(conn.shape).astype(np.int32)
+    ii = used // stride[0]
+    jj = (used // stride[1]) % (ny + 1)
+    kk = used % (nz + 1)
+    ijk = np.stack([ii, jj, kk], axis=1)
+    X = ijk.astype(np.float64) * h + np.asarray(origin, dtype=np.float64)
+    return X, conn, ijk
+
+
+def box_mesh(kind: str, n: int | tuple, L: float | tuple):
+    """Structured box of n cells per side; kind 't4' (6 Kuhn tets per cell) or 'h8'."""
+    n = (n, n, n) if np.isscalar(n) else tuple(n)
+    L = (L, L, L) if np.isscalar(L) else tuple(L)
+    h = L[0] / n[0]
+    ii, jj, kk = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    cells = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.int64)
+    X, conn, _ = _cells_to_mesh(cells, n, h, (0.0, 0.0, 0.0), kind)
+    return X, conn, h
+
+
+def smooth_fibre_field(P: np.ndarray, L: float, seed: int = 1, n_modes: int = 8):
+    """Unit vectors a0 = normalise(sum_m c_m sin(2 pi k_m . P / L + phi_m)), k_m in {-2..2}^3 \\ {0}."""
+    rng = np.random.default_rng(seed)
+    ks = np.array([(a, b, c) for a in range(-2, 3) for b in range(-2, 3) for c in range(-2, 3)
+                   if (a, b, c) != (0, 0, 0)], dtype=np.float64)
+    kidx = rng.choice(len(ks), size=n_modes, replace=False)
+    K = ks[kidx]
+    C = rng.standard_normal((n_modes, 3))
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    arg = 2.0 * np.pi * (P @ K.T) / L + phi[None, :]
+    v = np.sin(arg) @ C
+    nv = np.linalg.norm(v, axis=1, keepdims=True)
+    bad = nv[:, 0] < 1e-6
+    v[bad] = np.array([1.0, 0.0, 0.0])
+    nv[bad] = 1.0
+    return v / nv
+
+
+def centroids(X: np.ndarray, conn: np.ndarray) -> np.ndarray:
+    return X[conn].mean(axis=1)
+
+
+def _normalise_power(w: np.ndarray, volumes, power: float) -> np.ndarray:
+    """Scale weights so that sum(q_e * element volume) = power (W); volumes may be a scalar."""
+    return w * (power / (w * volumes).sum())
+
+
+def _tet_volumes(X: np.ndarray, conn: np.ndarray) -> np.ndarray:
+    """Input recipe only (total source power): signed tet volumes via numpy's determinant."""
+    d = X[conn[:, 1:]] - X[conn[:, :1]]
+    return np.linalg.det(d.transpose(0, 2, 1)) / 6.0
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+
+def cube_t4(n: int = 10, L: float = 0.04, steps: int = 1000) -> Problem:
+    """0.04 m cube, 10^3 cells x 6 Kuhn tets; Gaussian source sigma 4 mm, 5e7 W/m^3."""
+    X, conn, h = box_mesh("t4", n, L)
+    P = centroids(X, conn)
+    r2 = ((P - L / 2.0) ** 2).sum(1)
+    sigma = 0.004
+    q = 5e7 * np.exp(-r2 / (2.0 * sigma * sigma))
+    fix = np.where(np.isclose(X[:, 2], 0.0), 7, 0).astype(np.uint8)
+    params = base_material()
+    a0 = np.tile(np.array([1.0, 0.0, 0.0]), (conn.shape[0], 1))
+    return Problem("cube_t4", 4, X, conn, params, a0=a0, q=q, fix=fix, gamma=80.0,
+                   nsteps=steps, h=h, meta=dict(n=n, L=L))
+
+
+def cube_h8(n: int = 64, L: float = 0.1, power: float = 10.0, steps: int = 1000,
+            t_on: float = 0.0, t_off: float = 60.0) -> Problem:
+    """0.1 m cube of n^3 H8; fibre field (seed 1), mu(T) drop 30 % 310->370 K, 1/r^2 point source."""
+    X, conn, h = box_mesh("h8", n, L)
+    P = centroids(X, conn)
+    r = np.sqrt(((P - L / 2.0) ** 2).sum(1))
+    r0 = h
+    w = 1.0 / np.maximum(r, r0) ** 2
+    q = _normalise_power(w, h ** 3, power)
+    fix = np.where(np.isclose(X[:, 2], 0.0), 7, 0).astype(np.uint8)
+    params = base_material()
+    params.update(muT_on=1)
+    a0 = smooth_fibre_field(P, L, seed=1)
+    return Problem("cube_h8", 8, X, conn, params, a0=a0, q=q, fix=fix, gamma=80.0,
+                   t_on=t_on, t_off=t_off, nsteps=steps, h=h, meta=dict(n=n, L=L))
+
+
+def _radial_noise(seed: int = 2, lmax: int = 3, amp: float = 0.05):
+    """rho(theta, phi) = 1 + sum_{l,m} (a cos m phi + b sin m phi) P_l^m(cos theta), max |dev| = amp."""
+    from scipy.special import lpmv
+    rng = np.random.default_rng(seed)
+    terms = []
+    for l in range(1, lmax + 1):
+        for m in range(0, l + 1):
+            a, b = rng.standard_normal(2)
+            terms.append((l, m, a, b))
+
+    def raw(th, ph):
+        s = np.zeros_like(th)
+        ct = np.cos(th)
+        for l, m, a, b in terms:
+            s += (a * np.cos(m * ph) + b * np.sin(m * ph)) * lpmv(m, l, ct)
+        return s
+
+    th, ph = np.meshgrid(np.linspace(0, np.pi, 181), np.linspace(0, 2 * np.pi, 361), indexing="ij")
+    scale = amp / np.abs(raw(th, ph)).max()
+    return lambda t, p: 1.0 + scale * raw(t, p)
+
+
+def ellipsoid_t4(target_elems: int = 1_000_000, semi=(0.1, 0.075, 0.05), seed_shape: int = 2,
+                 seed_jitter: int = 0, seed_perm: int = 5, jitter: float = 0.2, power: float = 10.0,
+                 steps: int = 20000, permute: bool = True) -> Problem:
+    """Noisy ellipsoid, voxelised, 6 Kuhn tets per kept cell; ~target_elems T4."""
+    a, b, c = semi
+    vol = 4.0 / 3.0 * np.pi * a * b * c
+    h = (vol / (target_elems / 6.0)) ** (1.0 / 3.0)
+    n = tuple(int(math.ceil(2 * s / h)) + 2 for s in semi)
+    origin = tuple(-(ni * h) / 2.0 for ni in n)
+    rho = _radial_noise(seed_shape)
+    ii, jj, kk = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    cells = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.int64)
+    ctr = (cells + 0.5) * h + np.asarray(origin)
+    p = ctr / np.array(semi)
+    rr = np.linalg.norm(p, axis=1)
+    th = np.arccos(np.clip(p[:, 2] / np.maximum(rr, 1e-300), -1.0, 1.0))
+    ph = np.arctan2(p[:, 1], p[:, 0])
+    inside = rr <= rho(th, ph)
+    cells = cells[inside]
+    X, conn, ijk = _cells_to_mesh(cells, n, h, origin, "t4")
+    # interior nodes: all 8 surrounding cells kept
+    kept = np.zeros(n, dtype=bool)
+    kept[cells[:, 0], cells[:, 1], cells[:, 2]] = True
+    interior = np.ones(len(X), dtype=bool)
+    for dx in (-1, 0):
+        for dy in (-1, 0):
+            for dz in (-1, 0):
+                ci = ijk + np.array([dx, dy, dz])
+                ok = np.all((ci >= 0) & (ci < np.array(n)), axis=1)
+                inner = np.zeros(len(X), dtype=bool)
+                inner[ok] = kept[ci[ok, 0], ci[ok, 1], ci[ok, 2]]
+                interior &= inner
+    rng = np.random.default_rng(seed_jitter)
+    J = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+    X = X + J * interior[:, None]
+    # fixed bottom cap
+    zmin = X[:, 2].min()
+    fix = np.where(X[:, 2] <= zmin + 2.0 * h, 7, 0).astype(np.uint8)
+    if permute:
+        rng = np.random.default_rng(seed_perm)
+        pn = rng.permutation(len(X))        # new -> old
+        inv = np.empty_like(pn)
+        inv[pn] = np.arange(len(X))
+        X = X[pn]
+        fix = fix[pn]
+        conn = inv[conn].astype(np.int32)
+        pe = rng.permutation(len(conn))
+        conn = conn[pe]
+    P = centroids(X, conn)
+    # line source on the x axis, 20 mm long, centred; 1/r^4 with r0 = 1 mm
+    half = 0.010
+    xs = np.clip(P[:, 0], -half, half)
+    d = np.sqrt((P[:, 0] - xs) ** 2 + P[:, 1] ** 2 + P[:, 2] ** 2)
+    w = 1.0 / np.maximum(d, 1e-3) ** 4
+    q = _normalise_power(w, _tet_volumes(X, conn), power)
+    params = base_material()
+    params.update(g=[0.3, 0.2], tau=[0.1, 2.0], n_prony=2, shrink_on=1)
+    a0 = smooth_fibre_field(P - np.asarray(origin), 2 * a, seed=1)
+    return Problem("ellipsoid_t4", 4, X, conn.astype(np.int32), params, a0=a0, q=q, fix=fix,
+                   gamma=80.0, nsteps=steps, h=h, meta=dict(target=target_elems, grid=n))
+
+
+def random_state(problem: Problem, seed: int, u_scale: float, dT_scale: float):
+    """A smooth-ish random state (u, u_prev, T) for single-step checks."""
+    rng = np.random.default_rng(seed)
+    X = problem.X
+    ctr = X.mean(0)
+    u = u_scale * (rng.standard_normal((1, 3)) + np.sin(40.0 * (X - ctr)) @ rng.standard_normal((3, 3)))
+    up = u * (1.0 - 1e-3) + 1e-2 * u_scale * rng.standard_normal(u.shape)
+    T = problem.params["T0"] + dT_scale * (1.0 + np.cos(60.0 * (X - ctr)).sum(1)) / 4.0
+    if problem.fix is not None:
+        m = problem.fix
+        for i in range(3):
+            u[(m >> i) & 1 == 1, i] = 0.0
+            up[(m >> i) & 1 == 1, i] = 0.0
+    return u, up, T
