@@ -1,0 +1,146 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled TLED + Pennes step on one MI355X.
+
+One step = one pass of the whole hot path (element physics, assembly, node
+updates) over the ~1.0M-tet noisy-ellipsoid workload (0.2 x 0.15 x 0.1 m,
+~180k nodes, two Prony terms, shrinkage, 1/r^4 line source).  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--variant 1|2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per element-update of the dominant kernel (T4, two Prony
+# terms): connectivity 16 + dh/dX 36 + V0 4 + fibre 12 + Prony state read and
+# written 96 = 164 B, plus 73 B per node of node state advanced inside it.
+ELEM_BYTES_T4_NP2 = 164.0
+NODE_BYTES = 73.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--variant", type=int, default=2)
+    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--elems", type=int, default=1_000_000)
+    ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_name: str, n_launch_units: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        from paper_2009_10400_amd.build import source_digest
+        if d.get("source_digest") != source_digest() or d.get("kernel") != kernel_name:
+            return None
+        return float(d["bytes_per_launch"])
+    except Exception:  # noqa: BLE001
+        return None
+
+
+def cpu_baseline(problem, dt, steps):
+    import oracle
+    oracle.build()
+    o = oracle.OracleSim(problem.npe, problem.X, problem.conn, problem.params, a0=problem.a0, q=problem.q,
+                         fix=problem.fix, t_on=problem.t_on, t_off=problem.t_off, dt=dt, gamma=problem.gamma)
+    st = o.initial_state(problem.params["T0"])
+    o.run(st, 1)                     # first touch of the state arrays
+    t0 = time.perf_counter()
+    o.run(st, steps)
+    el = time.perf_counter() - t0
+    return {"value": problem.ne * steps / el, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the full {problem.ne}-tet workload, serial FP64 oracle ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU domain decomposition is a design, not built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2009_10400_amd import tled, workloads as W
+
+    t = time.time()
+    p = W.ellipsoid_t4(args.elems)
+    log(f"[bench] workload ne={p.ne} nn={p.nn} built in {time.time() - t:.1f}s")
+    t = time.time()
+    stream = torch.cuda.Stream(device=0)
+    sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, kernel_variant=args.variant,
+                            graph_steps=args.graph_steps)
+    info = sim.info()
+    log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.sync()
+    ms_per_step = 1e3 * el / args.steps
+    value = p.ne * args.steps / el
+    log(f"[bench] timed {args.steps} steps in {el:.3f}s -> {value:.4g} element-updates/s")
+
+    # dominant kernel, timed with HIP events on the library's stream
+    kt = sim.kernel_times(args.kernel_steps)
+    sim.sync()
+    kname = "patch_kernel" if info["kernel_variant"] == 2 else "t4_element_kernel"
+    if info["kernel_variant"] == 2:
+        n_interior = info["n_nodes"] - info["n_shared_nodes"]
+        alg_bytes = ELEM_BYTES_T4_NP2 * p.ne + NODE_BYTES * n_interior
+    else:
+        alg_bytes = ELEM_BYTES_T4_NP2 * p.ne + 16.0 * 4 * p.ne   # plus the nodal outputs it writes
+    achieved = alg_bytes / (kt["element_ms"] * 1e-3) / 1e9
+    traffic = traffic_from_profiles(kname, p.ne)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
+            "kernel_ms": kt["element_ms"], "second_kernel_ms": kt["node_ms"],
+            "algorithmic_bytes_per_launch": alg_bytes}
+    log(f"[bench] kernel times {kt}")
+    out = {
+        "metric": "coupled element-updates/s (HBM % peak)",
+        "value": value, "unit": "element-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"noisy ellipsoid 0.2x0.15x0.1 m, {p.ne} T4 / {p.nn} nodes, 2 Prony terms, "
+                               f"shrinkage above 323 K, 20 mm 1/r^4 line source (10 W), random numbering",
+                   "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
+                   "graph_steps": args.graph_steps, "dt": sim.dt},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        steps = args.cpu_steps or max(3, int(12e6 / p.ne))
+        log(f"[bench] CPU baseline: oracle {steps} steps")
+        out["cpu_baseline"] = cpu_baseline(p, sim.dt, steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * tled.h -- C-ABI of the MI355X coupled thermo-visco-hyperelastic TLED +
+ * explicit Pennes bioheat solver (Zhang, Lay, Roberts, Chauhan,
+ * arXiv 2009.10400).
+ *
+ * One time step of the method (Section 4, Eqs. 12-28):
+ *   per element: F from nodal displacements and precomputed dh/dX (Eq. 17);
+ *     thermal split F = F_el F_th with F_th = lambda I (Eqs. 7-8, 11);
+ *     fibre-reinforced neo-Hookean stress on the elastic part (Eq. 9,
+ *     Table 5 model) pulled back to the reference configuration (Eq. 10);
+ *     Prony relaxation (recursion after Eq. 27); nodal forces V0 F S dh/dX
+ *     (Eqs. 24-26, 28); pulled-back conduction loads (Eqs. 16, 18-19);
+ *   per node: forward Euler on temperature (Eq. 20) and central difference
+ *     with mass-proportional damping on displacement (Eqs. 22, 27).
+ *
+ * Conventions
+ *   - Units are SI; temperatures in kelvin.
+ *   - Host inputs are double arrays, row-major ("n x 3" = x,y,z per row).
+ *     The library copies every input at call time; the caller keeps
+ *     ownership of its buffers.  Device state is single precision and owned
+ *     by the library (allocated at tled_finalize through the allocator set
+ *     with tled_set_allocator, else hipMalloc, and freed by tled_destroy).
+ *   - Node and element numbers are those of the caller; the library may
+ *     reorder internally and undoes it on every read.
+ *   - Every call returns a tled_status; nothing aborts and no C++ exception
+ *     crosses the boundary.  tled_last_error() gives the message of the last
+ *     failure on a handle.
+ *   - tled_step is asynchronous on the library's stream; errors raised on the
+ *     device (non-finite values, inverted elements) surface as
+ *     TLED_E_UNSTABLE at the next tled_sync, read or monitor call.
+ *   - A handle is not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef TLED_H
+#define TLED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLED_OK = 0,
+    TLED_E_ARG = -1,          /* bad argument (null pointer, size, range)          */
+    TLED_E_MESH = -2,         /* degenerate or inverted element, bad connectivity  */
+    TLED_E_STATE = -3,        /* call out of order (e.g. step before finalize)     */
+    TLED_E_HIP = -4,          /* HIP runtime error                                 */
+    TLED_E_OOM = -5,          /* host or device allocation failed                  */
+    TLED_E_UNSTABLE = -6,     /* device raised non-finite values or J <= 0         */
+    TLED_E_UNSUPPORTED = -7   /* option not available on this build                */
+} tled_status;
+
+typedef struct tled_sim tled_sim;
+
+/* Element types: the value is the number of nodes per element. */
+enum { TLED_T4 = 4, TLED_H8 = 8 };
+
+/* Bits of tled_monitors.flags. */
+enum { TLED_FLAG_NONFINITE = 1u, TLED_FLAG_INVERTED = 2u };
+
+/*
+ * Material and load parameters (Tables 1 and 5).
+ * Strain energy Psi = mu/2 (I1bar - 3) + eta/2 (I4bar - 1)^2 + kappa/2 (J - 1)^2
+ * (Table 5) evaluated on the elastic deformation.  Thermal stretch
+ * lambda = 1 + alpha (T - T0) (Section 3.2, after Eq. 11).
+ */
+typedef struct {
+    double rho;          /* reference density, kg/m^3                                  */
+    double mu;           /* shear modulus at T0, Pa                                    */
+    double kappa;        /* bulk modulus, Pa                                           */
+    double eta;          /* fibre coefficient eta_a, Pa (0: isotropic neo-Hookean)    */
+    double alpha;        /* thermal expansion coefficient, 1/K                         */
+    double alpha_m;      /* expansion along the fibre when expan_mode = 1              */
+    double T0;           /* stress-free reference and initial temperature, K          */
+    double k;            /* thermal conductivity, W/(m K)                              */
+    double k_m;          /* conductivity along the fibre when cond_mode = 1            */
+    double c;            /* specific heat capacity, J/(kg K)                           */
+    double wbcb;         /* blood perfusion w_b c_b, W/(m^3 K)                         */
+    double T_art;        /* arterial blood temperature, K                              */
+    double Q_met;        /* metabolic heat generation, W/m^3                           */
+    double g[4];         /* Prony relative moduli phi_i (sum < 1)                      */
+    double tau[4];       /* Prony relaxation times, s                                  */
+    double muT_lo, muT_hi, muT_drop;           /* mu, eta scaled by 1 - drop * clamp((T - lo)/(hi - lo)) */
+    double shrink_T, shrink_width, shrink_eps; /* lambda scaled by 1 + eps * clamp((T - shrink_T)/width)  */
+    double ckT_lo, ckT_hi, c_hi, k_hi;         /* c(T), k(T) linear from (lo: c, k) to (hi: c_hi, k_hi) */
+    double hg_coef;      /* H8 hourglass coefficient (stiffness hg_coef (kappa + 4 mu/3) V0 sum|dh/dX|^2 / 8) */
+    int32_t n_prony;     /* 0..4                                                       */
+    int32_t expan_mode;  /* 0: F_th = lambda I; 1: lambda I + (lambda_m - lambda) a0 a0 (Eq. 11) */
+    int32_t cond_mode;   /* 0: D = k I; 1: D = k I + (k_m - k) a0 a0                    */
+    int32_t muT_on;      /* 1: temperature-dependent mu and eta                        */
+    int32_t shrink_on;   /* 1: shrinkage factor on lambda                             */
+    int32_t ckT_on;      /* 1: temperature-dependent c (per node) and k (per element)  */
+} tled_material;
+
+/* Execution options (all optional; zero fields keep the defaults). */
+typedef struct {
+    int32_t graph_steps;      /* steps per chunk: a chunk is one hipGraph replay (default 50;
+                                 < 0: eager launches in chunks of 100).  Monitors are reduced
+                                 at the last step of every chunk and of every tled_step call. */
+    int32_t kernel_variant;   /* 0: auto, 1: two-pass element/node kernels, 2: fused patch kernels */
+    int32_t reorder;          /* 0: auto (on), 1: on, -1: keep the caller's order             */
+    int32_t block_size;       /* threads per block for the element pass (0: default)         */
+    int32_t patch_elems;      /* elements per patch for the fused variant (0: default)        */
+    double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */
+} tled_options;
+
+typedef struct {
+    int64_t step;            /* steps completed since tled_finalize                          */
+    double  t;               /* simulated time = step * dt, s                                 */
+    double  kinetic;         /* 1/2 sum_a M_a |v_a|^2 with v at the half step, J              */
+    double  strain;          /* sum_e V0 det(F_th) Psi (+ H8 hourglass energy), J             */
+    double  T_max;           /* max nodal temperature, K                                      */
+    double  T_min;           /* min nodal temperature, K                                      */
+    double  ablated_volume;  /* lumped volume of nodes with T >= ablation_T, m^3              */
+    uint32_t flags;          /* TLED_FLAG_* raised since finalize                            */
+    uint32_t reserved;
+} tled_monitors;
+
+typedef struct {
+    int64_t n_nodes, n_elems;
+    int32_t elem_type;
+    int32_t n_prony;
+    int64_t n_swapped;       /* T4 elements repaired by swapping their last two nodes         */
+    int32_t kernel_variant;  /* variant in use after finalize                                 */
+    int32_t n_patches;       /* fused variant: number of element patches                     */
+    int64_t n_shared_nodes;  /* fused variant: nodes assembled across patches                */
+    int64_t device_bytes;    /* device memory held by the handle                              */
+    double  dt, dt_critical;
+} tled_info;
+
+/* --- lifetime ----------------------------------------------------------
+ * tled_create: device >= 0 selects a GPU ordinal; device = -1 creates a
+ * host-only handle that supports set-up, tled_critical_dt, tled_get_lumped and
+ * tled_finalize (precompute only) but no stepping (TLED_E_STATE).           */
+tled_status tled_create(tled_sim **out, int device);
+void        tled_destroy(tled_sim *sim);
+
+/* Optional device allocator: alloc(bytes, ctx) returns device memory or NULL;
+ * release(ptr, ctx) frees it.  Must be set before tled_finalize. */
+tled_status tled_set_allocator(tled_sim *sim, void *(*alloc)(size_t, void *),
+                               void (*release)(void *, void *), void *ctx);
+/* Stream (hipStream_t) used for every launch and copy; NULL = the null stream.
+ * Must be set before tled_finalize. */
+tled_status tled_set_stream(tled_sim *sim, void *hip_stream);
+tled_status tled_set_options(tled_sim *sim, const tled_options *opt);
+
+/* --- problem definition (before tled_finalize) --------------------------
+ * Mesh (Section 4.1, low-order elements): elem_type TLED_T4 or TLED_H8;
+ * X n_nodes x 3 reference coordinates; conn n_elems x elem_type node indices
+ * (0-based).  H8 local order (xi,eta,zeta) = (---),(+--),(++-),(-+-),(--+),
+ * (+-+),(+++),(-++).  T4 elements of negative volume are repaired by swapping
+ * their last two nodes (counted in tled_info.n_swapped); a zero-volume T4 or
+ * an H8 with det J0 <= 0 makes tled_finalize fail with TLED_E_MESH. */
+tled_status tled_set_mesh(tled_sim *sim, int elem_type, int64_t n_nodes, const double *X,
+                          int64_t n_elems, const int32_t *conn);
+tled_status tled_set_material(tled_sim *sim, const tled_material *m);
+/* Fibre directions a0, n_elems x 3, normalised inside (Table 5: unit vector a0).
+ * Default: (1, 0, 0) for every element. */
+tled_status tled_set_fibres(tled_sim *sim, const double *a0);
+/* Fixed displacement components: node[i] with mask[i] bits 0..2 = x, y, z.
+ * Fixed components stay at zero displacement.  Repeated calls accumulate. */
+tled_status tled_set_fixed_dofs(tled_sim *sim, int64_t n, const int32_t *node, const uint8_t *mask);
+/* Fixed temperatures (Dirichlet): node[i] held at T[i] (K). */
+tled_status tled_set_fixed_temperature(tled_sim *sim, int64_t n, const int32_t *node, const double *T);
+/* Regional heat source Q_r (Eq. 1) per element, W/m^3, lumped to nodes with the
+ * reference volume V0/npe; active while t_on <= step*dt < t_off. */
+tled_status tled_set_heat_source(tled_sim *sim, const double *q_elem, double t_on, double t_off);
+/* Time step dt (s) and mass-proportional damping coefficient gamma (1/s),
+ * D = gamma M (Eq. 21).  tled_finalize fails with TLED_E_ARG if dt exceeds
+ * the critical step. */
+tled_status tled_set_time(tled_sim *sim, double dt, double damping_gamma);
+/* Critical time step min_e L_e / c_d, c_d = sqrt((kappa + 4 mu/3 + 4 eta)/rho),
+ * L_e = 3 V0 / A_max (T4) or V0 / A_max (H8).  Needs mesh and material. */
+tled_status tled_critical_dt(tled_sim *sim, double *dt_cr);
+
+/* Precompute (FP64 on the host: dh/dX, V0, lumped M, C, K_b, Q), reorder,
+ * build the assembly lists, round to FP32 and upload.  Initial state:
+ * u = v = 0, T = T0 (fixed-T nodes at their value), Prony state 0. */
+tled_status tled_finalize(tled_sim *sim);
+
+/* --- stepping ----------------------------------------------------------- */
+tled_status tled_step(tled_sim *sim, int64_t n_steps);
+/* Wait for the stream and report device-raised errors. */
+tled_status tled_sync(tled_sim *sim);
+
+/* --- outputs (synchronous; caller numbering) ----------------------------- */
+tled_status tled_read_u(tled_sim *sim, double *u /* n_nodes x 3 */);
+tled_status tled_read_T(tled_sim *sim, double *T /* n_nodes, K */);
+/* Device-to-device copy of the fields in caller numbering, FP32:
+ * u_dst n_nodes x 3, T_dst n_nodes (K).  Either pointer may be NULL.
+ * Asynchronous on the library's stream. */
+tled_status tled_copy_fields_device(tled_sim *sim, float *u_dst, float *T_dst);
+tled_status tled_get_monitors(tled_sim *sim, tled_monitors *out);
+tled_status tled_get_info(tled_sim *sim, tled_info *out);
+/* Lumped host-precomputed quantities in caller numbering (any may be NULL):
+ * reference volume, mass, heat capacity (at T0), perfusion, metabolic and source loads. */
+tled_status tled_get_lumped(tled_sim *sim, double *Vl, double *M, double *C, double *Kb,
+                            double *Qm, double *Qr);
+
+/* --- state --------------------------------------------------------------
+ * Typed state in caller numbering: u n_nodes x 3 (m), v n_nodes x 3 velocity
+ * at the last half step (m/s), T n_nodes (K), theta n_elems x n_prony x 6
+ * Prony state (xx, yy, zz, xy, yz, xz; Pa), step.  Any array may be NULL on
+ * read; on write NULL leaves that part unchanged. */
+tled_status tled_read_state(tled_sim *sim, double *u, double *v, double *T, double *theta,
+                            int64_t *step);
+tled_status tled_write_state(tled_sim *sim, const double *u, const double *v, const double *T,
+                             const double *theta, int64_t step);
+/* Opaque bitwise checkpoint of the device state (restoring it and stepping
+ * reproduces the uninterrupted run bit for bit). */
+tled_status tled_state_size(tled_sim *sim, size_t *bytes);
+tled_status tled_get_state(tled_sim *sim, void *buf);
+tled_status tled_set_state(tled_sim *sim, const void *buf);
+
+/* --- measurement ---------------------------------------------------------
+ * Runs n_steps eagerly with a HIP event pair around every launch on the
+ * library's stream and returns the mean duration (ms) per launch of each
+ * kernel kind: ms[0] element (or fused patch) kernel, ms[1] node (or shared-
+ * node) kernel, ms[2] monitor reduction.  Advances the state like tled_step. */
+tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]);
+
+const char *tled_status_string(tled_status s);
+const char *tled_last_error(const tled_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLED_H */

@@ -1,0 +1,86 @@
+// Launch interface of the TLED kernels (host side of kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tled.h"
+#include "device_math.h"
+
+namespace tled {
+
+constexpr int kBlock = 256;   // threads per block (4 wavefronts of 64)
+constexpr int kNumXcd = 8;    // accelerator complex dies of an MI355X
+
+// Node-update constants.
+struct NodeParams {
+    float A;          // (1 - gamma dt/2) / (1 + gamma dt/2)
+    float dt;
+    float T0;
+    float rho;
+    float abl_T;      // ablation threshold temperature, K
+    float ck_lo, ck_inv, c_lo, c_hi;   // c(T) law (when enabled)
+    long long n_on, n_off;             // source active for n_on <= step < n_off
+};
+
+// Monitor record written by the finish kernel.
+struct DevMonitors {
+    long long step;
+    double kinetic, strain, T_max, T_min, ablated;
+    unsigned flags;
+    unsigned pad;
+};
+
+struct TwoPassArgs {
+    int ne, nn;
+    const int4 *conn4, *conn4b;          // T4: conn4; H8: conn4 (nodes 0-3), conn4b (4-7)
+    const float4 *g0, *g1, *g2;          // geometry planes
+    const float4 *hg0, *hg1, *hg2;       // H8 hourglass c_alpha planes
+    const float *khg;
+    float4 *nu4, *nv4;                   // node state (u, dT), (v, B)
+    const float4 *nth;                   // node thermal constants
+    const uint8_t *mask;
+    const float *Vl;
+    float *theta;
+    float4 *out;                         // ne * npe element-slot outputs
+    const int *rowptr, *inc;
+    const long long *step_base;
+    unsigned *status;
+    double *part_elem, *part_node;
+};
+
+struct PatchArgs {
+    int ne, n_patches, max_nodes, max_elems;
+    int n_interior, n_shared;
+    const int *elem_begin, *int_begin, *shared_begin, *shared_ids;
+    const uint16_t *lconn, *lrow, *lslot;
+    const int *lrow_begin;
+    const int *srow, *sidx;
+    const float4 *g0, *g1, *g2, *hg0, *hg1, *hg2;
+    const float *khg;
+    float4 *nu4, *nv4;
+    const float4 *nth;
+    const uint8_t *mask;
+    const float *Vl;
+    float *theta;
+    float4 *partial;
+    const long long *step_base;
+    unsigned *status;
+    double *part_elem, *part_node;
+};
+
+void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s);
+void launch_node(bool mon, bool ckt, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
+void launch_patch(int npe, int np, bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p,
+                  int j, hipStream_t s);
+void launch_shared_nodes(bool mon, bool ckt, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s);
+void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,
+                   long long *step_base, int k, const unsigned *status, DevMonitors *mon, hipStream_t s);
+size_t patch_lds_bytes(int npe, const PatchArgs &a);
+
+}  // namespace tled
+
+namespace tled {
+void launch_export_fields(const float4 *nu4, const int *new2old, int nn, float T0, float *u_dst, float *T_dst,
+                          hipStream_t s);
+}  // namespace tled

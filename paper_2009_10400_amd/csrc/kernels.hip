@@ -1,0 +1,689 @@
+// HIP kernels of one coupled TLED + Pennes time step for CDNA4 (gfx950).
+//
+// Two variants share the element physics of device_math.h:
+//   two-pass: element kernel (one thread per element) writes its npe nodal
+//     (force, heat) contributions; node kernel (one thread per node) sums its
+//     incident contributions in a fixed order and advances the node;
+//   fused patch: one workgroup per patch of contiguous elements stages the
+//     patch nodes in LDS, computes the elements, assembles and advances the
+//     patch-interior nodes in LDS, and writes partial sums for the nodes it
+//     shares with other patches; a shared-node kernel finishes those.
+// No atomics in the assembly; every sum has a fixed order, so a run is
+// bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.h"
+#include "kernels.h"
+
+namespace tled {
+
+// Workgroups are dispatched round-robin over the XCDs; map them so that
+// consecutive logical blocks (neighbouring elements in the locality order)
+// run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int q = G / kNumXcd, r = G % kNumXcd;
+    const int x = b % kNumXcd, i = b / kNumXcd;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ __forceinline__ bool finite4(float4 v) {
+    return isfinite(v.x) && isfinite(v.y) && isfinite(v.z) && isfinite(v.w);
+}
+
+// Block-wide sum of a double, then one partial per block (fixed order).
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BS / 64; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+template <int BS>
+__device__ __forceinline__ float block_max(float v, float *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    float s = -INFINITY;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BS / 64; ++i) s = fmaxf(s, sh[i]);
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ void raise_flags(unsigned *status, bool nonfinite, bool inverted) {
+    // one atomic per wavefront, only when something went wrong
+    unsigned f = (nonfinite ? TLED_FLAG_NONFINITE : 0u) | (inverted ? TLED_FLAG_INVERTED : 0u);
+    unsigned long long any = __ballot(f != 0u);
+    if (any) {
+        unsigned fw = f;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) fw |= __shfl_xor(fw, o);
+        if ((threadIdx.x & 63) == 0) atomicOr(status, fw);
+    }
+}
+
+// ---------------------------------------------------------------- element math
+
+struct ElemResultT4 {
+    float4 o[4];
+    float psiV;
+    bool nonfinite, inverted;
+};
+
+// T4: node data u4 = (ux, uy, uz, dT); geometry g0,g1,g2 = (b1, b2, b3, V0, fibre oct).
+template <int NP, bool MON>
+__device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], float4 g0, float4 g1, float4 g2,
+                                           float *th, ElemResultT4 &r) {
+    const float b[3][3] = {{g0.x, g0.y, g0.z}, {g0.w, g1.x, g1.y}, {g1.z, g1.w, g2.x}};
+    const float V0 = g2.y;
+    float a[3];
+    oct_decode(g2.z, g2.w, a);
+    float d[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        d[k][0] = u[k + 1].x - u[0].x;
+        d[k][1] = u[k + 1].y - u[0].y;
+        d[k][2] = u[k + 1].z - u[0].z;
+        d[k][3] = u[k + 1].w - u[0].w;
+    }
+    float H[9], gT[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) H[3 * i + j] = d[0][i] * b[0][j] + d[1][i] * b[1][j] + d[2][i] * b[2][j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gT[j] = d[0][3] * b[0][j] + d[1][3] * b[1][j] + d[2][3] * b[2][j];
+    const float dTe = 0.25f * (u[0].w + u[1].w + u[2].w + u[3].w);
+    ElemOut eo;
+    element_physics<NP>(m, H, gT, dTe, a, V0, th, MON, eo);
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float4 f;
+        f.x = eo.PV[0] * b[k][0] + eo.PV[1] * b[k][1] + eo.PV[2] * b[k][2];
+        f.y = eo.PV[3] * b[k][0] + eo.PV[4] * b[k][1] + eo.PV[5] * b[k][2];
+        f.z = eo.PV[6] * b[k][0] + eo.PV[7] * b[k][1] + eo.PV[8] * b[k][2];
+        f.w = eo.qV[0] * b[k][0] + eo.qV[1] * b[k][1] + eo.qV[2] * b[k][2];
+        r.o[k + 1] = f;
+        s.x += f.x; s.y += f.y; s.z += f.z; s.w += f.w;
+    }
+    r.o[0] = make_float4(-s.x, -s.y, -s.z, -s.w);
+    r.psiV = MON ? eo.psiV : 0.0f;
+    r.inverted = !(eo.Jmin > 0.0f);
+    r.nonfinite = !(finite4(r.o[0]) && finite4(r.o[1]) && finite4(r.o[2]) && finite4(r.o[3]));
+}
+
+// H8 natural-coordinate signs (---),(+--),(++-),(-+-),(--+),(+-+),(+++),(-++) and
+// hourglass base vectors eta zeta, zeta xi, xi eta, xi eta zeta.
+__device__ __forceinline__ float hsx(int a) { return (a == 1 || a == 2 || a == 5 || a == 6) ? 1.f : -1.f; }
+__device__ __forceinline__ float hsy(int a) { return (a == 2 || a == 3 || a == 6 || a == 7) ? 1.f : -1.f; }
+__device__ __forceinline__ float hsz(int a) { return (a >= 4) ? 1.f : -1.f; }
+
+struct ElemResultH8 {
+    float4 o[8];
+    float psiV;
+    bool nonfinite, inverted;
+};
+
+// H8 one-point: G = J0^-T (dh_a/dX = G s_a / 8), c_alpha = X^T h_alpha, k_hg.
+template <int NP, bool MON>
+__device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], float4 g0, float4 g1, float4 g2,
+                                           const float c[12], float khg, float *th, ElemResultH8 &r) {
+    const float G[9] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x};
+    const float V0 = g2.y;
+    float a[3];
+    oct_decode(g2.z, g2.w, a);
+    // U_ik = sum_a u_a,i s_a,k / 8 ; t_k = sum_a dT_a s_a,k / 8 ; hourglass sums
+    float U[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, t[3] = {0, 0, 0};
+    float hu[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    float dsum = 0.f;
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const float s[3] = {hsx(n), hsy(n), hsz(n)};
+        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
+        const float uv[4] = {u[n].x, u[n].y, u[n].z, u[n].w};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) U[i][k] += s[k] * uv[i];
+#pragma unroll
+            for (int al = 0; al < 4; ++al) hu[al][i] += h[al] * uv[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k] += s[k] * uv[3];
+        dsum += uv[3];
+    }
+    float H[9], gT[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            H[3 * i + j] = 0.125f * (U[i][0] * G[3 * j] + U[i][1] * G[3 * j + 1] + U[i][2] * G[3 * j + 2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gT[j] = 0.125f * (G[3 * j] * t[0] + G[3 * j + 1] * t[1] + G[3 * j + 2] * t[2]);
+    const float dTe = 0.125f * dsum;
+    ElemOut eo;
+    element_physics<NP>(m, H, gT, dTe, a, V0, th, MON, eo);
+    // hourglass: q_alpha = sum_a h_alpha,a u_a - H c_alpha ; W = sum_alpha q_alpha c_alpha^T
+    float q[4][3], W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float ehg = 0.f;
+#pragma unroll
+    for (int al = 0; al < 4; ++al) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            q[al][i] = hu[al][i] - (H[3 * i] * c[3 * al] + H[3 * i + 1] * c[3 * al + 1] + H[3 * i + 2] * c[3 * al + 2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) W[3 * i + j] += q[al][i] * c[3 * al + j];
+        ehg += q[al][0] * q[al][0] + q[al][1] * q[al][1] + q[al][2] * q[al][2];
+    }
+    // f_a = Q s_a + khg sum_alpha h_alpha,a q_alpha with Q = (PV - khg W) G / 8 ; h_a = s_a . (G^T qV / 8)
+    float Q[9], rq[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc += (eo.PV[3 * i + j] - khg * W[3 * i + j]) * G[3 * j + k];
+            Q[3 * i + k] = 0.125f * acc;
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        rq[k] = 0.125f * (G[k] * eo.qV[0] + G[3 + k] * eo.qV[1] + G[6 + k] * eo.qV[2]);
+    bool nf = false;
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const float s[3] = {hsx(n), hsy(n), hsz(n)};
+        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
+        float4 f;
+        f.x = Q[0] * s[0] + Q[1] * s[1] + Q[2] * s[2] + khg * (h[0] * q[0][0] + h[1] * q[1][0] + h[2] * q[2][0] + h[3] * q[3][0]);
+        f.y = Q[3] * s[0] + Q[4] * s[1] + Q[5] * s[2] + khg * (h[0] * q[0][1] + h[1] * q[1][1] + h[2] * q[2][1] + h[3] * q[3][1]);
+        f.z = Q[6] * s[0] + Q[7] * s[1] + Q[8] * s[2] + khg * (h[0] * q[0][2] + h[1] * q[1][2] + h[2] * q[2][2] + h[3] * q[3][2]);
+        f.w = rq[0] * s[0] + rq[1] * s[1] + rq[2] * s[2];
+        r.o[n] = f;
+        nf |= !finite4(f);
+    }
+    r.psiV = MON ? eo.psiV + 0.5f * khg * ehg : 0.0f;
+    r.inverted = !(eo.Jmin > 0.0f);
+    r.nonfinite = nf;
+}
+
+__device__ __forceinline__ void load_theta(const float *__restrict__ theta, size_t ne, size_t e, int np, float *th) {
+    for (int k = 0; k < 6 * np; ++k) th[k] = theta[size_t(k) * ne + e];
+}
+__device__ __forceinline__ void store_theta(float *__restrict__ theta, size_t ne, size_t e, int np, const float *th) {
+    for (int k = 0; k < 6 * np; ++k) theta[size_t(k) * ne + e] = th[k];
+}
+
+// ---------------------------------------------------------------- node update
+
+struct NodeNew {
+    float4 u, v;
+    bool nonfinite;
+};
+
+// Eq. 20 (temperature, forward Euler; conduction with a minus sign) and the
+// velocity form of the central difference of Eq. 27 (R = 0, D = gamma M):
+//   v+ = A v- - B f,  A = (1 - gamma dt/2)/(1 + gamma dt/2),  B = dt / (M (1 + gamma dt/2)),
+//   u+ = u + dt v+.
+template <bool CKT>
+__device__ __forceinline__ NodeNew node_advance(const NodeParams &p, float4 u, float4 v, float4 th, unsigned mk,
+                                                float4 acc, float src) {
+    NodeNew r;
+    float dT = u.w;
+    if (!(mk & 8u)) {
+        float dtC = th.x;
+        if (CKT) {
+            float w = clamp01f((p.T0 + dT - p.ck_lo) * p.ck_inv);
+            dtC = dtC / (p.c_lo + w * (p.c_hi - p.c_lo));
+        }
+        dT = dT + dtC * (-acc.w - th.y * dT + th.z + src * th.w);
+    }
+    const float B = v.w;
+    float vx = (mk & 1u) ? 0.f : p.A * v.x - B * acc.x;
+    float vy = (mk & 2u) ? 0.f : p.A * v.y - B * acc.y;
+    float vz = (mk & 4u) ? 0.f : p.A * v.z - B * acc.z;
+    r.v = make_float4(vx, vy, vz, B);
+    r.u = make_float4((mk & 1u) ? 0.f : u.x + p.dt * vx, (mk & 2u) ? 0.f : u.y + p.dt * vy,
+                      (mk & 4u) ? 0.f : u.z + p.dt * vz, dT);
+    r.nonfinite = !(finite4(r.u) && isfinite(vx) && isfinite(vy) && isfinite(vz));
+    return r;
+}
+
+struct NodeMon {
+    double ke;
+    float tmax, tmin;
+    double abl;
+};
+
+__device__ __forceinline__ void node_monitor(const NodeParams &p, const NodeNew &r, float Vl, NodeMon &mo) {
+    mo.ke += 0.5 * double(p.rho) * double(Vl) * double(r.v.x * r.v.x + r.v.y * r.v.y + r.v.z * r.v.z);
+    float T = p.T0 + r.u.w;
+    mo.tmax = fmaxf(mo.tmax, T);
+    mo.tmin = fminf(mo.tmin, T);
+    if (T >= p.abl_T) mo.abl += double(Vl);
+}
+
+template <int BS>
+__device__ __forceinline__ void write_node_partials(NodeMon mo, double *part, double *shd, float *shf) {
+    double ke = block_sum<BS>(mo.ke, shd);
+    double abl = block_sum<BS>(mo.abl, shd);
+    float tmax = block_max<BS>(mo.tmax, shf);
+    float tmin = -block_max<BS>(-mo.tmin, shf);
+    if (threadIdx.x == 0) {
+        double *pp = part + 4 * size_t(blockIdx.x);
+        pp[0] = ke; pp[1] = tmax; pp[2] = tmin; pp[3] = abl;
+    }
+}
+
+__device__ __forceinline__ float source_switch(const NodeParams &p, const long long *step_base, int j) {
+    const long long n = *step_base + j;
+    return (n >= p.n_on && n < p.n_off) ? 1.0f : 0.0f;
+}
+
+// ---------------------------------------------------------------- two-pass kernels
+
+template <int NP, bool MON>
+__global__ __launch_bounds__(kBlock) void t4_element_kernel(
+    const int4 *__restrict__ conn, const float4 *__restrict__ g0, const float4 *__restrict__ g1,
+    const float4 *__restrict__ g2, const float4 *__restrict__ nu4, float *__restrict__ theta,
+    float4 *__restrict__ out, int ne, KMat m, unsigned *__restrict__ status, double *__restrict__ part) {
+    __shared__ double shd[kBlock / 64];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int e = blk * kBlock + threadIdx.x;
+    float psi = 0.f;
+    bool nf = false, inv = false;
+    if (e < ne) {
+        const int4 c = conn[e];
+        float4 u[4] = {nu4[c.x], nu4[c.y], nu4[c.z], nu4[c.w]};
+        float th[6 * NP + 1];
+        load_theta(theta, ne, e, NP, th);
+        ElemResultT4 r;
+        t4_compute<NP, MON>(m, u, g0[e], g1[e], g2[e], th, r);
+        store_theta(theta, ne, e, NP, th);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[4 * size_t(e) + k] = r.o[k];
+        psi = r.psiV;
+        nf = r.nonfinite;
+        inv = r.inverted;
+    }
+    raise_flags(status, nf, inv);
+    if (MON) {
+        double s = block_sum<kBlock>(double(psi), shd);
+        if (threadIdx.x == 0) part[blk] = s;
+    }
+}
+
+template <int NP, bool MON>
+__global__ __launch_bounds__(kBlock) void h8_element_kernel(
+    const int4 *__restrict__ conn0, const int4 *__restrict__ conn1, const float4 *__restrict__ g0,
+    const float4 *__restrict__ g1, const float4 *__restrict__ g2, const float4 *__restrict__ hg0,
+    const float4 *__restrict__ hg1, const float4 *__restrict__ hg2, const float *__restrict__ khg,
+    const float4 *__restrict__ nu4, float *__restrict__ theta, float4 *__restrict__ out, int ne, KMat m,
+    unsigned *__restrict__ status, double *__restrict__ part) {
+    __shared__ double shd[kBlock / 64];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int e = blk * kBlock + threadIdx.x;
+    float psi = 0.f;
+    bool nf = false, inv = false;
+    if (e < ne) {
+        const int4 ca = conn0[e], cb = conn1[e];
+        float4 u[8] = {nu4[ca.x], nu4[ca.y], nu4[ca.z], nu4[ca.w], nu4[cb.x], nu4[cb.y], nu4[cb.z], nu4[cb.w]};
+        const float4 h0 = hg0[e], h1 = hg1[e], h2 = hg2[e];
+        const float c[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+        float th[6 * NP + 1];
+        load_theta(theta, ne, e, NP, th);
+        ElemResultH8 r;
+        h8_compute<NP, MON>(m, u, g0[e], g1[e], g2[e], c, khg[e], th, r);
+        store_theta(theta, ne, e, NP, th);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) out[8 * size_t(e) + k] = r.o[k];
+        psi = r.psiV;
+        nf = r.nonfinite;
+        inv = r.inverted;
+    }
+    raise_flags(status, nf, inv);
+    if (MON) {
+        double s = block_sum<kBlock>(double(psi), shd);
+        if (threadIdx.x == 0) part[blk] = s;
+    }
+}
+
+template <bool MON, bool CKT>
+__global__ __launch_bounds__(kBlock) void node_kernel(
+    const int *__restrict__ rowptr, const int *__restrict__ inc, const float4 *__restrict__ out,
+    float4 *__restrict__ nu4, float4 *__restrict__ nv4, const float4 *__restrict__ nth,
+    const uint8_t *__restrict__ mask, const float *__restrict__ Vl, int nn, NodeParams p,
+    const long long *__restrict__ step_base, int j, unsigned *__restrict__ status, double *__restrict__ part) {
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int a = blk * kBlock + threadIdx.x;
+    const float src = source_switch(p, step_base, j);
+    NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
+    bool nf = false;
+    if (a < nn) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int k1 = rowptr[a + 1];
+        for (int k = rowptr[a]; k < k1; ++k) {
+            const float4 o = out[inc[k]];
+            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+        }
+        NodeNew r = node_advance<CKT>(p, nu4[a], nv4[a], nth[a], mask[a], acc, src);
+        nu4[a] = r.u;
+        nv4[a] = r.v;
+        nf = r.nonfinite;
+        if (MON) node_monitor(p, r, Vl[a], mo);
+    }
+    raise_flags(status, nf, false);
+    if (MON) write_node_partials<kBlock>(mo, part, shd, shf);
+}
+
+// ---------------------------------------------------------------- fused patch kernels
+
+// One workgroup per patch.  LDS: local node data (npe-independent float4 per
+// local node) and the element-slot outputs (float4 per element slot).
+template <int NPE, int NP, bool MON, bool CKT>
+__global__ __launch_bounds__(kBlock) void patch_kernel(PatchArgs A, KMat m, NodeParams p, int j) {
+    extern __shared__ float4 lds[];
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    const int pid = xcd_block(blockIdx.x, gridDim.x);
+    const int e0 = A.elem_begin[pid], e1 = A.elem_begin[pid + 1];
+    const int ib = A.int_begin[pid], ie = A.int_begin[pid + 1];
+    const int sb = A.shared_begin[pid], se = A.shared_begin[pid + 1];
+    const int nint = ie - ib, nloc = nint + (se - sb);
+    float4 *lnode = lds;                    // nloc
+    float4 *lout = lds + A.max_nodes;       // (e1 - e0) * NPE
+    for (int l = threadIdx.x; l < nloc; l += kBlock)
+        lnode[l] = (l < nint) ? A.nu4[ib + l] : A.nu4[A.shared_ids[sb + l - nint]];
+    __syncthreads();
+    float psi = 0.f;
+    bool nf = false, inv = false;
+    for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        float th[6 * NP + 1];
+        load_theta(A.theta, A.ne, e, NP, th);
+        const int el = e - e0;
+        if (NPE == 4) {
+            const ushort4 c = reinterpret_cast<const ushort4 *>(A.lconn)[e];
+            float4 u[4] = {lnode[c.x], lnode[c.y], lnode[c.z], lnode[c.w]};
+            ElemResultT4 r;
+            t4_compute<NP, MON>(m, u, A.g0[e], A.g1[e], A.g2[e], th, r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lout[4 * el + k] = r.o[k];
+            psi += r.psiV;
+            nf |= r.nonfinite;
+            inv |= r.inverted;
+        } else {
+            const ushort4 ca = reinterpret_cast<const ushort4 *>(A.lconn)[2 * e];
+            const ushort4 cb = reinterpret_cast<const ushort4 *>(A.lconn)[2 * e + 1];
+            float4 u[8] = {lnode[ca.x], lnode[ca.y], lnode[ca.z], lnode[ca.w],
+                           lnode[cb.x], lnode[cb.y], lnode[cb.z], lnode[cb.w]};
+            const float4 h0 = A.hg0[e], h1 = A.hg1[e], h2 = A.hg2[e];
+            const float c[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+            ElemResultH8 r;
+            h8_compute<NP, MON>(m, u, A.g0[e], A.g1[e], A.g2[e], c, A.khg[e], th, r);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) lout[8 * el + k] = r.o[k];
+            psi += r.psiV;
+            nf |= r.nonfinite;
+            inv |= r.inverted;
+        }
+        store_theta(A.theta, A.ne, e, NP, th);
+    }
+    __syncthreads();
+    // assemble local nodes in a fixed order
+    const float src = source_switch(p, A.step_base, j);
+    const uint16_t *lrow = A.lrow + A.lrow_begin[pid];
+    const uint16_t *lslot = A.lslot + size_t(e0) * NPE;
+    NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
+    for (int l = threadIdx.x; l < nloc; l += kBlock) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int k1 = lrow[l + 1];
+        for (int k = lrow[l]; k < k1; ++k) {
+            const float4 o = lout[lslot[k]];
+            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+        }
+        if (l < nint) {
+            const int a = ib + l;
+            NodeNew r = node_advance<CKT>(p, lnode[l], A.nv4[a], A.nth[a], A.mask[a], acc, src);
+            A.nu4[a] = r.u;
+            A.nv4[a] = r.v;
+            nf |= r.nonfinite;
+            if (MON) node_monitor(p, r, A.Vl[a], mo);
+        } else {
+            A.partial[sb + l - nint] = acc;
+        }
+    }
+    raise_flags(A.status, nf, inv);
+    if (MON) {
+        double s = block_sum<kBlock>(double(psi), shd);
+        if (threadIdx.x == 0) A.part_elem[pid] = s;
+        write_node_partials<kBlock>(mo, A.part_node, shd, shf);
+    }
+}
+
+template <bool MON, bool CKT>
+__global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, NodeParams p, int j) {
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * kBlock + threadIdx.x;
+    const float src = source_switch(p, A.step_base, j);
+    NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
+    bool nf = false;
+    if (s < A.n_shared) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int k1 = A.srow[s + 1];
+        for (int k = A.srow[s]; k < k1; ++k) {
+            const float4 o = A.partial[A.sidx[k]];
+            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+        }
+        const int a = A.n_interior + s;
+        NodeNew r = node_advance<CKT>(p, A.nu4[a], A.nv4[a], A.nth[a], A.mask[a], acc, src);
+        A.nu4[a] = r.u;
+        A.nv4[a] = r.v;
+        nf = r.nonfinite;
+        if (MON) node_monitor(p, r, A.Vl[a], mo);
+    }
+    raise_flags(A.status, nf, false);
+    if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), shd, shf);
+}
+
+// ---------------------------------------------------------------- monitors
+
+// One block: sums the per-block partials in a fixed order, writes the monitor
+// record and advances the device step counter by the chunk length.
+__global__ __launch_bounds__(kBlock) void finish_kernel(const double *__restrict__ part_elem, int n_elem_parts,
+                                                        const double *__restrict__ part_node, int n_node_parts,
+                                                        long long *step_base, int k, const unsigned *status,
+                                                        DevMonitors *mon) {
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    double se = 0.0, ke = 0.0, abl = 0.0;
+    float tmax = -INFINITY, tmin = INFINITY;
+    for (int i = threadIdx.x; i < n_elem_parts; i += kBlock) se += part_elem[i];
+    for (int i = threadIdx.x; i < n_node_parts; i += kBlock) {
+        ke += part_node[4 * i];
+        tmax = fmaxf(tmax, float(part_node[4 * i + 1]));
+        tmin = fminf(tmin, float(part_node[4 * i + 2]));
+        abl += part_node[4 * i + 3];
+    }
+    se = block_sum<kBlock>(se, shd);
+    ke = block_sum<kBlock>(ke, shd);
+    abl = block_sum<kBlock>(abl, shd);
+    tmax = block_max<kBlock>(tmax, shf);
+    tmin = -block_max<kBlock>(-tmin, shf);
+    if (threadIdx.x == 0) {
+        const long long n = *step_base + k;
+        *step_base = n;
+        mon->step = n;
+        mon->strain = se;
+        mon->kinetic = ke;
+        mon->T_max = tmax;
+        mon->T_min = tmin;
+        mon->ablated = abl;
+        mon->flags = *status;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+namespace {
+template <int NP>
+void launch_t4_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+    dim3 grid((a.ne + kBlock - 1) / kBlock);
+    if (mon)
+        hipLaunchKernelGGL((t4_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
+                           a.theta, a.out, a.ne, m, a.status, a.part_elem);
+    else
+        hipLaunchKernelGGL((t4_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
+                           a.theta, a.out, a.ne, m, a.status, a.part_elem);
+}
+template <int NP>
+void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+    dim3 grid((a.ne + kBlock - 1) / kBlock);
+    if (mon)
+        hipLaunchKernelGGL((h8_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
+                           a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
+    else
+        hipLaunchKernelGGL((h8_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
+                           a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
+}
+
+template <int NPE, int NP>
+void launch_patch_np(bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
+                     size_t lds, hipStream_t s) {
+    dim3 grid(a.n_patches);
+    if (mon) {
+        if (ckt) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, true>), grid, dim3(kBlock), lds, s, a, m, p, j);
+        else hipLaunchKernelGGL((patch_kernel<NPE, NP, true, false>), grid, dim3(kBlock), lds, s, a, m, p, j);
+    } else {
+        if (ckt) hipLaunchKernelGGL((patch_kernel<NPE, NP, false, true>), grid, dim3(kBlock), lds, s, a, m, p, j);
+        else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, false>), grid, dim3(kBlock), lds, s, a, m, p, j);
+    }
+}
+}  // namespace
+
+void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+    if (a.ne == 0) return;
+    if (npe == 4) {
+        switch (np) {
+            case 0: launch_t4_element<0>(mon, a, m, s); break;
+            case 1: launch_t4_element<1>(mon, a, m, s); break;
+            case 2: launch_t4_element<2>(mon, a, m, s); break;
+            case 3: launch_t4_element<3>(mon, a, m, s); break;
+            default: launch_t4_element<4>(mon, a, m, s); break;
+        }
+    } else {
+        switch (np) {
+            case 0: launch_h8_element<0>(mon, a, m, s); break;
+            case 1: launch_h8_element<1>(mon, a, m, s); break;
+            case 2: launch_h8_element<2>(mon, a, m, s); break;
+            case 3: launch_h8_element<3>(mon, a, m, s); break;
+            default: launch_h8_element<4>(mon, a, m, s); break;
+        }
+    }
+}
+
+void launch_node(bool mon, bool ckt, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s) {
+    dim3 grid((a.nn + kBlock - 1) / kBlock);
+    if (mon) {
+        if (ckt) hipLaunchKernelGGL((node_kernel<true, true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
+                                    a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+        else hipLaunchKernelGGL((node_kernel<true, false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
+                                a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+    } else {
+        if (ckt) hipLaunchKernelGGL((node_kernel<false, true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
+                                    a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+        else hipLaunchKernelGGL((node_kernel<false, false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
+                                a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+    }
+}
+
+void launch_patch(int npe, int np, bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
+                  hipStream_t s) {
+    const size_t lds = sizeof(float4) * (size_t(a.max_nodes) + size_t(a.max_elems) * npe);
+    if (npe == 4) {
+        switch (np) {
+            case 0: launch_patch_np<4, 0>(mon, ckt, a, m, p, j, lds, s); break;
+            case 1: launch_patch_np<4, 1>(mon, ckt, a, m, p, j, lds, s); break;
+            case 2: launch_patch_np<4, 2>(mon, ckt, a, m, p, j, lds, s); break;
+            case 3: launch_patch_np<4, 3>(mon, ckt, a, m, p, j, lds, s); break;
+            default: launch_patch_np<4, 4>(mon, ckt, a, m, p, j, lds, s); break;
+        }
+    } else {
+        switch (np) {
+            case 0: launch_patch_np<8, 0>(mon, ckt, a, m, p, j, lds, s); break;
+            case 1: launch_patch_np<8, 1>(mon, ckt, a, m, p, j, lds, s); break;
+            case 2: launch_patch_np<8, 2>(mon, ckt, a, m, p, j, lds, s); break;
+            case 3: launch_patch_np<8, 3>(mon, ckt, a, m, p, j, lds, s); break;
+            default: launch_patch_np<8, 4>(mon, ckt, a, m, p, j, lds, s); break;
+        }
+    }
+}
+
+void launch_shared_nodes(bool mon, bool ckt, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s) {
+    const int nb = int((a.n_shared + kBlock - 1) / kBlock);
+    if (nb == 0) return;
+    dim3 grid(nb);
+    if (mon) {
+        if (ckt) hipLaunchKernelGGL((shared_node_kernel<true, true>), grid, dim3(kBlock), 0, s, a, p, j);
+        else hipLaunchKernelGGL((shared_node_kernel<true, false>), grid, dim3(kBlock), 0, s, a, p, j);
+    } else {
+        if (ckt) hipLaunchKernelGGL((shared_node_kernel<false, true>), grid, dim3(kBlock), 0, s, a, p, j);
+        else hipLaunchKernelGGL((shared_node_kernel<false, false>), grid, dim3(kBlock), 0, s, a, p, j);
+    }
+}
+
+void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,
+                   long long *step_base, int k, const unsigned *status, DevMonitors *mon, hipStream_t s) {
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(kBlock), 0, s, part_elem, n_elem_parts, part_node, n_node_parts,
+                       step_base, k, status, mon);
+}
+
+size_t patch_lds_bytes(int npe, const PatchArgs &a) {
+    return sizeof(float4) * (size_t(a.max_nodes) + size_t(a.max_elems) * npe);
+}
+
+}  // namespace tled
+
+// ---------------------------------------------------------------- field export
+
+namespace tled {
+
+__global__ __launch_bounds__(kBlock) void export_fields_kernel(const float4 *__restrict__ nu4,
+                                                               const int *__restrict__ new2old, int nn, float T0,
+                                                               float *__restrict__ u_dst, float *__restrict__ T_dst) {
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nn) return;
+    const float4 u = nu4[a];
+    const int o = new2old[a];
+    if (u_dst) {
+        u_dst[3 * size_t(o)] = u.x;
+        u_dst[3 * size_t(o) + 1] = u.y;
+        u_dst[3 * size_t(o) + 2] = u.z;
+    }
+    if (T_dst) T_dst[o] = T0 + u.w;
+}
+
+void launch_export_fields(const float4 *nu4, const int *new2old, int nn, float T0, float *u_dst, float *T_dst,
+                          hipStream_t s) {
+    if (nn == 0) return;
+    hipLaunchKernelGGL(export_fields_kernel, dim3((nn + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nu4, new2old, nn,
+                       T0, u_dst, T_dst);
+}
+
+}  // namespace tled

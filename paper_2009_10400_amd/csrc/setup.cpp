@@ -1,0 +1,494 @@
+// Host-side set-up of the TLED solver, in double precision: validation,
+// orientation repair, element geometry, lumped matrices, critical time step,
+// locality reordering and the assembly lists of both kernel variants.
+//
+// The geometry is the total-Lagrangian precompute of Section 5 (spatial
+// derivatives, initial volumes, initial Jacobian, mass): it is done once,
+// here, and rounded to single precision once when uploaded.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "tled_internal.h"
+
+namespace tled {
+namespace {
+
+// H8 natural-coordinate signs of the local nodes (---),(+--),(++-),(-+-),(--+),(+-+),(+++),(-++).
+const int kHexSign[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                            {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+
+// Hourglass base vectors eta*zeta, zeta*xi, xi*eta, xi*eta*zeta at the nodes.
+inline int hourglass_base(int alpha, int a) {
+    const int *s = kHexSign[a];
+    switch (alpha) {
+        case 0: return s[1] * s[2];
+        case 1: return s[2] * s[0];
+        case 2: return s[0] * s[1];
+        default: return s[0] * s[1] * s[2];
+    }
+}
+
+inline double det3(const double m[9]) {
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// Inverse through the cofactor matrix; returns the determinant.
+inline double invert3(const double m[9], double r[9]) {
+    double c[9] = {m[4] * m[8] - m[5] * m[7], m[5] * m[6] - m[3] * m[8], m[3] * m[7] - m[4] * m[6],
+                   m[2] * m[7] - m[1] * m[8], m[0] * m[8] - m[2] * m[6], m[1] * m[6] - m[0] * m[7],
+                   m[1] * m[5] - m[2] * m[4], m[2] * m[3] - m[0] * m[5], m[0] * m[4] - m[1] * m[3]};
+    double d = m[0] * c[0] + m[1] * c[1] + m[2] * c[2];
+    // r = adj(m) / d, adj = cofactor^T
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) r[3 * i + j] = c[3 * j + i] / d;
+    return d;
+}
+
+inline double norm_cross(const double *u, const double *v) {
+    double w0 = u[1] * v[2] - u[2] * v[1], w1 = u[2] * v[0] - u[0] * v[2], w2 = u[0] * v[1] - u[1] * v[0];
+    return std::sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+}
+
+struct ElemGeo {
+    double geo[9];   // T4: rows dh/dX of local nodes 1..3 ; H8: G = J0^-T
+    double V0;
+    double hgc[12];  // H8 only
+    double sum_dh2;  // sum_a |dh_a/dX|^2
+    double L;        // characteristic length
+};
+
+// T4 geometry from the edge matrix D (columns X_k - X_0, k = 1..3):
+// dh_k/dX = row k-1 of D^-1, V0 = det D / 6.
+double tet_geometry(const double *Xe, ElemGeo *g) {
+    double D[9];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) D[3 * i + k] = Xe[3 * (k + 1) + i] - Xe[i];
+    double d = det3(D);
+    if (!(d > 0.0)) return d;
+    double Di[9];
+    invert3(D, Di);
+    std::memcpy(g->geo, Di, sizeof(Di));
+    g->V0 = d / 6.0;
+    double s = 0.0, r0[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) {
+            s += Di[3 * k + j] * Di[3 * k + j];
+            r0[j] -= Di[3 * k + j];
+        }
+    g->sum_dh2 = s + r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+    // length = 3 V0 / largest face area
+    static const int face[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    double amax = 0.0;
+    for (auto &f : face) {
+        const double *p = Xe + 3 * f[0], *q = Xe + 3 * f[1], *r = Xe + 3 * f[2];
+        double u[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+        double v[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+        amax = std::max(amax, 0.5 * norm_cross(u, v));
+    }
+    g->L = 3.0 * g->V0 / amax;
+    return d;
+}
+
+// H8 one-point geometry: J0 = sum_a X_a (x) s_a / 8 (derivatives of the
+// trilinear shape functions at the centre), G = J0^-T so dh_a/dX = G s_a / 8,
+// V0 = 8 det J0; hourglass c_alpha = sum_a X_a h_alpha,a.
+double hex_geometry(const double *Xe, ElemGeo *g) {
+    double J0[9] = {0};
+    double Xr[24];
+    for (int a = 0; a < 8; ++a)
+        for (int i = 0; i < 3; ++i) Xr[3 * a + i] = Xe[3 * a + i] - Xe[i];  // translation-free
+    for (int a = 0; a < 8; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) J0[3 * i + j] += Xr[3 * a + i] * kHexSign[a][j] / 8.0;
+    double d = det3(J0);
+    if (!(d > 0.0)) return d;
+    double Ji[9];
+    invert3(J0, Ji);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) g->geo[3 * i + j] = Ji[3 * j + i];  // G = J0^-T
+    g->V0 = 8.0 * d;
+    double s = 0.0;
+    for (int a = 0; a < 8; ++a)
+        for (int j = 0; j < 3; ++j) {
+            double dh = (g->geo[3 * j] * kHexSign[a][0] + g->geo[3 * j + 1] * kHexSign[a][1] +
+                         g->geo[3 * j + 2] * kHexSign[a][2]) / 8.0;
+            s += dh * dh;
+        }
+    g->sum_dh2 = s;
+    for (int al = 0; al < 4; ++al)
+        for (int i = 0; i < 3; ++i) {
+            double c = 0.0;
+            for (int a = 0; a < 8; ++a) c += Xr[3 * a + i] * hourglass_base(al, a);
+            g->hgc[3 * al + i] = c;
+        }
+    static const int face[6][4] = {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 3, 7, 4},
+                                   {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 6, 7}};
+    double amax = 0.0;
+    for (auto &f : face) {
+        const double *p0 = Xe + 3 * f[0], *p1 = Xe + 3 * f[1], *p2 = Xe + 3 * f[2], *p3 = Xe + 3 * f[3];
+        double d1[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        double d2[3] = {p3[0] - p1[0], p3[1] - p1[1], p3[2] - p1[2]};
+        amax = std::max(amax, 0.5 * norm_cross(d1, d2));
+    }
+    g->L = g->V0 / amax;
+    return d;
+}
+
+double wave_speed(const tled_material &m) {
+    return std::sqrt((m.kappa + 4.0 * m.mu / 3.0 + 4.0 * m.eta) / m.rho);
+}
+
+tled_status check_inputs(const HostProblem &p, std::string *err) {
+    if (!p.have_mesh) { *err = "mesh not set"; return TLED_E_STATE; }
+    if (!p.have_mat) { *err = "material not set"; return TLED_E_STATE; }
+    const tled_material &m = p.mat;
+    if (!(m.rho > 0) || !(m.mu > 0) || !(m.kappa > 0) || m.eta < 0 || !(m.c > 0) || m.k < 0 ||
+        m.wbcb < 0 || m.n_prony < 0 || m.n_prony > 4) {
+        *err = "material out of range (rho, mu, kappa, c > 0; eta, k, wbcb >= 0; 0 <= n_prony <= 4)";
+        return TLED_E_ARG;
+    }
+    double gs = 0.0;
+    for (int i = 0; i < m.n_prony; ++i) {
+        if (!(m.tau[i] > 0) || m.g[i] < 0) { *err = "Prony terms need tau > 0, g >= 0"; return TLED_E_ARG; }
+        gs += m.g[i];
+    }
+    if (gs >= 1.0) { *err = "Prony moduli must sum below 1"; return TLED_E_ARG; }
+    if (m.muT_on && !(m.muT_hi > m.muT_lo)) { *err = "muT_hi must exceed muT_lo"; return TLED_E_ARG; }
+    if (m.shrink_on && !(m.shrink_width > 0)) { *err = "shrink_width must be > 0"; return TLED_E_ARG; }
+    if (m.ckT_on && !(m.ckT_hi > m.ckT_lo)) { *err = "ckT_hi must exceed ckT_lo"; return TLED_E_ARG; }
+    if (m.ckT_on && (!(m.c_hi > 0) || m.k_hi < 0)) { *err = "c_hi > 0 and k_hi >= 0 required"; return TLED_E_ARG; }
+    if (m.expan_mode < 0 || m.expan_mode > 1 || m.cond_mode < 0 || m.cond_mode > 1) {
+        *err = "expan_mode and cond_mode must be 0 or 1"; return TLED_E_ARG;
+    }
+    return TLED_OK;
+}
+
+// Elements in caller order with repaired orientation; geometry per element.
+tled_status element_pass(const HostProblem &p, std::vector<int32_t> *conn, std::vector<ElemGeo> *geo,
+                         int64_t *n_swapped, std::string *err) {
+    const int npe = p.npe;
+    *conn = p.conn;
+    geo->resize(p.ne);
+    *n_swapped = 0;
+    for (int64_t e = 0; e < p.ne; ++e) {
+        int32_t *c = conn->data() + npe * e;
+        double Xe[24];
+        for (int a = 0; a < npe; ++a) {
+            if (c[a] < 0 || c[a] >= p.nn) {
+                *err = "connectivity of element " + std::to_string(e) + " out of range";
+                return TLED_E_MESH;
+            }
+            std::memcpy(Xe + 3 * a, p.X.data() + 3 * int64_t(c[a]), 3 * sizeof(double));
+        }
+        double d;
+        if (npe == 4) {
+            d = tet_geometry(Xe, &(*geo)[e]);
+            if (d < 0.0) {
+                std::swap(c[2], c[3]);
+                for (int i = 0; i < 3; ++i) std::swap(Xe[6 + i], Xe[9 + i]);
+                d = tet_geometry(Xe, &(*geo)[e]);
+                ++*n_swapped;
+            }
+            if (!(d > 0.0)) {
+                *err = "T4 element " + std::to_string(e) + " has zero volume";
+                return TLED_E_MESH;
+            }
+        } else {
+            d = hex_geometry(Xe, &(*geo)[e]);
+            if (!(d > 0.0)) {
+                *err = "H8 element " + std::to_string(e) + " has det J0 <= 0 (inverted or degenerate)";
+                return TLED_E_MESH;
+            }
+        }
+    }
+    return TLED_OK;
+}
+
+uint64_t spread3(uint64_t x) {
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+// Element order along a Morton (Z-order) curve of the centroids.
+std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_t> &conn) {
+    const int npe = p.npe;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t a = 0; a < p.nn; ++a)
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = std::min(lo[i], p.X[3 * a + i]);
+            hi[i] = std::max(hi[i], p.X[3 * a + i]);
+        }
+    double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint64_t, int64_t>> key(p.ne);
+    for (int64_t e = 0; e < p.ne; ++e) {
+        double c[3] = {0, 0, 0};
+        for (int a = 0; a < npe; ++a)
+            for (int i = 0; i < 3; ++i) c[i] += p.X[3 * int64_t(conn[npe * e + a]) + i];
+        uint64_t k = 0;
+        for (int i = 0; i < 3; ++i) {
+            double t = (c[i] / npe - lo[i]) / span;
+            uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+            k |= spread3(q) << i;
+        }
+        key[e] = {k, e};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int64_t> order(p.ne);
+    for (int64_t e = 0; e < p.ne; ++e) order[e] = key[e].second;
+    return order;
+}
+
+void build_patches(Precomputed *pc, int patch_elems) {
+    const int npe = pc->npe;
+    const int64_t ne = pc->ne, nn = pc->nn;
+    Patches &P = pc->patches;
+    P.n = int32_t((ne + patch_elems - 1) / patch_elems);
+    P.elem_begin.resize(P.n + 1);
+    for (int32_t p = 0; p <= P.n; ++p) P.elem_begin[p] = int32_t(std::min<int64_t>(ne, int64_t(p) * patch_elems));
+    // patch membership of nodes: interior iff touched by exactly one patch
+    std::vector<int32_t> owner(nn, -1);
+    std::vector<uint8_t> shared(nn, 0);
+    for (int32_t p = 0; p < P.n; ++p)
+        for (int64_t e = P.elem_begin[p]; e < P.elem_begin[p + 1]; ++e)
+            for (int a = 0; a < npe; ++a) {
+                int32_t n = pc->conn[npe * e + a];
+                if (owner[n] == -1) owner[n] = p;
+                else if (owner[n] != p) shared[n] = 1;
+            }
+    // new node order: interior nodes patch by patch (first-touch inside the
+    // patch), then shared nodes in first-touch order
+    std::vector<int64_t> old2new(nn, -1), new2old;
+    new2old.reserve(nn);
+    P.int_begin.assign(P.n + 1, 0);
+    for (int32_t p = 0; p < P.n; ++p) {
+        P.int_begin[p] = int32_t(new2old.size());
+        for (int64_t e = P.elem_begin[p]; e < P.elem_begin[p + 1]; ++e)
+            for (int a = 0; a < npe; ++a) {
+                int32_t n = pc->conn[npe * e + a];
+                if (!shared[n] && old2new[n] < 0) {
+                    old2new[n] = int64_t(new2old.size());
+                    new2old.push_back(n);
+                }
+            }
+    }
+    P.int_begin[P.n] = int32_t(new2old.size());
+    P.n_interior = int64_t(new2old.size());
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < npe; ++a) {
+            int32_t n = pc->conn[npe * e + a];
+            if (shared[n] && old2new[n] < 0) {
+                old2new[n] = int64_t(new2old.size());
+                new2old.push_back(n);
+            }
+        }
+    // renumber everything node-indexed
+    auto permute_d = [&](std::vector<double> &v, int w) {
+        std::vector<double> t(v.size());
+        for (int64_t i = 0; i < nn; ++i)
+            for (int k = 0; k < w; ++k) t[w * i + k] = v[w * new2old[i] + k];
+        v.swap(t);
+    };
+    permute_d(pc->Vl, 1); permute_d(pc->M, 1); permute_d(pc->C, 1); permute_d(pc->Kb, 1);
+    permute_d(pc->Qm, 1); permute_d(pc->Qr, 1); permute_d(pc->Tfix, 1);
+    {
+        std::vector<uint8_t> t(nn);
+        for (int64_t i = 0; i < nn; ++i) t[i] = pc->fix[new2old[i]];
+        pc->fix.swap(t);
+        std::vector<int64_t> n2o(nn);
+        for (int64_t i = 0; i < nn; ++i) n2o[i] = pc->node_new2old[new2old[i]];
+        pc->node_new2old.swap(n2o);
+        for (int64_t i = 0; i < nn; ++i) pc->node_old2new[pc->node_new2old[i]] = i;
+    }
+    for (auto &c : pc->conn) c = int32_t(old2new[c]);
+
+    // per-patch local numbering, gather lists and shared partial slots
+    P.shared_begin.assign(P.n + 1, 0);
+    P.shared_ids.clear();
+    P.lconn.resize(size_t(ne) * npe);
+    P.lrow_begin.assign(P.n + 1, 0);
+    P.lrow.clear();
+    P.lslot.resize(size_t(ne) * npe);
+    P.lslot_begin.assign(P.n + 1, 0);
+    P.max_nodes = 0;
+    P.max_elems = 0;
+    std::vector<int32_t> local(nn, -1);
+    std::vector<std::vector<int32_t>> shared_parts(nn - P.n_interior);
+    for (int32_t p = 0; p < P.n; ++p) {
+        const int32_t e0 = P.elem_begin[p], e1 = P.elem_begin[p + 1];
+        const int32_t ib = P.int_begin[p], ie = P.int_begin[p + 1];
+        const int32_t nint = ie - ib;
+        P.shared_begin[p] = int32_t(P.shared_ids.size());
+        std::vector<int32_t> touched;
+        for (int32_t n = ib; n < ie; ++n) local[n] = n - ib;
+        int32_t nloc = nint;
+        for (int32_t e = e0; e < e1; ++e)
+            for (int a = 0; a < npe; ++a) {
+                int32_t n = pc->conn[npe * e + a];
+                if (n >= P.n_interior && local[n] < 0) {
+                    local[n] = nloc++;
+                    touched.push_back(n);
+                    shared_parts[n - P.n_interior].push_back(int32_t(P.shared_ids.size()));
+                    P.shared_ids.push_back(n);
+                }
+                P.lconn[size_t(npe) * e + a] = uint16_t(local[n]);
+            }
+        P.max_nodes = std::max(P.max_nodes, nloc);
+        P.max_elems = std::max(P.max_elems, e1 - e0);
+        // local gather lists
+        std::vector<int32_t> cnt(nloc + 1, 0);
+        for (int32_t e = e0; e < e1; ++e)
+            for (int a = 0; a < npe; ++a) cnt[P.lconn[size_t(npe) * e + a] + 1]++;
+        for (int32_t l = 0; l < nloc; ++l) cnt[l + 1] += cnt[l];
+        P.lrow_begin[p] = int32_t(P.lrow.size());
+        for (int32_t l = 0; l <= nloc; ++l) P.lrow.push_back(uint16_t(cnt[l]));
+        P.lslot_begin[p] = e0 * npe;
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int32_t e = e0; e < e1; ++e)
+            for (int a = 0; a < npe; ++a) {
+                int32_t l = P.lconn[size_t(npe) * e + a];
+                P.lslot[size_t(e0) * npe + fill[l]++] = uint16_t((e - e0) * npe + a);
+            }
+        for (int32_t n = ib; n < ie; ++n) local[n] = -1;
+        for (int32_t n : touched) local[n] = -1;
+    }
+    P.shared_begin[P.n] = int32_t(P.shared_ids.size());
+    P.lrow_begin[P.n] = int32_t(P.lrow.size());
+    P.lslot_begin[P.n] = int32_t(ne * npe);
+    const int64_t nsh = nn - P.n_interior;
+    P.srow.assign(nsh + 1, 0);
+    P.sidx.clear();
+    for (int64_t s = 0; s < nsh; ++s) {
+        P.srow[s] = int32_t(P.sidx.size());
+        for (int32_t k : shared_parts[s]) P.sidx.push_back(k);
+    }
+    P.srow[nsh] = int32_t(P.sidx.size());
+}
+
+}  // namespace
+
+tled_status critical_dt(const HostProblem &p, double *dt_cr, std::string *err) {
+    tled_status st = check_inputs(p, err);
+    if (st != TLED_OK) return st;
+    std::vector<int32_t> conn;
+    std::vector<ElemGeo> geo;
+    int64_t ns;
+    st = element_pass(p, &conn, &geo, &ns, err);
+    if (st != TLED_OK) return st;
+    double cd = wave_speed(p.mat), dtc = std::numeric_limits<double>::infinity();
+    for (auto &g : geo) dtc = std::min(dtc, g.L / cd);
+    *dt_cr = dtc;
+    return TLED_OK;
+}
+
+tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precomputed *out, std::string *err) {
+    tled_status st = check_inputs(p, err);
+    if (st != TLED_OK) return st;
+    if (p.ne <= 0 || p.nn <= 0) { *err = "empty mesh"; return TLED_E_ARG; }
+    const int npe = p.npe;
+    std::vector<int32_t> conn;
+    std::vector<ElemGeo> geo;
+    Precomputed &pc = *out;
+    pc = Precomputed();
+    pc.npe = npe; pc.nn = p.nn; pc.ne = p.ne;
+    st = element_pass(p, &conn, &geo, &pc.n_swapped, err);
+    if (st != TLED_OK) return st;
+
+    double cd = wave_speed(p.mat);
+    pc.dt_cr = std::numeric_limits<double>::infinity();
+    for (auto &g : geo) pc.dt_cr = std::min(pc.dt_cr, g.L / cd);
+
+    // element order
+    std::vector<int64_t> eorder(p.ne);
+    if (opt.reorder) eorder = morton_order(p, conn);
+    else std::iota(eorder.begin(), eorder.end(), 0);
+    pc.elem_new2old = eorder;
+    // node order: first touch along the element order (or identity)
+    pc.node_old2new.assign(p.nn, -1);
+    pc.node_new2old.clear();
+    pc.node_new2old.reserve(p.nn);
+    if (opt.reorder) {
+        for (int64_t ei = 0; ei < p.ne; ++ei)
+            for (int a = 0; a < npe; ++a) {
+                int32_t n = conn[npe * eorder[ei] + a];
+                if (pc.node_old2new[n] < 0) {
+                    pc.node_old2new[n] = int64_t(pc.node_new2old.size());
+                    pc.node_new2old.push_back(n);
+                }
+            }
+        if (int64_t(pc.node_new2old.size()) != p.nn) {
+            *err = "mesh has nodes that belong to no element";
+            return TLED_E_MESH;
+        }
+    } else {
+        for (int64_t a = 0; a < p.nn; ++a) { pc.node_old2new[a] = a; pc.node_new2old.push_back(a); }
+    }
+    const int64_t nn = p.nn, ne = p.ne;
+
+    pc.conn.resize(size_t(ne) * npe);
+    pc.geo.resize(size_t(ne) * 9);
+    pc.V0.resize(ne);
+    pc.a0.resize(size_t(ne) * 3);
+    if (npe == 8) { pc.hgc.resize(size_t(ne) * 12); pc.khg.resize(ne); }
+    std::vector<double> q(ne, 0.0);
+    for (int64_t ei = 0; ei < ne; ++ei) {
+        int64_t e = eorder[ei];
+        for (int a = 0; a < npe; ++a) pc.conn[npe * ei + a] = int32_t(pc.node_old2new[conn[npe * e + a]]);
+        const ElemGeo &g = geo[e];
+        std::memcpy(&pc.geo[9 * ei], g.geo, 9 * sizeof(double));
+        pc.V0[ei] = g.V0;
+        double a0[3] = {1.0, 0.0, 0.0};
+        if (!p.a0.empty()) { a0[0] = p.a0[3 * e]; a0[1] = p.a0[3 * e + 1]; a0[2] = p.a0[3 * e + 2]; }
+        double an = std::sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
+        if (!(an > 0.0)) { *err = "zero fibre vector at element " + std::to_string(e); return TLED_E_ARG; }
+        for (int i = 0; i < 3; ++i) pc.a0[3 * ei + i] = a0[i] / an;
+        if (npe == 8) {
+            std::memcpy(&pc.hgc[12 * ei], g.hgc, 12 * sizeof(double));
+            pc.khg[ei] = p.mat.hg_coef * (p.mat.kappa + 4.0 * p.mat.mu / 3.0) * g.V0 * g.sum_dh2 / 8.0;
+        }
+        if (!p.q.empty()) q[ei] = p.q[e];
+    }
+
+    // lumped quantities with reference volumes
+    pc.Vl.assign(nn, 0.0);
+    pc.Qr.assign(nn, 0.0);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < npe; ++a) {
+            int32_t n = pc.conn[npe * e + a];
+            pc.Vl[n] += pc.V0[e] / npe;
+            pc.Qr[n] += q[e] * pc.V0[e] / npe;
+        }
+    pc.M.resize(nn); pc.C.resize(nn); pc.Kb.resize(nn); pc.Qm.resize(nn);
+    pc.fix.assign(nn, 0);
+    pc.Tfix.assign(nn, p.mat.T0);
+    for (int64_t a = 0; a < nn; ++a) {
+        pc.M[a] = p.mat.rho * pc.Vl[a];
+        pc.C[a] = p.mat.rho * p.mat.c * pc.Vl[a];
+        pc.Kb[a] = p.mat.wbcb * pc.Vl[a];
+        pc.Qm[a] = p.mat.Q_met * pc.Vl[a];
+        int64_t o = pc.node_new2old[a];
+        if (!p.fix.empty()) pc.fix[a] = p.fix[o];
+        if (!p.Tfix.empty()) pc.Tfix[a] = p.Tfix[o];
+    }
+
+    if (opt.build_patches) build_patches(&pc, std::max(8, std::min(opt.patch_elems, 65536 / npe)));
+
+    // node -> element-slot incidence (ascending slot order)
+    pc.rowptr.assign(nn + 1, 0);
+    for (int64_t s = 0; s < ne * npe; ++s) pc.rowptr[pc.conn[s] + 1]++;
+    for (int64_t a = 0; a < nn; ++a) pc.rowptr[a + 1] += pc.rowptr[a];
+    pc.inc.resize(size_t(ne) * npe);
+    std::vector<int32_t> fill(pc.rowptr.begin(), pc.rowptr.end() - 1);
+    for (int64_t s = 0; s < ne * npe; ++s) pc.inc[fill[pc.conn[s]]++] = int32_t(s);
+    return TLED_OK;
+}
+
+}  // namespace tled

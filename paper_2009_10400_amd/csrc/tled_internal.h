@@ -1,0 +1,93 @@
+// Internal host-side structures of the TLED library (no HIP types here, so
+// the set-up code also builds with a plain C++ compiler).
+#pragma once
+
+#include <cstdint>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/tled.h"
+
+namespace tled {
+
+// Problem as given by the caller (caller numbering, FP64).
+struct HostProblem {
+    int npe = 0;
+    int64_t nn = 0, ne = 0;
+    std::vector<double> X;          // nn * 3
+    std::vector<int32_t> conn;      // ne * npe
+    std::vector<double> a0;         // ne * 3, empty = (1,0,0)
+    std::vector<double> q;          // ne, empty = 0
+    std::vector<uint8_t> fix;       // nn, bit0..2 fixed u, bit3 fixed T
+    std::vector<double> Tfix;       // nn
+    double t_on = 0.0, t_off = std::numeric_limits<double>::infinity();
+    double dt = 0.0, gamma = 0.0;
+    tled_material mat{};
+    bool have_mesh = false, have_mat = false, have_time = false;
+};
+
+// Patch partition of the fused variant.  Elements of patch p are the
+// contiguous range [elem_begin[p], elem_begin[p+1]) of the internal element
+// order; its nodes are the interior range [int_begin[p], int_begin[p+1]) of
+// the internal node order (nodes touched by this patch only) followed by the
+// shared nodes listed in shared_ids[shared_begin[p] .. shared_begin[p+1]).
+struct Patches {
+    int32_t n = 0;
+    int32_t max_nodes = 0;                 // max local nodes over patches
+    int32_t max_elems = 0;
+    std::vector<int32_t> elem_begin;       // n + 1
+    std::vector<int32_t> int_begin;        // n + 1 (interior node ranges)
+    std::vector<int32_t> shared_begin;     // n + 1 (into shared_ids)
+    std::vector<int32_t> shared_ids;       // internal node ids of shared nodes per patch
+    std::vector<uint16_t> lconn;           // ne * npe local node indices
+    // local gather lists: for local node l of patch p, its incident element
+    // slots (e_local * npe + s) are lslot[lrow[off+l] .. lrow[off+l+1]).
+    std::vector<int32_t> lrow_begin;       // n + 1 offsets into lrow (each patch has nloc+1 entries)
+    std::vector<uint16_t> lrow;            // row pointers, local to the patch slot list
+    std::vector<uint16_t> lslot;           // ne * npe entries, sorted per local node
+    std::vector<int32_t> lslot_begin;      // n + 1 offsets into lslot (= elem_begin * npe)
+    // shared-node assembly: partial of (patch p, local shared index j) lives at
+    // partial slot shared_begin[p] + j; node n_int + s sums the partial slots
+    // srow[s] .. srow[s+1] listed in sidx.
+    int64_t n_interior = 0;                // nodes [0, n_interior) are interior
+    std::vector<int32_t> srow;             // n_shared + 1
+    std::vector<int32_t> sidx;             // shared_ids.size()
+};
+
+// Precomputed quantities in the internal (reordered) numbering, FP64.
+struct Precomputed {
+    int npe = 0;
+    int64_t nn = 0, ne = 0;
+    std::vector<int64_t> node_new2old, node_old2new, elem_new2old;
+    std::vector<int32_t> conn;      // ne * npe internal node ids, orientation repaired
+    std::vector<double> geo;        // ne * 9: T4 dh/dX rows of nodes 1..3; H8 G = J0^-T
+    std::vector<double> V0;         // ne
+    std::vector<double> hgc;        // ne * 12: H8 c_alpha = X^T h_alpha (alpha = 0..3)
+    std::vector<double> khg;        // ne: H8 hourglass stiffness
+    std::vector<double> a0;         // ne * 3 unit fibres
+    std::vector<double> Vl, M, C, Kb, Qm, Qr;  // nn lumped quantities (C at T0)
+    std::vector<uint8_t> fix;       // nn
+    std::vector<double> Tfix;       // nn
+    std::vector<int32_t> rowptr;    // nn + 1 node -> element-slot incidence (two-pass)
+    std::vector<int32_t> inc;       // ne * npe values e * npe + s, ascending per node
+    int64_t n_swapped = 0;
+    double dt_cr = 0.0;
+    Patches patches;
+};
+
+struct SetupOptions {
+    bool reorder = true;
+    bool build_patches = false;
+    int patch_elems = 512;
+};
+
+// Element geometry and critical step only (no reordering), for tled_critical_dt.
+// Returns TLED_OK or TLED_E_MESH with a message.
+tled_status critical_dt(const HostProblem &p, double *dt_cr, std::string *err);
+
+// Full precompute.  Returns TLED_OK, TLED_E_MESH or TLED_E_ARG with a message.
+tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precomputed *out,
+                       std::string *err);
+
+}  // namespace tled

@@ -1,0 +1,338 @@
+"""Thin ctypes binding of ``libtled.so`` (C-ABI in ``include/tled.h``).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch is used for device memory (optional caching-allocator
+callback) and streams.  There is no fallback: if the library is missing this
+module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "csrc", "libtled.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_10400_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_ARG, E_MESH, E_STATE, E_HIP, E_OOM, E_UNSTABLE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+T4, H8 = 4, 8
+FLAG_NONFINITE, FLAG_INVERTED = 1, 2
+
+_d = ctypes.c_double
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class Material(ctypes.Structure):
+    _fields_ = [
+        ("rho", _d), ("mu", _d), ("kappa", _d), ("eta", _d), ("alpha", _d), ("alpha_m", _d),
+        ("T0", _d), ("k", _d), ("k_m", _d), ("c", _d), ("wbcb", _d), ("T_art", _d), ("Q_met", _d),
+        ("g", _d * 4), ("tau", _d * 4),
+        ("muT_lo", _d), ("muT_hi", _d), ("muT_drop", _d),
+        ("shrink_T", _d), ("shrink_width", _d), ("shrink_eps", _d),
+        ("ckT_lo", _d), ("ckT_hi", _d), ("c_hi", _d), ("k_hi", _d), ("hg_coef", _d),
+        ("n_prony", _i32), ("expan_mode", _i32), ("cond_mode", _i32), ("muT_on", _i32),
+        ("shrink_on", _i32), ("ckT_on", _i32),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("graph_steps", _i32), ("kernel_variant", _i32), ("reorder", _i32),
+                ("block_size", _i32), ("patch_elems", _i32), ("ablation_T", _d)]
+
+
+class Monitors(ctypes.Structure):
+    _fields_ = [("step", _i64), ("t", _d), ("kinetic", _d), ("strain", _d), ("T_max", _d),
+                ("T_min", _d), ("ablated_volume", _d), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_nodes", _i64), ("n_elems", _i64), ("elem_type", _i32), ("n_prony", _i32),
+                ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
+                ("n_shared_nodes", _i64), ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_dp = ctypes.POINTER(_d)
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_SIGS = {
+    "tled_create": ([ctypes.POINTER(_P), ctypes.c_int], ctypes.c_int),
+    "tled_destroy": ([_P], None),
+    "tled_set_allocator": ([_P, _ALLOC, _FREE, _P], ctypes.c_int),
+    "tled_set_stream": ([_P, _P], ctypes.c_int),
+    "tled_set_options": ([_P, ctypes.POINTER(Options)], ctypes.c_int),
+    "tled_set_mesh": ([_P, ctypes.c_int, _i64, _dp, _i64, ctypes.POINTER(_i32)], ctypes.c_int),
+    "tled_set_material": ([_P, ctypes.POINTER(Material)], ctypes.c_int),
+    "tled_set_fibres": ([_P, _dp], ctypes.c_int),
+    "tled_set_fixed_dofs": ([_P, _i64, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
+    "tled_set_fixed_temperature": ([_P, _i64, ctypes.POINTER(_i32), _dp], ctypes.c_int),
+    "tled_set_heat_source": ([_P, _dp, _d, _d], ctypes.c_int),
+    "tled_set_time": ([_P, _d, _d], ctypes.c_int),
+    "tled_critical_dt": ([_P, _dp], ctypes.c_int),
+    "tled_finalize": ([_P], ctypes.c_int),
+    "tled_step": ([_P, _i64], ctypes.c_int),
+    "tled_sync": ([_P], ctypes.c_int),
+    "tled_read_u": ([_P, _dp], ctypes.c_int),
+    "tled_read_T": ([_P, _dp], ctypes.c_int),
+    "tled_copy_fields_device": ([_P, _P, _P], ctypes.c_int),
+    "tled_get_monitors": ([_P, ctypes.POINTER(Monitors)], ctypes.c_int),
+    "tled_get_info": ([_P, ctypes.POINTER(Info)], ctypes.c_int),
+    "tled_get_lumped": ([_P, _dp, _dp, _dp, _dp, _dp, _dp], ctypes.c_int),
+    "tled_read_state": ([_P, _dp, _dp, _dp, _dp, ctypes.POINTER(_i64)], ctypes.c_int),
+    "tled_write_state": ([_P, _dp, _dp, _dp, _dp, _i64], ctypes.c_int),
+    "tled_state_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "tled_get_state": ([_P, _P], ctypes.c_int),
+    "tled_set_state": ([_P, _P], ctypes.c_int),
+    "tled_kernel_times": ([_P, _i64, _dp], ctypes.c_int),
+    "tled_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "tled_last_error": ([_P], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class TledError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_lib.tled_status_string(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def material(params: dict) -> Material:
+    """Material struct from a dict of field names (missing fields are zero / off)."""
+    m = Material()
+    ints = ("n_prony", "expan_mode", "cond_mode", "muT_on", "shrink_on", "ckT_on")
+    for name, _ in Material._fields_:
+        if name not in params:
+            continue
+        v = params[name]
+        if name in ("g", "tau"):
+            setattr(m, name, (_d * 4)(*([float(x) for x in v] + [0.0] * (4 - len(v)))))
+        elif name in ints:
+            setattr(m, name, int(v))
+        else:
+            setattr(m, name, float(v))
+    if "n_prony" not in params and "g" in params:
+        m.n_prony = len(params["g"])
+    return m
+
+
+class Sim:
+    """One problem on one device (``device=-1``: host-only set-up)."""
+
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = False):
+        h = _P()
+        st = _lib.tled_create(ctypes.byref(h), int(device))
+        if st != OK:
+            raise TledError(st, f"tled_create(device={device}) failed")
+        self._h = h
+        self.device = device
+        self._cb = None
+        if use_torch_allocator and device >= 0:
+            import torch
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+                except Exception:  # noqa: BLE001 - report as allocation failure (NULL)
+                    return None
+
+            def _free(ptr, ctx):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._cb = (_ALLOC(_alloc), _FREE(_free))
+            self._check(_lib.tled_set_allocator(h, self._cb[0], self._cb[1], None))
+        if stream is not None:
+            self._check(_lib.tled_set_stream(h, _P(int(stream))))
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != OK:
+            raise TledError(st, _lib.tled_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tled_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    # ------------------------------------------------------------------ set-up
+    def set_options(self, **kw):
+        o = Options()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        self._check(_lib.tled_set_options(self._h, ctypes.byref(o)))
+
+    def set_mesh(self, elem_type, X, conn):
+        X = _f64(X)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.nn, self.ne, self.npe = X.shape[0], conn.shape[0], int(elem_type)
+        self._check(_lib.tled_set_mesh(self._h, int(elem_type), self.nn, _ptr(X), self.ne,
+                                       conn.ctypes.data_as(ctypes.POINTER(_i32))))
+
+    def set_material(self, params: dict):
+        self.params = dict(params)
+        self._mat = material(params)
+        self.n_prony = self._mat.n_prony
+        self._check(_lib.tled_set_material(self._h, ctypes.byref(self._mat)))
+
+    def set_fibres(self, a0):
+        self._check(_lib.tled_set_fibres(self._h, _ptr(_f64(a0))))
+
+    def set_fixed_dofs(self, nodes, masks):
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        masks = np.ascontiguousarray(masks, dtype=np.uint8)
+        self._check(_lib.tled_set_fixed_dofs(self._h, len(nodes), nodes.ctypes.data_as(ctypes.POINTER(_i32)),
+                                             masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+
+    def set_fixed_temperature(self, nodes, T):
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        T = _f64(T)
+        self._check(_lib.tled_set_fixed_temperature(self._h, len(nodes),
+                                                    nodes.ctypes.data_as(ctypes.POINTER(_i32)), _ptr(T)))
+
+    def set_heat_source(self, q_elem, t_on=0.0, t_off=float("inf")):
+        self._check(_lib.tled_set_heat_source(self._h, _ptr(_f64(q_elem)), float(t_on), float(t_off)))
+
+    def set_time(self, dt, gamma):
+        self.dt = float(dt)
+        self._check(_lib.tled_set_time(self._h, float(dt), float(gamma)))
+
+    def critical_dt(self) -> float:
+        v = _d()
+        self._check(_lib.tled_critical_dt(self._h, ctypes.byref(v)))
+        return v.value
+
+    def finalize(self):
+        self._check(_lib.tled_finalize(self._h))
+
+    # ------------------------------------------------------------------ run
+    def step(self, n: int):
+        self._check(_lib.tled_step(self._h, int(n)))
+
+    def sync(self):
+        self._check(_lib.tled_sync(self._h))
+
+    def read_u(self):
+        out = np.zeros((self.nn, 3))
+        self._check(_lib.tled_read_u(self._h, _ptr(out)))
+        return out
+
+    def read_T(self):
+        out = np.zeros(self.nn)
+        self._check(_lib.tled_read_T(self._h, _ptr(out)))
+        return out
+
+    def copy_fields_device(self, u_dst=None, T_dst=None):
+        """Write u (nn x 3) and T (nn) as float32 into device tensors (caller numbering)."""
+        up = None if u_dst is None else _P(u_dst.data_ptr())
+        tp = None if T_dst is None else _P(T_dst.data_ptr())
+        self._check(_lib.tled_copy_fields_device(self._h, up, tp))
+
+    def monitors(self) -> dict:
+        m = Monitors()
+        self._check(_lib.tled_get_monitors(self._h, ctypes.byref(m)))
+        return m.as_dict()
+
+    def info(self) -> dict:
+        i = Info()
+        self._check(_lib.tled_get_info(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def lumped(self) -> dict:
+        out = {k: np.zeros(self.nn) for k in ("Vl", "M", "C", "Kb", "Qm", "Qr")}
+        self._check(_lib.tled_get_lumped(self._h, *(_ptr(out[k]) for k in ("Vl", "M", "C", "Kb", "Qm", "Qr"))))
+        return out
+
+    def read_state(self) -> dict:
+        u = np.zeros((self.nn, 3)); v = np.zeros((self.nn, 3)); T = np.zeros(self.nn)
+        th = np.zeros((self.ne, self.n_prony, 6))
+        step = _i64()
+        self._check(_lib.tled_read_state(self._h, _ptr(u), _ptr(v), _ptr(T), _ptr(th) if th.size else None,
+                                         ctypes.byref(step)))
+        return {"u": u, "v": v, "T": T, "theta": th, "step": step.value}
+
+    def write_state(self, u=None, v=None, T=None, theta=None, step=0):
+        self._check(_lib.tled_write_state(self._h, _ptr(_f64(u)), _ptr(_f64(v)), _ptr(_f64(T)),
+                                          _ptr(_f64(theta)) if theta is not None and np.size(theta) else None,
+                                          int(step)))
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        self._check(_lib.tled_state_size(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(_lib.tled_get_state(self._h, buf))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(_lib.tled_set_state(self._h, buf))
+
+    def kernel_times(self, n_steps: int):
+        ms = (_d * 3)()
+        self._check(_lib.tled_kernel_times(self._h, int(n_steps), ms))
+        return {"element_ms": ms[0], "node_ms": ms[1], "finish_ms": ms[2]}
+
+
+def from_problem(problem, dt=None, device: int = 0, stream=None, finalize: bool = True,
+                 use_torch_allocator: bool = False, **options) -> Sim:
+    """Set up a :class:`Sim` from a :class:`workloads.Problem` (dt defaults to cfl * critical step)."""
+    s = Sim(device, stream=stream, use_torch_allocator=use_torch_allocator)
+    if options:
+        s.set_options(**options)
+    s.set_mesh(problem.npe, problem.X, problem.conn)
+    s.set_material(problem.params)
+    if problem.a0 is not None:
+        s.set_fibres(problem.a0)
+    if problem.fix is not None:
+        nodes = np.nonzero(problem.fix & 7)[0]
+        if len(nodes):
+            s.set_fixed_dofs(nodes, problem.fix[nodes] & 7)
+        tn = np.nonzero(problem.fix & 8)[0]
+        if len(tn):
+            s.set_fixed_temperature(tn, problem.Tfix[tn])
+    if problem.q is not None:
+        s.set_heat_source(problem.q, problem.t_on, problem.t_off)
+    if dt is None:
+        dt = problem.cfl * s.critical_dt()
+    s.set_time(dt, problem.gamma)
+    if finalize:
+        s.finalize()
+    return s

@@ -1,0 +1,139 @@
+"""CPU-side checks of the library: it loads, exports every symbol the C header declares, and its
+host-only set-up (validation, FP64 precompute, reordering, patch partition) agrees with the
+oracle's independent precompute.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_10400_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tled.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tled_[A-Za-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_10400_amd import tled
+    lib = ctypes.CDLL(tled.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 30
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(tled.EXPORTED)
+
+
+def test_binding_refuses_without_library(tmp_path, monkeypatch):
+    """The product path fails loudly when the HIP library is missing (no CPU fallback)."""
+    import importlib.util
+    import shutil
+    pkg = tmp_path / "pkg"
+    (pkg / "csrc").mkdir(parents=True)
+    shutil.copy(os.path.join(ROOT, "paper_2009_10400_amd", "tled.py"), pkg / "tled.py")
+    spec = importlib.util.spec_from_file_location("tled_missing", pkg / "tled.py")
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)
+
+
+def host_sim(problem, dt=None, **opts):
+    from paper_2009_10400_amd import tled
+    return tled.from_problem(problem, dt=dt if dt is not None else 1e-5, device=-1, **opts)
+
+
+@pytest.mark.parametrize("name", ["cube_t4", "cube_h8", "ellipsoid"])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_host_precompute_matches_oracle(name, variant):
+    p = {"cube_t4": lambda: W.cube_t4(), "cube_h8": lambda: W.cube_h8(n=10),
+         "ellipsoid": lambda: W.ellipsoid_t4(20000)}[name]()
+    s = host_sim(p, kernel_variant=variant)
+    o = oracle.OracleSim(p.npe, p.X, p.conn, p.params, a0=p.a0, q=p.q, fix=p.fix, dt=1e-5)
+    assert s.critical_dt() == pytest.approx(o.critical_dt, rel=1e-12)
+    L, Lo = s.lumped(), o.lumped()
+    for k in ("Vl", "M", "Kb", "Qm", "Qr"):
+        scale = max(np.abs(Lo[k]).max(), 1e-300)
+        assert np.abs(L[k] - Lo[k]).max() <= 1e-12 * scale, k
+    assert L["C"] == pytest.approx(p.params["rho"] * p.params["c"] * Lo["Vl"], rel=1e-12)
+    info = s.info()
+    assert info["kernel_variant"] == variant
+    assert info["n_nodes"] == p.nn and info["n_elems"] == p.ne
+    if variant == 2:
+        assert info["n_patches"] == -(-p.ne // (512 if p.npe == 4 else 256))
+        assert 0 < info["n_shared_nodes"] < p.nn
+
+
+def test_orientation_repair_counted():
+    p = W.cube_t4(n=4, L=0.016)
+    rng = np.random.default_rng(1)
+    flip = rng.random(p.ne) < 0.4
+    p.conn[flip] = p.conn[flip][:, [0, 1, 3, 2]]
+    s = host_sim(p)
+    assert s.info()["n_swapped"] == flip.sum()
+
+
+def test_setup_errors():
+    from paper_2009_10400_amd import tled
+    p = W.cube_t4(n=2, L=0.01)
+    s = tled.Sim(-1)
+    with pytest.raises(tled.TledError) as e:
+        s.set_mesh(5, p.X, p.conn)
+    assert e.value.status == tled.E_ARG
+    bad = p.conn.copy(); bad[0, 0] = p.nn + 3
+    s.set_mesh(4, p.X, bad)
+    s.set_material(p.params)
+    s.set_time(1e-6, 0.0)
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_MESH
+    s = tled.Sim(-1)
+    s.set_mesh(4, p.X, p.conn)
+    s.set_material(dict(p.params, g=[0.6, 0.5], tau=[1, 1], n_prony=2))
+    s.set_time(1e-6, 0.0)
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_ARG and "Prony" in str(e.value)
+    s = tled.Sim(-1)
+    s.set_mesh(4, p.X, p.conn)
+    s.set_material(p.params)
+    s.set_time(1.0, 0.0)            # far above the critical step
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_ARG
+    # inverted H8
+    X, conn, h = W.box_mesh("h8", 2, 0.01)
+    conn = conn.copy(); conn[0] = conn[0][[4, 5, 6, 7, 0, 1, 2, 3]]
+    s = tled.Sim(-1)
+    s.set_mesh(8, X, conn)
+    s.set_material(p.params)
+    s.set_time(1e-6, 0.0)
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_MESH
+    # orphan node
+    X2 = np.vstack([p.X, [[1.0, 1.0, 1.0]]])
+    s = tled.Sim(-1)
+    s.set_mesh(4, X2, p.conn)
+    s.set_material(p.params)
+    s.set_time(1e-6, 0.0)
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_MESH
+
+
+def test_host_handle_refuses_stepping():
+    from paper_2009_10400_amd import tled
+    s = host_sim(W.cube_t4(n=2, L=0.01))
+    with pytest.raises(tled.TledError) as e:
+        s.step(1)
+    assert e.value.status == tled.E_STATE
+    with pytest.raises(tled.TledError) as e:
+        s.read_u()
+    assert e.value.status == tled.E_STATE
