@@ -36,7 +36,7 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--variant", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=50)
@@ -44,7 +44,22 @@ def parse():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 launches) to calibrate HBM counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE give the counter scale."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
 def traffic_from_profiles(kernel_name: str, n_launch_units: float):
@@ -83,6 +98,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU domain decomposition is a design, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
     from paper_2009_10400_amd import tled, workloads as W
 
@@ -136,7 +154,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        steps = args.cpu_steps or max(3, int(12e6 / p.ne))
+        steps = args.cpu_steps or max(3, int(40e6 / p.ne))
         log(f"[bench] CPU baseline: oracle {steps} steps")
         out["cpu_baseline"] = cpu_baseline(p, sim.dt, steps)
     print(json.dumps(out), flush=True)

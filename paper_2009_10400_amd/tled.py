@@ -160,16 +160,22 @@ class Sim:
         self.device = device
         self._cb = None
         if use_torch_allocator and device >= 0:
+            import sys
+
             import torch
+            torch.cuda.init()
+            dev = torch.device("cuda", device)
 
             def _alloc(nbytes, ctx):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), device)
-                except Exception:  # noqa: BLE001 - report as allocation failure (NULL)
+                    with torch.cuda.device(dev):
+                        return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
+                except Exception as exc:  # noqa: BLE001 - reported, then NULL (TLED_E_OOM)
+                    print(f"tled: torch allocator failed for {nbytes} bytes: {exc!r}", file=sys.stderr)
                     return None
 
             def _free(ptr, ctx):
-                torch.cuda.caching_allocator_delete(ptr)
+                torch.cuda.caching_allocator_delete(int(ptr))
 
             self._cb = (_ALLOC(_alloc), _FREE(_free))
             self._check(_lib.tled_set_allocator(h, self._cb[0], self._cb[1], None))
