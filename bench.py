@@ -22,10 +22,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per element-update of the dominant kernel (T4, two Prony
-# terms): connectivity 16 + dh/dX 36 + V0 4 + fibre 12 + Prony state read and
-# written 96 = 164 B, plus 73 B per node of node state advanced inside it.
-ELEM_BYTES_T4_NP2 = 164.0
+# Algorithmic bytes per element-update of the dominant kernel: connectivity
+# 4 or 8 ints, dh/dX (3 or 7 rows of 3 floats), V0, fibre (3 floats), H8
+# hourglass vectors and stiffness (29 floats), Prony state read and written
+# (24 B per term each way); plus 73 B per node of node state advanced inside it.
+def elem_bytes(npe: int, n_prony: int) -> float:
+    if npe == 4:
+        return 16 + 36 + 4 + 12 + 48.0 * n_prony
+    return 32 + 84 + 4 + 12 + 116 + 48.0 * n_prony
+
+
 NODE_BYTES = 73.0
 
 
@@ -40,7 +46,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--variant", type=int, default=2)
     ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--patch-elems", type=int, default=0, help="elements per patch (0: library default)")
+    ap.add_argument("--block-size", type=int, default=0, help="patch kernel threads per workgroup (0: default)")
     ap.add_argument("--elems", type=int, default=1_000_000)
+    ap.add_argument("--workload", default="ellipsoid_t4", choices=["ellipsoid_t4", "cube_h8"],
+                    help="ellipsoid_t4: ~1.0M-tet noisy ellipsoid (default); cube_h8: 64^3 H8 cube")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -62,9 +72,9 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
-def traffic_from_profiles(kernel_name: str, n_launch_units: float):
+def traffic_from_profiles(kernel_name: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -105,12 +115,13 @@ def main():
     from paper_2009_10400_amd import tled, workloads as W
 
     t = time.time()
-    p = W.ellipsoid_t4(args.elems)
+    p = W.ellipsoid_t4(args.elems) if args.workload == "ellipsoid_t4" else W.cube_h8(64)
     log(f"[bench] workload ne={p.ne} nn={p.nn} built in {time.time() - t:.1f}s")
     t = time.time()
     stream = torch.cuda.Stream(device=0)
     sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, kernel_variant=args.variant,
-                            graph_steps=args.graph_steps)
+                            graph_steps=args.graph_steps, patch_elems=args.patch_elems,
+                            block_size=args.block_size)
     info = sim.info()
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
     sim.step(args.warmup)
@@ -129,14 +140,15 @@ def main():
     # dominant kernel, timed with HIP events on the library's stream
     kt = sim.kernel_times(args.kernel_steps)
     sim.sync()
-    kname = "patch_kernel" if info["kernel_variant"] == 2 else "t4_element_kernel"
-    if info["kernel_variant"] == 2:
+    kname = "patch_kernel" if info["kernel_variant"] >= 2 else ("t4_element_kernel" if p.npe == 4 else "h8_element_kernel")
+    eb = elem_bytes(p.npe, info["n_prony"])
+    if info["kernel_variant"] >= 2:
         n_interior = info["n_nodes"] - info["n_shared_nodes"]
-        alg_bytes = ELEM_BYTES_T4_NP2 * p.ne + NODE_BYTES * n_interior
+        alg_bytes = eb * p.ne + NODE_BYTES * n_interior
     else:
-        alg_bytes = ELEM_BYTES_T4_NP2 * p.ne + 16.0 * 4 * p.ne   # plus the nodal outputs it writes
+        alg_bytes = eb * p.ne + 16.0 * p.npe * p.ne   # plus the nodal outputs it writes
     achieved = alg_bytes / (kt["element_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profiles(kname, p.ne)
+    traffic = traffic_from_profiles(kname, p.name)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "kernel_ms": kt["element_ms"], "second_kernel_ms": kt["node_ms"],
@@ -147,13 +159,16 @@ def main():
         "value": value, "unit": "element-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"noisy ellipsoid 0.2x0.15x0.1 m, {p.ne} T4 / {p.nn} nodes, 2 Prony terms, "
-                               f"shrinkage above 323 K, 20 mm 1/r^4 line source (10 W), random numbering",
+        "config": {"workload": (f"noisy ellipsoid 0.2x0.15x0.1 m, {p.ne} T4 / {p.nn} nodes, 2 Prony terms, "
+                                f"shrinkage above 323 K, 20 mm 1/r^4 line source (10 W), random numbering"
+                                if p.npe == 4 else
+                                f"0.1 m cube, {p.ne} H8 (64^3, one-point + hourglass) / {p.nn} nodes, "
+                                f"fibre field, mu(T), 1/r^2 point source (10 W)"),
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
-                   "graph_steps": args.graph_steps, "dt": sim.dt},
+                   "graph_steps": args.graph_steps, "patches": info["n_patches"], "dt": sim.dt},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and p.npe == 4:
         steps = args.cpu_steps or max(3, int(40e6 / p.ne))
         log(f"[bench] CPU baseline: oracle {steps} steps")
         out["cpu_baseline"] = cpu_baseline(p, sim.dt, steps)

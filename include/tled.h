@@ -98,9 +98,13 @@ typedef struct {
     int32_t graph_steps;      /* steps per chunk: a chunk is one hipGraph replay (default 50;
                                  < 0: eager launches in chunks of 100).  Monitors are reduced
                                  at the last step of every chunk and of every tled_step call. */
-    int32_t kernel_variant;   /* 0: auto, 1: two-pass element/node kernels, 2: fused patch kernels */
+    int32_t kernel_variant;   /* 0: default (2); 1: two-pass element/node kernels with precomputed
+                                 geometry; 2: fused patch kernels rebuilding the geometry from
+                                 patch-local coordinates; 3: fused patch kernels reading the
+                                 precomputed geometry                                          */
     int32_t reorder;          /* 0: auto (on), 1: on, -1: keep the caller's order             */
-    int32_t block_size;       /* threads per block for the element pass (0: default)         */
+    int32_t block_size;       /* threads per workgroup of the fused patch kernel: 0 (256),
+                                 256, or 512 (T4 only)                                        */
     int32_t patch_elems;      /* elements per patch for the fused variant (0: default)        */
     double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */
 } tled_options;
@@ -125,6 +129,8 @@ typedef struct {
     int32_t kernel_variant;  /* variant in use after finalize                                 */
     int32_t n_patches;       /* fused variant: number of element patches                     */
     int64_t n_shared_nodes;  /* fused variant: nodes assembled across patches                */
+    int32_t patch_max_nodes; /* fused variant: largest number of nodes of one patch           */
+    int32_t patch_lds_bytes; /* fused variant: dynamic LDS per workgroup                      */
     int64_t device_bytes;    /* device memory held by the handle                              */
     double  dt, dt_critical;
 } tled_info;

@@ -170,6 +170,7 @@ void build_kernel_constants(tled_sim *s) {
             k.pc2[i] = float(m.tau[i] / (dt + m.tau[i]));
         }
     }
+    k.hgk = float(m.hg_coef * (m.kappa + 4.0 * m.mu / 3.0));
     k.n_prony = m.n_prony;
     k.expan_mode = m.expan_mode; k.cond_mode = m.cond_mode; k.muT_on = m.muT_on;
     k.shrink_on = m.shrink_on; k.ckT_on = m.ckT_on;
@@ -180,6 +181,7 @@ void build_kernel_constants(tled_sim *s) {
     p.rho = float(m.rho);
     p.abl_T = float(s->opt.ablation_T > 0 ? s->opt.ablation_T : 333.15);
     p.ck_lo = k.ck_lo; p.ck_inv = k.ck_inv; p.c_lo = k.c_lo; p.c_hi = k.c_hi;
+    p.ckT_on = m.ckT_on;
     p.n_on = first_step_at(s->prob.t_on, dt);
     p.n_off = first_step_at(s->prob.t_off, dt);
 }
@@ -196,6 +198,7 @@ tled_status upload_all(tled_sim *s) {
 
     // element planes
     std::vector<float4> g0(ne), g1(ne), g2(ne), h0, h1, h2;
+    std::vector<float2> fib(ne);
     std::vector<float> khg;
     std::vector<int4> c0(ne), c1;
     if (npe == 8) { h0.resize(ne); h1.resize(ne); h2.resize(ne); khg.resize(ne); c1.resize(ne); }
@@ -203,6 +206,7 @@ tled_status upload_all(tled_sim *s) {
         const double *G = &pc.geo[9 * e];
         float ox, oy;
         oct_encode(&pc.a0[3 * e], &ox, &oy);
+        fib[e] = make_float2(ox, oy);
         g0[e] = make_float4(float(G[0]), float(G[1]), float(G[2]), float(G[3]));
         g1[e] = make_float4(float(G[4]), float(G[5]), float(G[6]), float(G[7]));
         g2[e] = make_float4(float(G[8]), float(pc.V0[e]), ox, oy);
@@ -248,11 +252,13 @@ tled_status upload_all(tled_sim *s) {
     t.nn = int(nn);
     const float4 *cg0, *cg1, *cg2, *chg0 = nullptr, *chg1 = nullptr, *chg2 = nullptr;
     const float *ckhg = nullptr;
-    float4 *dg0, *dg1, *dg2, *dh0 = nullptr, *dh1 = nullptr, *dh2 = nullptr;
+    float4 *dg0 = nullptr, *dg1 = nullptr, *dg2 = nullptr, *dh0 = nullptr, *dh1 = nullptr, *dh2 = nullptr;
     float *dkhg = nullptr;
-    TRY(upload(s, &dg0, g0)); TRY(upload(s, &dg1, g1)); TRY(upload(s, &dg2, g2));
-    if (npe == 8) {
-        TRY(upload(s, &dh0, h0)); TRY(upload(s, &dh1, h1)); TRY(upload(s, &dh2, h2)); TRY(upload(s, &dkhg, khg));
+    if (s->variant != 2) {   // variant 2 rebuilds the geometry from patch-local coordinates
+        TRY(upload(s, &dg0, g0)); TRY(upload(s, &dg1, g1)); TRY(upload(s, &dg2, g2));
+        if (npe == 8) {
+            TRY(upload(s, &dh0, h0)); TRY(upload(s, &dh1, h1)); TRY(upload(s, &dh2, h2)); TRY(upload(s, &dkhg, khg));
+        }
     }
     cg0 = dg0; cg1 = dg1; cg2 = dg2; chg0 = dh0; chg1 = dh1; chg2 = dh2; ckhg = dkhg;
     float4 *dnu4, *dnv4, *dnth;
@@ -304,13 +310,19 @@ tled_status upload_all(tled_sim *s) {
         TRY(upload(s, &d, P.shared_ids)); a.shared_ids = d;
         TRY(upload(s, &d, P.lrow_begin)); a.lrow_begin = d;
         TRY(upload(s, &d, P.srow)); a.srow = d;
-        TRY(upload(s, &d, P.sidx)); a.sidx = d;
+        TRY(upload(s, &d, P.ppos)); a.ppos = d;
+        a.slot_stride = P.slot_stride;
+        TRY(upload(s, &d, P.lx_begin)); a.lx_begin = d;
+        float *dlx;
+        TRY(upload(s, &dlx, P.lX)); a.lX = dlx;
+        float2 *dfib;
+        TRY(upload(s, &dfib, fib)); a.fib = dfib;
         uint16_t *u16;
         TRY(upload(s, &u16, P.lconn)); a.lconn = u16;
         TRY(upload(s, &u16, P.lrow)); a.lrow = u16;
         TRY(upload(s, &u16, P.lslot)); a.lslot = u16;
-        a.g0 = cg0; a.g1 = cg1; a.g2 = cg2; a.hg0 = chg0; a.hg1 = chg1; a.hg2 = chg2; a.khg = ckhg;
         a.nu4 = dnu4; a.nv4 = dnv4; a.nth = dnth; a.mask = dmask; a.Vl = dVl; a.theta = dtheta;
+        a.g0 = cg0; a.g1 = cg1; a.g2 = cg2; a.hg0 = chg0; a.hg1 = chg1; a.hg2 = chg2; a.khg = ckhg;
         float4 *dpart;
         TRY(zeros(s, &dpart, std::max<size_t>(P.shared_ids.size(), 1)));
         a.partial = dpart;
@@ -330,15 +342,15 @@ tled_status upload_all(tled_sim *s) {
 // Enqueue a chunk of k steps (eager, or under stream capture).
 tled_status enqueue_chunk(tled_sim *s, int k, double *ms = nullptr, std::vector<hipEvent_t> *ev = nullptr) {
     const int npe = s->pc.npe;
-    const bool ckt = s->prob.mat.ckT_on != 0;
+    const int bs = s->opt.block_size > 0 ? s->opt.block_size : kBlock;
     for (int j = 0; j < k; ++j) {
         const bool mon = (j == k - 1);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j], s->stream));
         if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream);
-        else launch_patch(npe, s->np, mon, ckt, s->pa, s->km, s->nparams, j, s->stream);
+        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->pa, s->km, s->nparams, j, s->stream);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 1], s->stream));
-        if (s->variant == 1) launch_node(mon, ckt, s->tp, s->nparams, j, s->stream);
-        else launch_shared_nodes(mon, ckt, s->pa, s->nparams, j, s->stream);
+        if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream);
+        else launch_shared_nodes(mon, s->pa, s->nparams, j, s->stream);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 2], s->stream));
     }
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,
@@ -471,9 +483,10 @@ tled_status tled_set_stream(tled_sim *sim, void *hip_stream) {
 
 tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
     if (!sim || !opt) return TLED_E_ARG;
-    if (opt->kernel_variant < 0 || opt->kernel_variant > 2) return fail(sim, TLED_E_ARG, "kernel_variant must be 0, 1 or 2");
+    if (opt->kernel_variant < 0 || opt->kernel_variant > 3) return fail(sim, TLED_E_ARG, "kernel_variant must be 0..3");
     if (opt->patch_elems < 0 || opt->patch_elems > 4096) return fail(sim, TLED_E_ARG, "patch_elems out of range");
-    if (opt->block_size != 0 && opt->block_size != kBlock) return fail(sim, TLED_E_UNSUPPORTED, "block_size must be 256");
+    if (opt->block_size != 0 && opt->block_size != 256 && opt->block_size != 512)
+        return fail(sim, TLED_E_UNSUPPORTED, "block_size must be 256 or 512");
     if (sim->finalized && (opt->kernel_variant != sim->opt.kernel_variant || opt->reorder != sim->opt.reorder ||
                            opt->patch_elems != sim->opt.patch_elems))
         return fail(sim, TLED_E_STATE, "layout options must be set before tled_finalize");
@@ -590,21 +603,25 @@ tled_status tled_critical_dt(tled_sim *sim, double *dt_cr) {
 tled_status tled_finalize(tled_sim *sim) {
     TRY(need_setup(sim));
     if (!sim->prob.have_time) return fail(sim, TLED_E_STATE, "call tled_set_time first");
-    int v = sim->opt.kernel_variant == 0 ? 1 : sim->opt.kernel_variant;
+    int v = sim->opt.kernel_variant == 0 ? 2 : sim->opt.kernel_variant;
     SetupOptions so;
     so.reorder = sim->opt.reorder >= 0;
-    so.build_patches = (v == 2);
-    so.patch_elems = sim->opt.patch_elems > 0 ? sim->opt.patch_elems : (sim->prob.npe == 4 ? 512 : 256);
+    so.build_patches = (v >= 2);
+    // Default patch sizes: 448 T4 elements (3 workgroups of 256 threads per CU fit the LDS, and
+    // the ~1M-tet mesh then fills the machine in just under three rounds), 256 H8 elements.
+    so.patch_elems = sim->opt.patch_elems > 0 ? sim->opt.patch_elems : (sim->prob.npe == 4 ? 448 : 256);
+    if (sim->opt.block_size == 512 && sim->prob.npe == 8)
+        return fail(sim, TLED_E_UNSUPPORTED, "block_size 512 is for T4 meshes only");
     tled_status st = precompute(sim->prob, so, &sim->pc, &sim->err);
     if (st != TLED_OK) return st;
     if (sim->prob.dt > sim->pc.dt_cr)
         return fail(sim, TLED_E_ARG, "dt exceeds the critical time step " + std::to_string(sim->pc.dt_cr));
     sim->variant = v;
-    if (v == 2) {
+    if (v >= 2) {
         PatchArgs probe{};
         probe.max_nodes = sim->pc.patches.max_nodes;
         probe.max_elems = sim->pc.patches.max_elems;
-        if (patch_lds_bytes(sim->prob.npe, probe) > 65536 - 1024)
+        if (patch_lds_bytes(sim->prob.npe, v == 2, probe) > 65536 - 1024)
             return fail(sim, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
     }
     build_kernel_constants(sim);
@@ -719,8 +736,16 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
     if (sim->finalized) {
         out->n_swapped = sim->pc.n_swapped;
         out->kernel_variant = sim->variant;
-        out->n_patches = sim->variant == 2 ? sim->pc.patches.n : 0;
-        out->n_shared_nodes = sim->variant == 2 ? sim->pc.nn - sim->pc.patches.n_interior : 0;
+        const bool fused = sim->variant >= 2;
+        out->n_patches = fused ? sim->pc.patches.n : 0;
+        out->n_shared_nodes = fused ? sim->pc.nn - sim->pc.patches.n_interior : 0;
+        out->patch_max_nodes = fused ? sim->pc.patches.max_nodes : 0;
+        if (fused) {
+            PatchArgs probe{};
+            probe.max_nodes = sim->pc.patches.max_nodes;
+            probe.max_elems = sim->pc.patches.max_elems;
+            out->patch_lds_bytes = int32_t(patch_lds_bytes(sim->prob.npe, sim->variant == 2, probe));
+        }
         out->device_bytes = sim->device_bytes;
         out->dt_critical = sim->pc.dt_cr;
     }

@@ -25,6 +25,7 @@ struct KMat {
     float ck_lo, ck_inv;          // c(T), k(T) ramp
     float c_lo, c_hi, kr_hi;      // c at lo/hi; k_hi / k
     float pc1[4], pc2[4];         // Prony: dt g/(dt + tau), tau/(dt + tau)
+    float hgk;                    // hourglass: hg_coef (kappa + 4 mu / 3)
     int n_prony;
     int expan_mode, cond_mode, muT_on, shrink_on, ckT_on;
 };
@@ -34,6 +35,20 @@ struct Sym3 {
 };
 
 __device__ __forceinline__ float clamp01f(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Hardware reciprocal (v_rcp_f32, within 1 ulp).  Every reciprocal here is of a
+// quantity near 1 or of a well-scaled determinant, so the IEEE division
+// sequence is not needed.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// (1 + x)^(-2/3) - 1.  Binomial series to x^5 for |x| < 0.02 (truncation below
+// 3e-11, i.e. < 3e-9 relative), else expm1(-2/3 log1p(x)).
+__device__ __forceinline__ float pow_m23_m1(float x) {
+    if (fabsf(x) < 0.02f)
+        return x * (-2.0f / 3.0f +
+                    x * (5.0f / 9.0f + x * (-40.0f / 81.0f + x * (110.0f / 243.0f + x * (-308.0f / 729.0f)))));
+    return expm1f(-(2.0f / 3.0f) * log1pf(x));
+}
 
 // Symmetric product (A B + (A B)^T)/2 of two symmetric matrices.
 __device__ __forceinline__ Sym3 sym_prod(const Sym3 &A, const Sym3 &B) {
@@ -101,7 +116,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     // ---- thermal split, Eqs. 7-8, 11
     float li1, lm1;
     stretch_m1(m, dTe, li1, lm1);
-    const float li = 1.0f + li1, inv_li = 1.0f / li;
+    const float li = 1.0f + li1, inv_li = rcp(li);
     float He[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) He[i] = H[i] * inv_li;
@@ -112,7 +127,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     if (m.expan_mode == 1) {
         // F_e = F/li + beta (F a) (x) a, beta = 1/lm - 1/li = (li1 - lm1)/(li lm)
         lm = 1.0f + lm1;
-        beta = (li1 - lm1) * inv_li / lm;
+        beta = (li1 - lm1) * inv_li * rcp(lm);
         float Fa0 = a[0] + H[0] * a[0] + H[1] * a[1] + H[2] * a[2];
         float Fa1 = a[1] + H[3] * a[0] + H[4] * a[1] + H[5] * a[2];
         float Fa2 = a[2] + H[6] * a[0] + H[7] * a[1] + H[8] * a[2];
@@ -132,12 +147,12 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     E.xz = 0.5f * (He[2] + He[6] + He[0] * He[2] + He[3] * He[5] + He[6] * He[8]);
     const float Jm1 = det_m1(He);
     const float J = 1.0f + Jm1;
-    const float j23m1 = expm1f(-(2.0f / 3.0f) * log1pf(Jm1));
+    const float j23m1 = pow_m23_m1(Jm1);
     const float j23 = 1.0f + j23m1;
     // C = I + 2E, C^-1 = adj(C) / J^2
     Sym3 C{1.0f + 2.0f * E.xx, 1.0f + 2.0f * E.yy, 1.0f + 2.0f * E.zz, 2.0f * E.xy, 2.0f * E.yz, 2.0f * E.xz};
     Sym3 Ci = sym_adj(C);
-    const float invJ2 = 1.0f / (J * J);
+    const float invJ2 = rcp(J * J);
     Ci.xx *= invJ2; Ci.yy *= invJ2; Ci.zz *= invJ2; Ci.xy *= invJ2; Ci.yz *= invJ2; Ci.xz *= invJ2;
     const float trE = E.xx + E.yy + E.zz;
     Sym3 dev{E.xx - trE * (1.0f / 3.0f), E.yy - trE * (1.0f / 3.0f), E.zz - trE * (1.0f / 3.0f), E.xy, E.yz, E.xz};
@@ -221,7 +236,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
                 H[5] + H[7] + H[1] * H[2] + H[4] * H[5] + H[7] * H[8],
                 H[2] + H[6] + H[0] * H[2] + H[3] * H[5] + H[6] * H[8]};
         Sym3 A = sym_adj(Ct);
-        const float f = m.k * kscale / Jt;
+        const float f = m.k * kscale * rcp(Jt);
         K[0] = f * A.xx; K[1] = f * A.yy; K[2] = f * A.zz; K[3] = f * A.xy; K[4] = f * A.yz; K[5] = f * A.xz;
     } else {
         // adj(F) D adj(F)^T / J, D = k I + (k_m - k) a a
@@ -229,7 +244,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
         float Ad[9] = {F[4] * F[8] - F[5] * F[7], F[2] * F[7] - F[1] * F[8], F[1] * F[5] - F[2] * F[4],
                        F[5] * F[6] - F[3] * F[8], F[0] * F[8] - F[2] * F[6], F[2] * F[3] - F[0] * F[5],
                        F[3] * F[7] - F[4] * F[6], F[1] * F[6] - F[0] * F[7], F[0] * F[4] - F[1] * F[3]};
-        const float kk = m.k * kscale, km = m.k_m * kscale;
+        const float kk = m.k * kscale, km = m.k_m * kscale, iJt = rcp(Jt);
         float Aa[3] = {Ad[0] * a[0] + Ad[1] * a[1] + Ad[2] * a[2], Ad[3] * a[0] + Ad[4] * a[1] + Ad[5] * a[2],
                        Ad[6] * a[0] + Ad[7] * a[1] + Ad[8] * a[2]};
         float r[3][3];
@@ -238,7 +253,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
 #pragma unroll
             for (int j = 0; j < 3; ++j)
                 r[i][j] = (kk * (Ad[3 * i] * Ad[3 * j] + Ad[3 * i + 1] * Ad[3 * j + 1] + Ad[3 * i + 2] * Ad[3 * j + 2]) +
-                           (km - kk) * Aa[i] * Aa[j]) / Jt;
+                           (km - kk) * Aa[i] * Aa[j]) * iJt;
         K[0] = r[0][0]; K[1] = r[1][1]; K[2] = r[2][2]; K[3] = r[0][1]; K[4] = r[1][2]; K[5] = r[0][2];
     }
     o.qV[0] = V0 * (K[0] * gT[0] + K[3] * gT[1] + K[5] * gT[2]);

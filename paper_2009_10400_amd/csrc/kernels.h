@@ -12,6 +12,9 @@ namespace tled {
 constexpr int kBlock = 256;   // threads per block (4 wavefronts of 64)
 constexpr int kNumXcd = 8;    // accelerator complex dies of an MI355X
 
+// Threads per workgroup of the fused patch kernel: 256 (4 wavefronts); T4 may
+// also use 512.
+
 // Node-update constants.
 struct NodeParams {
     float A;          // (1 - gamma dt/2) / (1 + gamma dt/2)
@@ -19,7 +22,8 @@ struct NodeParams {
     float T0;
     float rho;
     float abl_T;      // ablation threshold temperature, K
-    float ck_lo, ck_inv, c_lo, c_hi;   // c(T) law (when enabled)
+    float ck_lo, ck_inv, c_lo, c_hi;   // c(T) law (when ckT_on)
+    int ckT_on;
     long long n_on, n_off;             // source active for n_on <= step < n_off
 };
 
@@ -50,13 +54,16 @@ struct TwoPassArgs {
 };
 
 struct PatchArgs {
-    int ne, n_patches, max_nodes, max_elems;
+    int ne, n_patches, max_nodes, max_elems, slot_stride;
     int n_interior, n_shared;
     const int *elem_begin, *int_begin, *shared_begin, *shared_ids;
     const uint16_t *lconn, *lrow, *lslot;
     const int *lrow_begin;
-    const int *srow, *sidx;
-    const float4 *g0, *g1, *g2, *hg0, *hg1, *hg2;
+    const int *srow, *ppos;
+    const float *lX;            // per-patch local reference coordinates (x, y, z)
+    const int *lx_begin;
+    const float2 *fib;          // fibre, octahedral coordinates
+    const float4 *g0, *g1, *g2, *hg0, *hg1, *hg2;   // precomputed geometry (plane variant)
     const float *khg;
     float4 *nu4, *nv4;
     const float4 *nth;
@@ -70,13 +77,13 @@ struct PatchArgs {
 };
 
 void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s);
-void launch_node(bool mon, bool ckt, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
-void launch_patch(int npe, int np, bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p,
-                  int j, hipStream_t s);
-void launch_shared_nodes(bool mon, bool ckt, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s);
+void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m,
+                  const NodeParams &p, int j, hipStream_t s);
+void launch_shared_nodes(bool mon, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s);
 void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,
                    long long *step_base, int k, const unsigned *status, DevMonitors *mon, hipStream_t s);
-size_t patch_lds_bytes(int npe, const PatchArgs &a);
+size_t patch_lds_bytes(int npe, bool geox, const PatchArgs &a);
 
 }  // namespace tled
 

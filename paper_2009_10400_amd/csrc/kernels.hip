@@ -80,14 +80,53 @@ struct ElemResultT4 {
     bool nonfinite, inverted;
 };
 
-// T4: node data u4 = (ux, uy, uz, dT); geometry g0,g1,g2 = (b1, b2, b3, V0, fibre oct).
-template <int NP, bool MON>
-__device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], float4 g0, float4 g1, float4 g2,
-                                           float *th, ElemResultT4 &r) {
-    const float b[3][3] = {{g0.x, g0.y, g0.z}, {g0.w, g1.x, g1.y}, {g1.z, g1.w, g2.x}};
-    const float V0 = g2.y;
+// T4 geometry: rows b_k = dh_{k}/dX of local nodes 1..3 (node 0 is minus their sum), V0, fibre.
+struct GeoT4 {
+    float b[3][3];
+    float V0;
     float a[3];
-    oct_decode(g2.z, g2.w, a);
+};
+
+// From the precomputed planes g0,g1,g2 = (b1, b2, b3, V0, fibre in octahedral coordinates).
+__device__ __forceinline__ GeoT4 t4_geo_planes(float4 g0, float4 g1, float4 g2) {
+    GeoT4 g;
+    g.b[0][0] = g0.x; g.b[0][1] = g0.y; g.b[0][2] = g0.z;
+    g.b[1][0] = g0.w; g.b[1][1] = g1.x; g.b[1][2] = g1.y;
+    g.b[2][0] = g1.z; g.b[2][1] = g1.w; g.b[2][2] = g2.x;
+    g.V0 = g2.y;
+    oct_decode(g2.z, g2.w, g.a);
+    return g;
+}
+
+// From reference coordinates (relative to the patch centroid): with edge columns
+// e_k = X_k - X_0, D^-1 has rows (e2 x e3, e3 x e1, e1 x e2) / det D and V0 = det D / 6.
+__device__ __forceinline__ GeoT4 t4_geo_coords(const float4 x[4], float2 fib) {
+    GeoT4 g;
+    const float e[3][3] = {{x[1].x - x[0].x, x[1].y - x[0].y, x[1].z - x[0].z},
+                           {x[2].x - x[0].x, x[2].y - x[0].y, x[2].z - x[0].z},
+                           {x[3].x - x[0].x, x[3].y - x[0].y, x[3].z - x[0].z}};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float *p = e[(k + 1) % 3], *q = e[(k + 2) % 3];
+        g.b[k][0] = p[1] * q[2] - p[2] * q[1];
+        g.b[k][1] = p[2] * q[0] - p[0] * q[2];
+        g.b[k][2] = p[0] * q[1] - p[1] * q[0];
+    }
+    const float det = e[0][0] * g.b[0][0] + e[0][1] * g.b[0][1] + e[0][2] * g.b[0][2];
+    const float inv = rcp(det);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        g.b[k][0] *= inv; g.b[k][1] *= inv; g.b[k][2] *= inv;
+    }
+    g.V0 = det * (1.0f / 6.0f);
+    oct_decode(fib.x, fib.y, g.a);
+    return g;
+}
+
+// T4 element: node data u4 = (ux, uy, uz, dT).
+template <int NP, bool MON>
+__device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], const GeoT4 &g, float *th,
+                                           ElemResultT4 &r) {
     float d[3][4];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -100,20 +139,22 @@ __device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], flo
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) H[3 * i + j] = d[0][i] * b[0][j] + d[1][i] * b[1][j] + d[2][i] * b[2][j];
+        for (int j = 0; j < 3; ++j)
+            H[3 * i + j] = d[0][i] * g.b[0][j] + d[1][i] * g.b[1][j] + d[2][i] * g.b[2][j];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) gT[j] = d[0][3] * b[0][j] + d[1][3] * b[1][j] + d[2][3] * b[2][j];
+    for (int j = 0; j < 3; ++j) gT[j] = d[0][3] * g.b[0][j] + d[1][3] * g.b[1][j] + d[2][3] * g.b[2][j];
     const float dTe = 0.25f * (u[0].w + u[1].w + u[2].w + u[3].w);
     ElemOut eo;
-    element_physics<NP>(m, H, gT, dTe, a, V0, th, MON, eo);
+    element_physics<NP>(m, H, gT, dTe, g.a, g.V0, th, MON, eo);
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+        const float *b = g.b[k];
         float4 f;
-        f.x = eo.PV[0] * b[k][0] + eo.PV[1] * b[k][1] + eo.PV[2] * b[k][2];
-        f.y = eo.PV[3] * b[k][0] + eo.PV[4] * b[k][1] + eo.PV[5] * b[k][2];
-        f.z = eo.PV[6] * b[k][0] + eo.PV[7] * b[k][1] + eo.PV[8] * b[k][2];
-        f.w = eo.qV[0] * b[k][0] + eo.qV[1] * b[k][1] + eo.qV[2] * b[k][2];
+        f.x = eo.PV[0] * b[0] + eo.PV[1] * b[1] + eo.PV[2] * b[2];
+        f.y = eo.PV[3] * b[0] + eo.PV[4] * b[1] + eo.PV[5] * b[2];
+        f.z = eo.PV[6] * b[0] + eo.PV[7] * b[1] + eo.PV[8] * b[2];
+        f.w = eo.qV[0] * b[0] + eo.qV[1] * b[1] + eo.qV[2] * b[2];
         r.o[k + 1] = f;
         s.x += f.x; s.y += f.y; s.z += f.z; s.w += f.w;
     }
@@ -135,14 +176,77 @@ struct ElemResultH8 {
     bool nonfinite, inverted;
 };
 
-// H8 one-point: G = J0^-T (dh_a/dX = G s_a / 8), c_alpha = X^T h_alpha, k_hg.
-template <int NP, bool MON>
-__device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], float4 g0, float4 g1, float4 g2,
-                                           const float c[12], float khg, float *th, ElemResultH8 &r) {
-    const float G[9] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w, g2.x};
-    const float V0 = g2.y;
+// H8 geometry: G = J0^-T (dh_a/dX = G s_a / 8), V0, fibre, c_alpha = X^T h_alpha, k_hg.
+struct GeoH8 {
+    float G[9];
+    float V0;
     float a[3];
-    oct_decode(g2.z, g2.w, a);
+    float c[12];
+    float khg;
+};
+
+__device__ __forceinline__ GeoH8 h8_geo_planes(float4 g0, float4 g1, float4 g2, float4 h0, float4 h1, float4 h2,
+                                               float khg) {
+    GeoH8 g;
+    g.G[0] = g0.x; g.G[1] = g0.y; g.G[2] = g0.z; g.G[3] = g0.w; g.G[4] = g1.x;
+    g.G[5] = g1.y; g.G[6] = g1.z; g.G[7] = g1.w; g.G[8] = g2.x;
+    g.V0 = g2.y;
+    oct_decode(g2.z, g2.w, g.a);
+    const float c[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+#pragma unroll
+    for (int i = 0; i < 12; ++i) g.c[i] = c[i];
+    g.khg = khg;
+    return g;
+}
+
+// From reference coordinates: J0 = sum_a X_a (x) s_a / 8, G = J0^-T, V0 = 8 det J0,
+// c_alpha = sum_a h_alpha,a X_a, k_hg = hg (kappa + 4 mu / 3) V0 tr(G^T G) / 64
+// (sum_a |G s_a / 8|^2 = tr(G^T G) / 8 since sum_a s_a s_a^T = 8 I).
+__device__ __forceinline__ GeoH8 h8_geo_coords(const float4 x[8], float2 fib, float hgk) {
+    GeoH8 g;
+    float J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 12; ++i) g.c[i] = 0.f;
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        const float s[3] = {hsx(n), hsy(n), hsz(n)};
+        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
+        const float xv[3] = {x[n].x - x[0].x, x[n].y - x[0].y, x[n].z - x[0].z};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) J[3 * i + j] += xv[i] * s[j];
+#pragma unroll
+            for (int al = 0; al < 4; ++al) g.c[3 * al + i] += h[al] * xv[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) J[i] *= 0.125f;
+    // G = J0^-T = cof(J0) / det J0
+    const float cof[9] = {J[4] * J[8] - J[5] * J[7], J[5] * J[6] - J[3] * J[8], J[3] * J[7] - J[4] * J[6],
+                          J[2] * J[7] - J[1] * J[8], J[0] * J[8] - J[2] * J[6], J[1] * J[6] - J[0] * J[7],
+                          J[1] * J[5] - J[2] * J[4], J[2] * J[3] - J[0] * J[5], J[0] * J[4] - J[1] * J[3]};
+    const float det = J[0] * cof[0] + J[1] * cof[1] + J[2] * cof[2];
+    const float inv = rcp(det);
+    float tr = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        g.G[i] = cof[i] * inv;
+        tr += g.G[i] * g.G[i];
+    }
+    g.V0 = 8.0f * det;
+    g.khg = hgk * g.V0 * tr * (1.0f / 64.0f);
+    oct_decode(fib.x, fib.y, g.a);
+    return g;
+}
+
+template <int NP, bool MON>
+__device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], const GeoH8 &g, float *th,
+                                           ElemResultH8 &r) {
+    const float *G = g.G;
+    const float *c = g.c;
+    const float V0 = g.V0, khg = g.khg;
+    const float *a = g.a;
     // U_ik = sum_a u_a,i s_a,k / 8 ; t_k = sum_a dT_a s_a,k / 8 ; hourglass sums
     float U[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, t[3] = {0, 0, 0};
     float hu[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -238,14 +342,13 @@ struct NodeNew {
 // velocity form of the central difference of Eq. 27 (R = 0, D = gamma M):
 //   v+ = A v- - B f,  A = (1 - gamma dt/2)/(1 + gamma dt/2),  B = dt / (M (1 + gamma dt/2)),
 //   u+ = u + dt v+.
-template <bool CKT>
 __device__ __forceinline__ NodeNew node_advance(const NodeParams &p, float4 u, float4 v, float4 th, unsigned mk,
                                                 float4 acc, float src) {
     NodeNew r;
     float dT = u.w;
     if (!(mk & 8u)) {
         float dtC = th.x;
-        if (CKT) {
+        if (p.ckT_on) {
             float w = clamp01f((p.T0 + dT - p.ck_lo) * p.ck_inv);
             dtC = dtC / (p.c_lo + w * (p.c_hi - p.c_lo));
         }
@@ -311,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void t4_element_kernel(
         float th[6 * NP + 1];
         load_theta(theta, ne, e, NP, th);
         ElemResultT4 r;
-        t4_compute<NP, MON>(m, u, g0[e], g1[e], g2[e], th, r);
+        t4_compute<NP, MON>(m, u, t4_geo_planes(g0[e], g1[e], g2[e]), th, r);
         store_theta(theta, ne, e, NP, th);
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[4 * size_t(e) + k] = r.o[k];
@@ -341,12 +444,10 @@ __global__ __launch_bounds__(kBlock) void h8_element_kernel(
     if (e < ne) {
         const int4 ca = conn0[e], cb = conn1[e];
         float4 u[8] = {nu4[ca.x], nu4[ca.y], nu4[ca.z], nu4[ca.w], nu4[cb.x], nu4[cb.y], nu4[cb.z], nu4[cb.w]};
-        const float4 h0 = hg0[e], h1 = hg1[e], h2 = hg2[e];
-        const float c[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
         float th[6 * NP + 1];
         load_theta(theta, ne, e, NP, th);
         ElemResultH8 r;
-        h8_compute<NP, MON>(m, u, g0[e], g1[e], g2[e], c, khg[e], th, r);
+        h8_compute<NP, MON>(m, u, h8_geo_planes(g0[e], g1[e], g2[e], hg0[e], hg1[e], hg2[e], khg[e]), th, r);
         store_theta(theta, ne, e, NP, th);
 #pragma unroll
         for (int k = 0; k < 8; ++k) out[8 * size_t(e) + k] = r.o[k];
@@ -361,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void h8_element_kernel(
     }
 }
 
-template <bool MON, bool CKT>
+template <bool MON>
 __global__ __launch_bounds__(kBlock) void node_kernel(
     const int *__restrict__ rowptr, const int *__restrict__ inc, const float4 *__restrict__ out,
     float4 *__restrict__ nu4, float4 *__restrict__ nv4, const float4 *__restrict__ nth,
@@ -381,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
             const float4 o = out[inc[k]];
             acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
         }
-        NodeNew r = node_advance<CKT>(p, nu4[a], nv4[a], nth[a], mask[a], acc, src);
+        NodeNew r = node_advance(p, nu4[a], nv4[a], nth[a], mask[a], acc, src);
         nu4[a] = r.u;
         nv4[a] = r.v;
         nf = r.nonfinite;
@@ -393,36 +494,49 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
 
 // ---------------------------------------------------------------- fused patch kernels
 
-// One workgroup per patch.  LDS: local node data (npe-independent float4 per
-// local node) and the element-slot outputs (float4 per element slot).
-template <int NPE, int NP, bool MON, bool CKT>
-__global__ __launch_bounds__(kBlock) void patch_kernel(PatchArgs A, KMat m, NodeParams p, int j) {
+// One workgroup of BS threads per patch.  LDS: local node state and reference
+// coordinates (float4 each per local node) and the element-slot outputs
+// (float4 per element slot).  GEOX: element geometry rebuilt from the staged
+// coordinates (else read from the precomputed planes).
+template <int NPE, int NP, bool MON, int BS, bool GEOX>
+__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, KMat m, NodeParams p, int j) {
     extern __shared__ float4 lds[];
-    __shared__ double shd[kBlock / 64];
-    __shared__ float shf[kBlock / 64];
+    __shared__ double shd[BS / 64];
+    __shared__ float shf[BS / 64];
     const int pid = xcd_block(blockIdx.x, gridDim.x);
     const int e0 = A.elem_begin[pid], e1 = A.elem_begin[pid + 1];
     const int ib = A.int_begin[pid], ie = A.int_begin[pid + 1];
     const int sb = A.shared_begin[pid], se = A.shared_begin[pid + 1];
     const int nint = ie - ib, nloc = nint + (se - sb);
-    float4 *lnode = lds;                    // nloc
-    float4 *lout = lds + A.max_nodes;       // (e1 - e0) * NPE
-    for (int l = threadIdx.x; l < nloc; l += kBlock)
+    float4 *lnode = lds;                                   // nloc: (u, dT)
+    float4 *lxyz = lds + A.max_nodes;                      // nloc: reference coordinates (GEOX)
+    float4 *lout = lds + (GEOX ? 2 : 1) * A.max_nodes;     // (e1 - e0) * NPE
+    const float *gx = GEOX ? A.lX + 3 * size_t(A.lx_begin[pid]) : nullptr;
+    for (int l = threadIdx.x; l < nloc; l += BS) {
         lnode[l] = (l < nint) ? A.nu4[ib + l] : A.nu4[A.shared_ids[sb + l - nint]];
+        if (GEOX) lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2], 0.f);
+    }
     __syncthreads();
     float psi = 0.f;
     bool nf = false, inv = false;
-    for (int e = e0 + threadIdx.x; e < e1; e += kBlock) {
+    for (int e = e0 + threadIdx.x; e < e1; e += BS) {
         float th[6 * NP + 1];
         load_theta(A.theta, A.ne, e, NP, th);
         const int el = e - e0;
         if (NPE == 4) {
             const ushort4 c = reinterpret_cast<const ushort4 *>(A.lconn)[e];
             float4 u[4] = {lnode[c.x], lnode[c.y], lnode[c.z], lnode[c.w]};
+            GeoT4 g;
+            if (GEOX) {
+                const float4 x[4] = {lxyz[c.x], lxyz[c.y], lxyz[c.z], lxyz[c.w]};
+                g = t4_geo_coords(x, A.fib[e]);
+            } else {
+                g = t4_geo_planes(A.g0[e], A.g1[e], A.g2[e]);
+            }
             ElemResultT4 r;
-            t4_compute<NP, MON>(m, u, A.g0[e], A.g1[e], A.g2[e], th, r);
+            t4_compute<NP, MON>(m, u, g, th, r);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lout[4 * el + k] = r.o[k];
+            for (int k = 0; k < 4; ++k) lout[k * A.slot_stride + el] = r.o[k];
             psi += r.psiV;
             nf |= r.nonfinite;
             inv |= r.inverted;
@@ -431,12 +545,18 @@ __global__ __launch_bounds__(kBlock) void patch_kernel(PatchArgs A, KMat m, Node
             const ushort4 cb = reinterpret_cast<const ushort4 *>(A.lconn)[2 * e + 1];
             float4 u[8] = {lnode[ca.x], lnode[ca.y], lnode[ca.z], lnode[ca.w],
                            lnode[cb.x], lnode[cb.y], lnode[cb.z], lnode[cb.w]};
-            const float4 h0 = A.hg0[e], h1 = A.hg1[e], h2 = A.hg2[e];
-            const float c[12] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w, h2.x, h2.y, h2.z, h2.w};
+            GeoH8 g;
+            if (GEOX) {
+                const float4 x[8] = {lxyz[ca.x], lxyz[ca.y], lxyz[ca.z], lxyz[ca.w],
+                                     lxyz[cb.x], lxyz[cb.y], lxyz[cb.z], lxyz[cb.w]};
+                g = h8_geo_coords(x, A.fib[e], m.hgk);
+            } else {
+                g = h8_geo_planes(A.g0[e], A.g1[e], A.g2[e], A.hg0[e], A.hg1[e], A.hg2[e], A.khg[e]);
+            }
             ElemResultH8 r;
-            h8_compute<NP, MON>(m, u, A.g0[e], A.g1[e], A.g2[e], c, A.khg[e], th, r);
+            h8_compute<NP, MON>(m, u, g, th, r);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) lout[8 * el + k] = r.o[k];
+            for (int k = 0; k < 8; ++k) lout[k * A.slot_stride + el] = r.o[k];
             psi += r.psiV;
             nf |= r.nonfinite;
             inv |= r.inverted;
@@ -449,33 +569,41 @@ __global__ __launch_bounds__(kBlock) void patch_kernel(PatchArgs A, KMat m, Node
     const uint16_t *lrow = A.lrow + A.lrow_begin[pid];
     const uint16_t *lslot = A.lslot + size_t(e0) * NPE;
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
-    for (int l = threadIdx.x; l < nloc; l += kBlock) {
+    for (int l = threadIdx.x; l < nloc; l += BS) {
+        const bool interior = l < nint;
+        const int a = ib + (interior ? l : 0);
+        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), th = v0;
+        unsigned mk = 0;
+        if (interior) {   // node constants first: their latency overlaps the LDS gather
+            v0 = A.nv4[a];
+            th = A.nth[a];
+            mk = A.mask[a];
+        }
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         const int k1 = lrow[l + 1];
         for (int k = lrow[l]; k < k1; ++k) {
             const float4 o = lout[lslot[k]];
             acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
         }
-        if (l < nint) {
-            const int a = ib + l;
-            NodeNew r = node_advance<CKT>(p, lnode[l], A.nv4[a], A.nth[a], A.mask[a], acc, src);
+        if (interior) {
+            NodeNew r = node_advance(p, lnode[l], v0, th, mk, acc, src);
             A.nu4[a] = r.u;
             A.nv4[a] = r.v;
             nf |= r.nonfinite;
             if (MON) node_monitor(p, r, A.Vl[a], mo);
         } else {
-            A.partial[sb + l - nint] = acc;
+            A.partial[A.ppos[sb + l - nint]] = acc;
         }
     }
     raise_flags(A.status, nf, inv);
     if (MON) {
-        double s = block_sum<kBlock>(double(psi), shd);
+        double s = block_sum<BS>(double(psi), shd);
         if (threadIdx.x == 0) A.part_elem[pid] = s;
-        write_node_partials<kBlock>(mo, A.part_node, shd, shf);
+        write_node_partials<BS>(mo, A.part_node, shd, shf);
     }
 }
 
-template <bool MON, bool CKT>
+template <bool MON>
 __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, NodeParams p, int j) {
     __shared__ double shd[kBlock / 64];
     __shared__ float shf[kBlock / 64];
@@ -485,14 +613,22 @@ __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, NodePa
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
     bool nf = false;
     if (s < A.n_shared) {
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int k1 = A.srow[s + 1];
-        for (int k = A.srow[s]; k < k1; ++k) {
-            const float4 o = A.partial[A.sidx[k]];
-            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
-        }
         const int a = A.n_interior + s;
-        NodeNew r = node_advance<CKT>(p, A.nu4[a], A.nv4[a], A.nth[a], A.mask[a], acc, src);
+        const float4 u0 = A.nu4[a], v0 = A.nv4[a], th = A.nth[a];   // independent of the partials
+        const unsigned mk = A.mask[a];
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int k0 = A.srow[s], k1 = A.srow[s + 1];
+        // partials in groups of four independent loads (fixed order within and across groups)
+        for (int k = k0; k < k1; k += 4) {
+            float4 o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = (k + q < k1) ? A.partial[k + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc.x += o[q].x; acc.y += o[q].y; acc.z += o[q].z; acc.w += o[q].w;
+            }
+        }
+        NodeNew r = node_advance(p, u0, v0, th, mk, acc, src);
         A.nu4[a] = r.u;
         A.nv4[a] = r.v;
         nf = r.nonfinite;
@@ -563,16 +699,23 @@ void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_
                            a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
 }
 
-template <int NPE, int NP>
-void launch_patch_np(bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
-                     size_t lds, hipStream_t s) {
+template <int NPE, int NP, int BS, bool GEOX>
+void launch_patch_g(bool mon, const PatchArgs &a, const KMat &m, const NodeParams &p, int j, size_t lds,
+                    hipStream_t s) {
     dim3 grid(a.n_patches);
-    if (mon) {
-        if (ckt) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, true>), grid, dim3(kBlock), lds, s, a, m, p, j);
-        else hipLaunchKernelGGL((patch_kernel<NPE, NP, true, false>), grid, dim3(kBlock), lds, s, a, m, p, j);
+    if (mon) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, BS, GEOX>), grid, dim3(BS), lds, s, a, m, p, j);
+    else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, BS, GEOX>), grid, dim3(BS), lds, s, a, m, p, j);
+}
+
+template <int NPE, int NP>
+void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
+                     size_t lds, hipStream_t s) {
+    if (NPE == 4 && bs == 512) {
+        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, m, p, j, lds, s);
+        else launch_patch_g<NPE, NP, 512, false>(mon, a, m, p, j, lds, s);
     } else {
-        if (ckt) hipLaunchKernelGGL((patch_kernel<NPE, NP, false, true>), grid, dim3(kBlock), lds, s, a, m, p, j);
-        else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, false>), grid, dim3(kBlock), lds, s, a, m, p, j);
+        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, m, p, j, lds, s);
+        else launch_patch_g<NPE, NP, 256, false>(mon, a, m, p, j, lds, s);
     }
 }
 }  // namespace
@@ -598,54 +741,42 @@ void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat 
     }
 }
 
-void launch_node(bool mon, bool ckt, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s) {
+void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s) {
     dim3 grid((a.nn + kBlock - 1) / kBlock);
-    if (mon) {
-        if (ckt) hipLaunchKernelGGL((node_kernel<true, true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
-                                    a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
-        else hipLaunchKernelGGL((node_kernel<true, false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
-                                a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
-    } else {
-        if (ckt) hipLaunchKernelGGL((node_kernel<false, true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
-                                    a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
-        else hipLaunchKernelGGL((node_kernel<false, false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4,
-                                a.nv4, a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
-    }
+    if (mon) hipLaunchKernelGGL((node_kernel<true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4,
+                                a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+    else hipLaunchKernelGGL((node_kernel<false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4,
+                            a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
 }
 
-void launch_patch(int npe, int np, bool mon, bool ckt, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
-                  hipStream_t s) {
-    const size_t lds = sizeof(float4) * (size_t(a.max_nodes) + size_t(a.max_elems) * npe);
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m,
+                  const NodeParams &p, int j, hipStream_t s) {
+    const size_t lds = patch_lds_bytes(npe, geox, a);
     if (npe == 4) {
         switch (np) {
-            case 0: launch_patch_np<4, 0>(mon, ckt, a, m, p, j, lds, s); break;
-            case 1: launch_patch_np<4, 1>(mon, ckt, a, m, p, j, lds, s); break;
-            case 2: launch_patch_np<4, 2>(mon, ckt, a, m, p, j, lds, s); break;
-            case 3: launch_patch_np<4, 3>(mon, ckt, a, m, p, j, lds, s); break;
-            default: launch_patch_np<4, 4>(mon, ckt, a, m, p, j, lds, s); break;
+            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, m, p, j, lds, s); break;
+            default: launch_patch_np<4, 4>(mon, geox, bs, a, m, p, j, lds, s); break;
         }
     } else {
         switch (np) {
-            case 0: launch_patch_np<8, 0>(mon, ckt, a, m, p, j, lds, s); break;
-            case 1: launch_patch_np<8, 1>(mon, ckt, a, m, p, j, lds, s); break;
-            case 2: launch_patch_np<8, 2>(mon, ckt, a, m, p, j, lds, s); break;
-            case 3: launch_patch_np<8, 3>(mon, ckt, a, m, p, j, lds, s); break;
-            default: launch_patch_np<8, 4>(mon, ckt, a, m, p, j, lds, s); break;
+            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, m, p, j, lds, s); break;
+            default: launch_patch_np<8, 4>(mon, geox, bs, a, m, p, j, lds, s); break;
         }
     }
 }
 
-void launch_shared_nodes(bool mon, bool ckt, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s) {
+void launch_shared_nodes(bool mon, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s) {
     const int nb = int((a.n_shared + kBlock - 1) / kBlock);
     if (nb == 0) return;
     dim3 grid(nb);
-    if (mon) {
-        if (ckt) hipLaunchKernelGGL((shared_node_kernel<true, true>), grid, dim3(kBlock), 0, s, a, p, j);
-        else hipLaunchKernelGGL((shared_node_kernel<true, false>), grid, dim3(kBlock), 0, s, a, p, j);
-    } else {
-        if (ckt) hipLaunchKernelGGL((shared_node_kernel<false, true>), grid, dim3(kBlock), 0, s, a, p, j);
-        else hipLaunchKernelGGL((shared_node_kernel<false, false>), grid, dim3(kBlock), 0, s, a, p, j);
-    }
+    if (mon) hipLaunchKernelGGL((shared_node_kernel<true>), grid, dim3(kBlock), 0, s, a, p, j);
+    else hipLaunchKernelGGL((shared_node_kernel<false>), grid, dim3(kBlock), 0, s, a, p, j);
 }
 
 void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,
@@ -654,8 +785,8 @@ void launch_finish(const double *part_elem, int n_elem_parts, const double *part
                        step_base, k, status, mon);
 }
 
-size_t patch_lds_bytes(int npe, const PatchArgs &a) {
-    return sizeof(float4) * (size_t(a.max_nodes) + size_t(a.max_elems) * npe);
+size_t patch_lds_bytes(int npe, bool geox, const PatchArgs &a) {
+    return sizeof(float4) * ((geox ? 2 : 1) * size_t(a.max_nodes) + size_t(a.max_elems) * npe);
 }
 
 }  // namespace tled

@@ -247,7 +247,7 @@ std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_
     return order;
 }
 
-void build_patches(Precomputed *pc, int patch_elems) {
+void build_patches(Precomputed *pc, int patch_elems, const std::vector<double> &Xc) {
     const int npe = pc->npe;
     const int64_t ne = pc->ne, nn = pc->nn;
     Patches &P = pc->patches;
@@ -320,8 +320,11 @@ void build_patches(Precomputed *pc, int patch_elems) {
     P.lslot_begin.assign(P.n + 1, 0);
     P.max_nodes = 0;
     P.max_elems = 0;
+    P.slot_stride = int32_t(std::min<int64_t>(patch_elems, ne));
     std::vector<int32_t> local(nn, -1);
     std::vector<std::vector<int32_t>> shared_parts(nn - P.n_interior);
+    P.lX.clear();
+    P.lx_begin.assign(P.n + 1, 0);
     for (int32_t p = 0; p < P.n; ++p) {
         const int32_t e0 = P.elem_begin[p], e1 = P.elem_begin[p + 1];
         const int32_t ib = P.int_begin[p], ie = P.int_begin[p + 1];
@@ -343,6 +346,19 @@ void build_patches(Precomputed *pc, int patch_elems) {
             }
         P.max_nodes = std::max(P.max_nodes, nloc);
         P.max_elems = std::max(P.max_elems, e1 - e0);
+        // local reference coordinates relative to the patch centroid (FP64, then rounded)
+        {
+            std::vector<int32_t> ids(nloc);
+            for (int32_t n = ib; n < ie; ++n) ids[n - ib] = n;
+            for (size_t k = 0; k < touched.size(); ++k) ids[nint + k] = touched[k];
+            double o[3] = {0, 0, 0};
+            for (int32_t n : ids)
+                for (int i = 0; i < 3; ++i) o[i] += Xc[3 * pc->node_new2old[n] + i];
+            for (int i = 0; i < 3; ++i) o[i] /= double(nloc);
+            P.lx_begin[p] = int32_t(P.lX.size() / 3);
+            for (int32_t n : ids)
+                for (int i = 0; i < 3; ++i) P.lX.push_back(float(Xc[3 * pc->node_new2old[n] + i] - o[i]));
+        }
         // local gather lists
         std::vector<int32_t> cnt(nloc + 1, 0);
         for (int32_t e = e0; e < e1; ++e)
@@ -355,7 +371,7 @@ void build_patches(Precomputed *pc, int patch_elems) {
         for (int32_t e = e0; e < e1; ++e)
             for (int a = 0; a < npe; ++a) {
                 int32_t l = P.lconn[size_t(npe) * e + a];
-                P.lslot[size_t(e0) * npe + fill[l]++] = uint16_t((e - e0) * npe + a);
+                P.lslot[size_t(e0) * npe + fill[l]++] = uint16_t(a * P.slot_stride + (e - e0));
             }
         for (int32_t n = ib; n < ie; ++n) local[n] = -1;
         for (int32_t n : touched) local[n] = -1;
@@ -364,13 +380,15 @@ void build_patches(Precomputed *pc, int patch_elems) {
     P.lrow_begin[P.n] = int32_t(P.lrow.size());
     P.lslot_begin[P.n] = int32_t(ne * npe);
     const int64_t nsh = nn - P.n_interior;
+    P.lx_begin[P.n] = int32_t(P.lX.size() / 3);
     P.srow.assign(nsh + 1, 0);
-    P.sidx.clear();
+    P.ppos.assign(P.shared_ids.size(), -1);
+    int32_t pos = 0;
     for (int64_t s = 0; s < nsh; ++s) {
-        P.srow[s] = int32_t(P.sidx.size());
-        for (int32_t k : shared_parts[s]) P.sidx.push_back(k);
+        P.srow[s] = pos;
+        for (int32_t k : shared_parts[s]) P.ppos[k] = pos++;   // shared_parts[s] is in patch order
     }
-    P.srow[nsh] = int32_t(P.sidx.size());
+    P.srow[nsh] = pos;
 }
 
 }  // namespace
@@ -479,7 +497,7 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
         if (!p.Tfix.empty()) pc.Tfix[a] = p.Tfix[o];
     }
 
-    if (opt.build_patches) build_patches(&pc, std::max(8, std::min(opt.patch_elems, 65536 / npe)));
+    if (opt.build_patches) build_patches(&pc, std::max(8, std::min(opt.patch_elems, 65536 / npe)), p.X);
 
     // node -> element-slot incidence (ascending slot order)
     pc.rowptr.assign(nn + 1, 0);

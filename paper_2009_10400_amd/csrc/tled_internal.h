@@ -45,14 +45,20 @@ struct Patches {
     // slots (e_local * npe + s) are lslot[lrow[off+l] .. lrow[off+l+1]).
     std::vector<int32_t> lrow_begin;       // n + 1 offsets into lrow (each patch has nloc+1 entries)
     std::vector<uint16_t> lrow;            // row pointers, local to the patch slot list
-    std::vector<uint16_t> lslot;           // ne * npe entries, sorted per local node
+    std::vector<uint16_t> lslot;           // ne * npe entries (slot s * slot_stride + e_local), sorted per local node
+    int32_t slot_stride = 0;               // element stride of the slot-major LDS output array
     std::vector<int32_t> lslot_begin;      // n + 1 offsets into lslot (= elem_begin * npe)
-    // shared-node assembly: partial of (patch p, local shared index j) lives at
-    // partial slot shared_begin[p] + j; node n_int + s sums the partial slots
-    // srow[s] .. srow[s+1] listed in sidx.
+    // shared-node assembly: the partial of (patch p, local shared index j) is
+    // written to partial slot ppos[shared_begin[p] + j]; slots are sorted by
+    // node, then patch, so node n_interior + s sums the contiguous slots
+    // srow[s] .. srow[s+1].
     int64_t n_interior = 0;                // nodes [0, n_interior) are interior
     std::vector<int32_t> srow;             // n_shared + 1
-    std::vector<int32_t> sidx;             // shared_ids.size()
+    std::vector<int32_t> ppos;             // shared_ids.size()
+    // reference coordinates of every local node of every patch, relative to
+    // the patch centroid (x, y, z per local node; patch p starts at lx_begin[p])
+    std::vector<float> lX;
+    std::vector<int32_t> lx_begin;         // n + 1
 };
 
 // Precomputed quantities in the internal (reordered) numbering, FP64.

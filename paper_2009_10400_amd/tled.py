@@ -18,6 +18,27 @@ LIB_PATH = os.path.join(_HERE, "csrc", "libtled.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_10400_amd.build`")
 
+
+def _share_torch_hip_runtime():
+    """Bind the library to PyTorch's bundled HIP runtime when PyTorch is installed.
+
+    PyTorch ships its own ``libamdhip64`` (same soname as the system one).  If the
+    system copy were loaded first, importing torch later would bring a second HIP
+    runtime into the process and torch would find no device.  Loading torch's copy
+    (by path, without importing torch) before the library keeps one runtime.
+    """
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        return
+    for base in spec.submodule_search_locations:
+        path = os.path.join(base, "lib", "libamdhip64.so")
+        if os.path.exists(path):
+            ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+            return
+
+
+_share_torch_hip_runtime()
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_ARG, E_MESH, E_STATE, E_HIP, E_OOM, E_UNSTABLE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -59,7 +80,8 @@ class Monitors(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("n_nodes", _i64), ("n_elems", _i64), ("elem_type", _i32), ("n_prony", _i32),
                 ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
-                ("n_shared_nodes", _i64), ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d)]
+                ("n_shared_nodes", _i64), ("patch_max_nodes", _i32), ("patch_lds_bytes", _i32),
+                ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

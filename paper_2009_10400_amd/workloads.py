@@ -321,6 +321,27 @@ def ellipsoid_t4(target_elems: int = 1_000_000, semi=(0.1, 0.075, 0.05), seed_sh
                    gamma=80.0, nsteps=steps, h=h, meta=dict(target=target_elems, grid=n))
 
 
+def spheres_t4(n: int = 16, L: float = 0.06, steps: int = 1000, centres=None) -> Problem:
+    """Three touching spherical heat sources of diameter 0.01 m with the uniform Q_r of Table 5
+    (9 705 360 W/m^3) in a Kuhn-split cube with the Table 5 liver material (T-dependent c, k;
+    metabolic heat; perfusion; eta = 2 mu; one Prony term); bottom face fixed.  The paper's own
+    liver geometry is not available; the cube stands in for it."""
+    X, conn, h = box_mesh("t4", n, L)
+    P = centroids(X, conn)
+    if centres is None:
+        c = L / 2.0
+        centres = [(c - 0.01, c, c), (c, c, c), (c + 0.01, c, c)]   # diameters touch
+    q = np.zeros(len(conn))
+    for ctr in centres:
+        inside = ((P - np.asarray(ctr)) ** 2).sum(1) <= 0.005 ** 2
+        q[inside] = 9705360.0
+    params = paper_table5_material()
+    fix = np.where(np.isclose(X[:, 2], 0.0), 7, 0).astype(np.uint8)
+    a0 = np.tile(np.array([1.0, 0.0, 0.0]), (len(conn), 1))
+    return Problem("spheres_t4", 4, X, conn, params, a0=a0, q=q, fix=fix, gamma=80.0, nsteps=steps, h=h,
+                   meta=dict(n=n, L=L))
+
+
 def random_state(problem: Problem, seed: int, u_scale: float, dT_scale: float):
     """A smooth-ish random state (u, u_prev, T) for single-step checks."""
     rng = np.random.default_rng(seed)
