@@ -54,6 +54,11 @@ def parse():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", type=int, default=0, metavar="N",
+                    help="instead of the headline run: batched planning sweep of N scenarios (one JSON line)")
+    ap.add_argument("--duration-scale", type=float, default=1e-3,
+                    help="sweep heating durations are U(30, 300) s times this factor")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches) to calibrate HBM counters")
     return ap.parse_args()
@@ -102,6 +107,62 @@ def cpu_baseline(problem, dt, steps):
             "sample": f"{steps} steps of the full {problem.ne}-tet workload, serial FP64 oracle ({el:.1f} s)"}
 
 
+def sweep(args):
+    """Batched planning sweep: N scenarios (5k-200k tets, log-uniform) in one batch, every scenario run
+    to the end of its heating; reports scenarios/s and element-updates/s of the batch."""
+    import torch
+    from paper_2009_10400_amd import autotune, tled, workloads as W
+
+    t = time.time()
+    sc = W.planning_scenarios(args.sweep, seed=3, duration_scale=args.duration_scale)
+    probs = [p for p, _ in sc]
+    dts, steps = [], []
+    for p, dur in sc:
+        h = tled.from_problem(p, device=-1, finalize=False)
+        dt = p.cfl * h.critical_dt()
+        h.close()
+        dts.append(dt)
+        steps.append(max(1, int(round(dur / dt))))
+    ne_tot = sum(p.ne for p in probs)
+    log(f"[sweep] {len(sc)} scenarios, {ne_tot} elements, steps {min(steps)}..{max(steps)}, "
+        f"built in {time.time() - t:.1f}s")
+    stream = torch.cuda.Stream(device=0)
+    choice, report = {}, {}
+    if not args.no_autotune:
+        t = time.time()
+        choice, report = autotune.tune(probs, dts, stream=stream.cuda_stream, log=log)
+        log(f"[sweep] autotune {time.time() - t:.1f}s -> {choice}")
+    b = tled.Batch(0, stream=stream.cuda_stream)
+    b.set_options(graph_steps=args.graph_steps)
+    for p, dt, n in zip(probs, dts, steps):
+        b.add(p, dt, n, patch_elems=choice.get(autotune.bucket_of(p.ne), 0))
+    t = time.time()
+    b.finalize()
+    log(f"[sweep] finalize {time.time() - t:.1f}s info={b.batch_info()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    b.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    updates = sum(p.ne * n for p, n in zip(probs, steps))
+    tmax, vol = b.scenario_monitors(333.15)
+    out = {
+        "metric": "scenarios/s (batched planning sweep, solver)", "value": len(sc) / el, "unit": "scenarios/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "element_updates_per_s": updates / el, "seconds": el, "batch_steps": max(steps),
+        "config": {"workload": f"{len(sc)} scenarios, tet cubes and noisy ellipsoids of 5k-200k elements "
+                               f"(log-uniform, {ne_tot} total), probe 1/r^2 source U(20,80) W, E U(2,6) kPa, "
+                               f"heating U(30,300) s x {args.duration_scale:g}",
+                   "duration_scale": args.duration_scale, "autotune": {str(k): v for k, v in choice.items()},
+                   "graph_steps": args.graph_steps},
+        "autotune_report": {str(k): v for k, v in report.items()},
+        "ablated_volume_m3": {"min": float(vol.min()), "max": float(vol.max())},
+        "T_max_K": {"min": float(tmax.min()), "max": float(tmax.max())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -110,6 +171,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.sweep:
+        sweep(args)
         return
     import torch
     from paper_2009_10400_amd import tled, workloads as W

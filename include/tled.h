@@ -226,6 +226,51 @@ tled_status tled_set_state(tled_sim *sim, const void *buf);
  * node) kernel, ms[2] monitor reduction.  Advances the state like tled_step. */
 tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]);
 
+/* --- batched scenarios (planning sweeps) ----------------------------------
+ * Many independent problems of one element type and one Prony term count run
+ * together: every step of the fused kernels advances all of them, each with its
+ * own mesh, material, fibres, source, fixed dofs, dt and damping; a scenario
+ * stops after its own n_steps and holds its state while the others go on.
+ * A batch handle is created by tled_batch_create and destroyed by
+ * tled_batch_destroy; tled_set_stream, tled_set_options, tled_step, tled_sync,
+ * tled_get_monitors (sums and extrema over all scenarios), tled_get_state,
+ * tled_set_state, tled_kernel_times, tled_get_info and tled_last_error accept
+ * it; the single-problem set-up and read calls refuse it (TLED_E_STATE). */
+typedef struct tled_sim tled_batch;
+
+typedef struct {
+    int32_t n_scenarios;
+    int32_t n_patches;
+    int64_t n_elems, n_nodes;
+    int64_t n_shared_nodes;
+    int64_t max_steps;       /* largest n_steps of the scenarios */
+    int64_t step;            /* batch steps taken                */
+    int64_t device_bytes;
+    int32_t kernel_variant;
+    int32_t reserved;
+} tled_batch_info;
+
+tled_status tled_batch_create(tled_batch **out, int device);
+void        tled_batch_destroy(tled_batch *b);
+/* Add one scenario (arguments as in the single-problem set-up calls; arrays are
+ * copied).  n_fixed nodes fixed_nodes[i] with component mask fixed_mask[i];
+ * patch_elems 0 = default.  *index receives the scenario number. */
+tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const double *X, int64_t n_elems,
+                           const int32_t *conn, const tled_material *m, const double *a0, const double *q_elem,
+                           double t_on, double t_off, int64_t n_fixed, const int32_t *fixed_nodes,
+                           const uint8_t *fixed_mask, double dt, double damping_gamma, int64_t n_steps,
+                           int32_t patch_elems, int32_t *index);
+tled_status tled_batch_finalize(tled_batch *b);
+/* Enqueue steps until every scenario has reached its n_steps (asynchronous). */
+tled_status tled_batch_run(tled_batch *b);
+/* Displacement (n_nodes x 3) and temperature (n_nodes, K) of one scenario in its
+ * caller numbering; either pointer may be NULL. */
+tled_status tled_batch_read(tled_batch *b, int32_t scenario, double *u, double *T);
+/* Per scenario: maximum nodal temperature and lumped volume of the nodes at or
+ * above ablation_T (e.g. 333.15 K, the 60 C isotherm). */
+tled_status tled_batch_monitors(tled_batch *b, double ablation_T, double *T_max, double *ablated_volume);
+tled_status tled_batch_get_info(tled_batch *b, tled_batch_info *out);
+
 const char *tled_status_string(tled_status s);
 const char *tled_last_error(const tled_sim *sim);
 

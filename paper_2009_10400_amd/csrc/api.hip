@@ -58,6 +58,19 @@ struct tled_sim {
     int64_t step = 0;
     std::vector<float> B;   // per-node velocity coefficient (kept for state writes)
     size_t theta_floats = 0;
+    // scenarios: a single problem is a batch of one
+    bool is_batch = false;
+    std::vector<HostProblem> scen;
+    std::vector<int64_t> scen_steps;
+    std::vector<int32_t> scen_pe;
+    std::vector<ScenRange> ranges;
+    std::vector<int32_t> patch_scen, shared_scen;
+    std::vector<KMat> scen_km;
+    std::vector<NodeParams> scen_np;
+    KMat *d_km = nullptr;
+    NodeParams *d_np = nullptr;
+    long long *d_ranges = nullptr;
+    double *d_scen_mon = nullptr;
 };
 
 namespace {
@@ -150,11 +163,8 @@ long long first_step_at(double t, double dt) {
     return n;
 }
 
-void build_kernel_constants(tled_sim *s) {
-    const tled_material &m = s->prob.mat;
-    const double dt = s->prob.dt, g = s->prob.gamma;
-    KMat &k = s->km;
-    k = KMat{};
+KMat make_kmat(const tled_material &m, double dt) {
+    KMat k{};
     k.mu = float(m.mu); k.kappa = float(m.kappa); k.eta = float(m.eta);
     k.alpha = float(m.alpha); k.alpha_m = float(m.alpha_m); k.T0 = float(m.T0);
     k.k = float(m.k); k.k_m = float(m.k_m);
@@ -174,27 +184,44 @@ void build_kernel_constants(tled_sim *s) {
     k.n_prony = m.n_prony;
     k.expan_mode = m.expan_mode; k.cond_mode = m.cond_mode; k.muT_on = m.muT_on;
     k.shrink_on = m.shrink_on; k.ckT_on = m.ckT_on;
-    NodeParams &p = s->nparams;
+    return k;
+}
+
+NodeParams make_nparams(const HostProblem &pr, const KMat &k, double abl_T) {
+    const tled_material &m = pr.mat;
+    const double dt = pr.dt, g = pr.gamma;
+    NodeParams p{};
     p.A = float((1.0 - 0.5 * g * dt) / (1.0 + 0.5 * g * dt));
     p.dt = float(dt);
     p.T0 = float(m.T0);
     p.rho = float(m.rho);
-    p.abl_T = float(s->opt.ablation_T > 0 ? s->opt.ablation_T : 333.15);
+    p.abl_T = float(abl_T);
     p.ck_lo = k.ck_lo; p.ck_inv = k.ck_inv; p.c_lo = k.c_lo; p.c_hi = k.c_hi;
     p.ckT_on = m.ckT_on;
-    p.n_on = first_step_at(s->prob.t_on, dt);
-    p.n_off = first_step_at(s->prob.t_off, dt);
+    p.n_on = first_step_at(pr.t_on, dt);
+    p.n_off = first_step_at(pr.t_off, dt);
+    return p;
+}
+
+void build_kernel_constants(tled_sim *s) {
+    const double abl = s->opt.ablation_T > 0 ? s->opt.ablation_T : 333.15;
+    s->scen_km.clear();
+    s->scen_np.clear();
+    for (const HostProblem &pr : s->scen) {
+        s->scen_km.push_back(make_kmat(pr.mat, pr.dt));
+        s->scen_np.push_back(make_nparams(pr, s->scen_km.back(), abl));
+    }
+    s->km = s->scen_km[0];
+    s->nparams = s->scen_np[0];
 }
 
 // Single-precision device layout of the precomputed data, then upload.
 tled_status upload_all(tled_sim *s) {
     const Precomputed &pc = s->pc;
-    const tled_material &m = s->prob.mat;
     const int npe = pc.npe;
     const int64_t ne = pc.ne, nn = pc.nn;
-    const double dt = s->prob.dt, g = s->prob.gamma;
     if (nn > INT_MAX / 2 || ne * npe > INT_MAX) return fail(s, TLED_E_ARG, "mesh too large for 32-bit indices");
-    s->np = m.n_prony;
+    s->np = s->scen[0].mat.n_prony;
 
     // element planes
     std::vector<float4> g0(ne), g1(ne), g2(ne), h0, h1, h2;
@@ -221,13 +248,20 @@ tled_status upload_all(tled_sim *s) {
             khg[e] = float(pc.khg[e]);
         }
     }
-    // node arrays
+    // node arrays (each node with the constants of its scenario)
+    std::vector<int32_t> node_scen(nn, 0);
+    for (size_t k = 0; k < s->ranges.size(); ++k) {
+        for (int64_t a = s->ranges[k].int_lo; a < s->ranges[k].int_hi; ++a) node_scen[a] = int32_t(k);
+        for (int64_t a = s->ranges[k].sh_lo; a < s->ranges[k].sh_hi; ++a) node_scen[a] = int32_t(k);
+    }
     std::vector<float4> nu4(nn), nv4(nn), nth(nn);
     std::vector<float> Vl(nn);
     std::vector<uint8_t> mask(nn);
     s->B.assign(nn, 0.f);
-    const double half = 1.0 + 0.5 * g * dt;
     for (int64_t a = 0; a < nn; ++a) {
+        const HostProblem &pr = s->scen[node_scen[a]];
+        const tled_material &m = pr.mat;
+        const double dt = pr.dt, half = 1.0 + 0.5 * pr.gamma * pr.dt;
         const uint8_t mk = pc.fix[a];
         mask[a] = mk;
         Vl[a] = float(pc.Vl[a]);
@@ -334,9 +368,41 @@ tled_status upload_all(tled_sim *s) {
         TRY(zeros(s, &s->d_part_node, size_t(4) * s->n_node_parts));
         a.part_elem = s->d_part_elem;
         a.part_node = s->d_part_node;
+        // scenario tables
+        const size_t S = s->scen.size();
+        std::vector<long long> end(S), rng(4 * S);
+        for (size_t k = 0; k < S; ++k) {
+            end[k] = s->scen_steps[k];
+            rng[4 * k] = s->ranges[k].int_lo; rng[4 * k + 1] = s->ranges[k].int_hi;
+            rng[4 * k + 2] = s->ranges[k].sh_lo; rng[4 * k + 3] = s->ranges[k].sh_hi;
+        }
+        TRY(upload(s, &s->d_km, s->scen_km)); a.km = s->d_km;
+        TRY(upload(s, &s->d_np, s->scen_np)); a.np = s->d_np;
+        TRY(upload(s, &d, s->patch_scen)); a.patch_scen = d;
+        std::vector<int32_t> shs = s->shared_scen;
+        if (shs.empty()) shs.push_back(0);
+        TRY(upload(s, &d, shs)); a.shared_scen = d;
+        long long *dl;
+        TRY(upload(s, &dl, end)); a.scen_end = dl;
+        TRY(upload(s, &s->d_ranges, rng));
+        TRY(zeros(s, &s->d_scen_mon, 2 * S));
     }
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return TLED_OK;
+}
+
+// Scenario tables for a single problem: one scenario covering everything, never ending.
+void single_scenario(tled_sim *s) {
+    s->scen.assign(1, s->prob);
+    s->scen_steps.assign(1, LLONG_MAX);
+    ScenRange r;
+    r.elem_lo = 0; r.elem_hi = s->pc.ne;
+    const int64_t nint = s->variant >= 2 ? s->pc.patches.n_interior : s->pc.nn;
+    r.int_lo = 0; r.int_hi = nint; r.sh_lo = nint; r.sh_hi = s->pc.nn;
+    r.patch_lo = 0; r.patch_hi = s->pc.patches.n;
+    s->ranges.assign(1, r);
+    s->patch_scen.assign(std::max(s->pc.patches.n, 1), 0);
+    s->shared_scen.assign(std::max<int64_t>(s->pc.nn - nint, 1), 0);
 }
 
 // Enqueue a chunk of k steps (eager, or under stream capture).
@@ -347,10 +413,10 @@ tled_status enqueue_chunk(tled_sim *s, int k, double *ms = nullptr, std::vector<
         const bool mon = (j == k - 1);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j], s->stream));
         if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream);
-        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->pa, s->km, s->nparams, j, s->stream);
+        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->pa, j, s->stream);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 1], s->stream));
         if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream);
-        else launch_shared_nodes(mon, s->pa, s->nparams, j, s->stream);
+        else launch_shared_nodes(mon, s->pa, j, s->stream);
         if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 2], s->stream));
     }
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,
@@ -401,9 +467,21 @@ tled_status need_device(tled_sim *s) {
     return TLED_OK;
 }
 
+tled_status need_single(tled_sim *s) {
+    TRY(need_device(s));
+    if (s->is_batch) return fail(s, TLED_E_STATE, "batch handle: use the tled_batch_* reads");
+    return TLED_OK;
+}
+
 tled_status need_setup(tled_sim *s) {
     if (!s) return TLED_E_ARG;
     if (s->finalized) return fail(s, TLED_E_STATE, "problem already finalized");
+    return TLED_OK;
+}
+
+tled_status need_single_setup(tled_sim *s) {
+    TRY(need_setup(s));
+    if (s->is_batch) return fail(s, TLED_E_STATE, "batch handle: use tled_batch_add");
     return TLED_OK;
 }
 
@@ -497,13 +575,22 @@ tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
         (void)hipGraphExecDestroy(sim->graph);
         sim->graph = nullptr;
     }
-    if (sim->finalized) build_kernel_constants(sim);
+    if (sim->finalized) {
+        build_kernel_constants(sim);
+        if (sim->device >= 0 && sim->d_km) {
+            HIPCHK(sim, hipMemcpyAsync(sim->d_km, sim->scen_km.data(), sizeof(KMat) * sim->scen_km.size(),
+                                       hipMemcpyHostToDevice, sim->stream));
+            HIPCHK(sim, hipMemcpyAsync(sim->d_np, sim->scen_np.data(), sizeof(NodeParams) * sim->scen_np.size(),
+                                       hipMemcpyHostToDevice, sim->stream));
+            HIPCHK(sim, hipStreamSynchronize(sim->stream));
+        }
+    }
     return TLED_OK;
 }
 
 tled_status tled_set_mesh(tled_sim *sim, int elem_type, int64_t n_nodes, const double *X, int64_t n_elems,
                           const int32_t *conn) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (elem_type != TLED_T4 && elem_type != TLED_H8) return fail(sim, TLED_E_ARG, "elem_type must be 4 or 8");
     if (n_nodes <= 0 || n_elems <= 0 || !X || !conn) return fail(sim, TLED_E_ARG, "empty mesh or null array");
     if (n_nodes > (int64_t(1) << 30) || n_elems * elem_type > INT_MAX)
@@ -525,7 +612,7 @@ tled_status tled_set_mesh(tled_sim *sim, int elem_type, int64_t n_nodes, const d
 }
 
 tled_status tled_set_material(tled_sim *sim, const tled_material *m) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!m) return fail(sim, TLED_E_ARG, "null material");
     sim->prob.mat = *m;
     sim->prob.have_mat = true;
@@ -533,7 +620,7 @@ tled_status tled_set_material(tled_sim *sim, const tled_material *m) {
 }
 
 tled_status tled_set_fibres(tled_sim *sim, const double *a0) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
     if (!a0) { sim->prob.a0.clear(); return TLED_OK; }
     sim->prob.a0.assign(a0, a0 + 3 * sim->prob.ne);
@@ -541,7 +628,7 @@ tled_status tled_set_fibres(tled_sim *sim, const double *a0) {
 }
 
 tled_status tled_set_fixed_dofs(tled_sim *sim, int64_t n, const int32_t *node, const uint8_t *mask) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
     if (n < 0 || (n > 0 && (!node || !mask))) return fail(sim, TLED_E_ARG, "bad fixed-dof arrays");
     for (int64_t i = 0; i < n; ++i) {
@@ -552,7 +639,7 @@ tled_status tled_set_fixed_dofs(tled_sim *sim, int64_t n, const int32_t *node, c
 }
 
 tled_status tled_set_fixed_temperature(tled_sim *sim, int64_t n, const int32_t *node, const double *T) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
     if (n < 0 || (n > 0 && (!node || !T))) return fail(sim, TLED_E_ARG, "bad fixed-temperature arrays");
     for (int64_t i = 0; i < n; ++i) {
@@ -565,7 +652,7 @@ tled_status tled_set_fixed_temperature(tled_sim *sim, int64_t n, const int32_t *
 }
 
 tled_status tled_set_heat_source(tled_sim *sim, const double *q_elem, double t_on, double t_off) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
     if (std::isnan(t_on) || std::isnan(t_off)) return fail(sim, TLED_E_ARG, "NaN source window");
     if (q_elem) {
@@ -581,7 +668,7 @@ tled_status tled_set_heat_source(tled_sim *sim, const double *q_elem, double t_o
 }
 
 tled_status tled_set_time(tled_sim *sim, double dt, double damping_gamma) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!(dt > 0.0) || !std::isfinite(dt) || !(damping_gamma >= 0.0) || !std::isfinite(damping_gamma))
         return fail(sim, TLED_E_ARG, "dt must be > 0 and gamma >= 0");
     if (0.5 * damping_gamma * dt >= 1.0) return fail(sim, TLED_E_ARG, "gamma * dt / 2 must stay below 1");
@@ -601,7 +688,7 @@ tled_status tled_critical_dt(tled_sim *sim, double *dt_cr) {
 }
 
 tled_status tled_finalize(tled_sim *sim) {
-    TRY(need_setup(sim));
+    TRY(need_single_setup(sim));
     if (!sim->prob.have_time) return fail(sim, TLED_E_STATE, "call tled_set_time first");
     int v = sim->opt.kernel_variant == 0 ? 2 : sim->opt.kernel_variant;
     SetupOptions so;
@@ -624,6 +711,7 @@ tled_status tled_finalize(tled_sim *sim) {
         if (patch_lds_bytes(sim->prob.npe, v == 2, probe) > 65536 - 1024)
             return fail(sim, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
     }
+    single_scenario(sim);
     build_kernel_constants(sim);
     if (sim->device >= 0) {
         HIPCHK(sim, hipSetDevice(sim->device));
@@ -674,7 +762,7 @@ tled_status tled_sync(tled_sim *sim) {
 }
 
 tled_status tled_read_u(tled_sim *sim, double *u) {
-    TRY(need_device(sim));
+    TRY(need_single(sim));
     if (!u) return fail(sim, TLED_E_ARG, "null output");
     const int64_t nn = sim->pc.nn;
     std::vector<float4> h(nn);
@@ -688,19 +776,19 @@ tled_status tled_read_u(tled_sim *sim, double *u) {
 }
 
 tled_status tled_read_T(tled_sim *sim, double *T) {
-    TRY(need_device(sim));
+    TRY(need_single(sim));
     if (!T) return fail(sim, TLED_E_ARG, "null output");
     const int64_t nn = sim->pc.nn;
     std::vector<float4> h(nn);
     HIPCHK(sim, hipMemcpyAsync(h.data(), sim->tp.nu4, sizeof(float4) * nn, hipMemcpyDeviceToHost, sim->stream));
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
-    const float T0 = float(sim->prob.mat.T0);
-    for (int64_t a = 0; a < nn; ++a) T[sim->pc.node_new2old[a]] = double(T0) + double(h[a].w);
+    const double T0 = sim->prob.mat.T0;
+    for (int64_t a = 0; a < nn; ++a) T[sim->pc.node_new2old[a]] = T0 + double(h[a].w);
     return check_status(sim);
 }
 
 tled_status tled_copy_fields_device(tled_sim *sim, float *u_dst, float *T_dst) {
-    TRY(need_device(sim));
+    TRY(need_single(sim));
     launch_export_fields(sim->tp.nu4, sim->d_new2old, int(sim->pc.nn), float(sim->prob.mat.T0), u_dst, T_dst,
                          sim->stream);
     HIPCHK(sim, hipGetLastError());
@@ -754,6 +842,7 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
 
 tled_status tled_get_lumped(tled_sim *sim, double *Vl, double *M, double *C, double *Kb, double *Qm, double *Qr) {
     if (!sim) return TLED_E_ARG;
+    if (sim->is_batch) return fail(sim, TLED_E_STATE, "not available on a batch handle");
     if (!sim->finalized) return fail(sim, TLED_E_STATE, "call tled_finalize first");
     const Precomputed &pc = sim->pc;
     for (int64_t a = 0; a < pc.nn; ++a) {
@@ -769,7 +858,7 @@ tled_status tled_get_lumped(tled_sim *sim, double *Vl, double *M, double *C, dou
 }
 
 tled_status tled_read_state(tled_sim *sim, double *u, double *v, double *T, double *theta, int64_t *step) {
-    TRY(need_device(sim));
+    TRY(need_single(sim));
     const int64_t nn = sim->pc.nn, ne = sim->pc.ne;
     std::vector<float4> hu(nn), hv(nn);
     std::vector<float> ht(sim->theta_floats);
@@ -800,7 +889,7 @@ tled_status tled_read_state(tled_sim *sim, double *u, double *v, double *T, doub
 
 tled_status tled_write_state(tled_sim *sim, const double *u, const double *v, const double *T, const double *theta,
                              int64_t step) {
-    TRY(need_device(sim));
+    TRY(need_single(sim));
     if (step < 0) return fail(sim, TLED_E_ARG, "negative step");
     const int64_t nn = sim->pc.nn, ne = sim->pc.ne;
     std::vector<float4> hu(nn), hv(nn);
@@ -894,6 +983,165 @@ tled_status tled_set_state(tled_sim *sim, const void *buf) {
     HIPCHK(sim, hipMemcpyAsync(sim->d_status, &status, sizeof(status), hipMemcpyHostToDevice, sim->stream));
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
     sim->step = st;
+    return TLED_OK;
+}
+
+// ------------------------------------------------------------------ batched scenarios
+
+tled_status tled_batch_create(tled_batch **out, int device) {
+    TRY(tled_create(out, device));
+    (*out)->is_batch = true;
+    return TLED_OK;
+}
+
+void tled_batch_destroy(tled_batch *b) { tled_destroy(b); }
+
+tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const double *X, int64_t n_elems,
+                           const int32_t *conn, const tled_material *m, const double *a0, const double *q_elem,
+                           double t_on, double t_off, int64_t n_fixed, const int32_t *fixed_nodes,
+                           const uint8_t *fixed_mask, double dt, double damping_gamma, int64_t n_steps,
+                           int32_t patch_elems, int32_t *index) {
+    TRY(need_setup(b));
+    if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
+    if (elem_type != TLED_T4 && elem_type != TLED_H8) return fail(b, TLED_E_ARG, "elem_type must be 4 or 8");
+    if (n_nodes <= 0 || n_elems <= 0 || !X || !conn || !m) return fail(b, TLED_E_ARG, "empty mesh or null array");
+    if (n_nodes > (int64_t(1) << 30) || n_elems * elem_type > INT_MAX) return fail(b, TLED_E_ARG, "mesh too large");
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(damping_gamma >= 0.0) || 0.5 * damping_gamma * dt >= 1.0)
+        return fail(b, TLED_E_ARG, "dt must be > 0, gamma >= 0, gamma dt / 2 < 1");
+    if (n_steps < 0) return fail(b, TLED_E_ARG, "negative step count");
+    if (patch_elems < 0 || patch_elems > 4096) return fail(b, TLED_E_ARG, "patch_elems out of range");
+    if (std::isnan(t_on) || std::isnan(t_off)) return fail(b, TLED_E_ARG, "NaN source window");
+    if (!b->scen.empty() && b->scen[0].npe != elem_type) return fail(b, TLED_E_ARG, "a batch needs one element type");
+    if (!b->scen.empty() && b->scen[0].mat.n_prony != m->n_prony)
+        return fail(b, TLED_E_ARG, "a batch needs one Prony term count");
+    HostProblem p;
+    p.npe = elem_type; p.nn = n_nodes; p.ne = n_elems;
+    p.X.assign(X, X + 3 * n_nodes);
+    for (double v : p.X)
+        if (!std::isfinite(v)) return fail(b, TLED_E_ARG, "non-finite coordinate");
+    p.conn.assign(conn, conn + elem_type * n_elems);
+    if (a0) p.a0.assign(a0, a0 + 3 * n_elems);
+    if (q_elem) p.q.assign(q_elem, q_elem + n_elems);
+    for (double v : p.q)
+        if (!std::isfinite(v)) return fail(b, TLED_E_ARG, "non-finite source");
+    p.fix.assign(n_nodes, 0);
+    p.Tfix.assign(n_nodes, 0.0);
+    if (n_fixed < 0 || (n_fixed > 0 && (!fixed_nodes || !fixed_mask))) return fail(b, TLED_E_ARG, "bad fixed dofs");
+    for (int64_t i = 0; i < n_fixed; ++i) {
+        if (fixed_nodes[i] < 0 || fixed_nodes[i] >= n_nodes) return fail(b, TLED_E_ARG, "fixed node out of range");
+        p.fix[fixed_nodes[i]] |= uint8_t(fixed_mask[i] & 7);
+    }
+    p.t_on = t_on; p.t_off = t_off; p.dt = dt; p.gamma = damping_gamma; p.mat = *m;
+    p.have_mesh = p.have_mat = p.have_time = true;
+    b->scen.push_back(std::move(p));
+    b->scen_steps.push_back(n_steps);
+    b->scen_pe.push_back(patch_elems);
+    if (index) *index = int32_t(b->scen.size() - 1);
+    return TLED_OK;
+}
+
+tled_status tled_batch_finalize(tled_batch *b) {
+    TRY(need_setup(b));
+    if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
+    if (b->scen.empty()) return fail(b, TLED_E_STATE, "no scenario added");
+    const int v = b->opt.kernel_variant == 0 ? 2 : b->opt.kernel_variant;
+    if (v == 1) return fail(b, TLED_E_UNSUPPORTED, "batches run on the fused kernels (variant 2 or 3)");
+    if (b->opt.block_size == 512 && b->scen[0].npe == 8)
+        return fail(b, TLED_E_UNSUPPORTED, "block_size 512 is for T4 meshes only");
+    std::vector<int> pe(b->scen.size());
+    for (size_t k = 0; k < pe.size(); ++k)
+        pe[k] = b->scen_pe[k] > 0 ? b->scen_pe[k]
+                                  : (b->opt.patch_elems > 0 ? b->opt.patch_elems : (b->scen[k].npe == 4 ? 448 : 256));
+    tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, &b->pc, &b->ranges, &b->patch_scen,
+                                      &b->shared_scen, &b->err);
+    if (st != TLED_OK) return st;
+    for (size_t k = 0; k < b->scen.size(); ++k)
+        if (b->scen[k].dt > b->ranges[k].dt_cr)
+            return fail(b, TLED_E_ARG, "scenario " + std::to_string(k) + ": dt exceeds the critical step " +
+                                           std::to_string(b->ranges[k].dt_cr));
+    PatchArgs probe{};
+    probe.max_nodes = b->pc.patches.max_nodes;
+    probe.max_elems = b->pc.patches.slot_stride;
+    if (patch_lds_bytes(b->scen[0].npe, v == 2, probe) > 65536 - 1024)
+        return fail(b, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
+    b->variant = v;
+    b->prob = b->scen[0];
+    b->prob.nn = b->pc.nn;
+    b->prob.ne = b->pc.ne;
+    build_kernel_constants(b);
+    if (b->device >= 0) {
+        HIPCHK(b, hipSetDevice(b->device));
+        if (!b->stream) {
+            HIPCHK(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        st = upload_all(b);
+        if (st != TLED_OK) {
+            free_device(b);
+            return st;
+        }
+    }
+    b->step = 0;
+    b->finalized = true;
+    return TLED_OK;
+}
+
+tled_status tled_batch_run(tled_batch *b) {
+    TRY(need_device(b));
+    int64_t mx = 0;
+    for (auto n : b->scen_steps) mx = std::max(mx, n);
+    return mx > b->step ? tled_step(b, mx - b->step) : TLED_OK;
+}
+
+tled_status tled_batch_read(tled_batch *b, int32_t scenario, double *u, double *T) {
+    TRY(need_device(b));
+    if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
+    if (scenario < 0 || size_t(scenario) >= b->scen.size()) return fail(b, TLED_E_ARG, "scenario out of range");
+    const int64_t nn = b->pc.nn;
+    std::vector<float4> h(nn);
+    HIPCHK(b, hipMemcpyAsync(h.data(), b->tp.nu4, sizeof(float4) * nn, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    const ScenRange &R = b->ranges[scenario];
+    const double T0 = b->scen[scenario].mat.T0;
+    for (size_t i = 0; i < R.node_of.size(); ++i) {
+        const float4 v = h[R.node_of[i]];
+        if (u) { u[3 * i] = v.x; u[3 * i + 1] = v.y; u[3 * i + 2] = v.z; }
+        if (T) T[i] = T0 + double(v.w);
+    }
+    return check_status(b);
+}
+
+tled_status tled_batch_monitors(tled_batch *b, double ablation_T, double *T_max, double *ablated_volume) {
+    TRY(need_device(b));
+    if (!b->d_scen_mon) return fail(b, TLED_E_STATE, "scenario monitors need the fused kernels");
+    const int S = int(b->scen.size());
+    launch_scenario_monitors(b->tp.nu4, b->tp.Vl, b->d_ranges, b->d_np, S, float(ablation_T), b->d_scen_mon,
+                             b->stream);
+    HIPCHK(b, hipGetLastError());
+    std::vector<double> h(2 * S);
+    HIPCHK(b, hipMemcpyAsync(h.data(), b->d_scen_mon, sizeof(double) * 2 * S, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int k = 0; k < S; ++k) {
+        if (T_max) T_max[k] = h[2 * k];
+        if (ablated_volume) ablated_volume[k] = h[2 * k + 1];
+    }
+    return check_status(b);
+}
+
+tled_status tled_batch_get_info(tled_batch *b, tled_batch_info *out) {
+    if (!b || !out) return TLED_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->n_scenarios = int32_t(b->scen.size());
+    for (auto n : b->scen_steps) out->max_steps = std::max<int64_t>(out->max_steps, n);
+    for (auto &p : b->scen) out->n_elems += p.ne;
+    for (auto &p : b->scen) out->n_nodes += p.nn;
+    out->step = b->step;
+    if (b->finalized) {
+        out->n_patches = b->pc.patches.n;
+        out->n_shared_nodes = b->pc.nn - b->pc.patches.n_interior;
+        out->device_bytes = b->device_bytes;
+        out->kernel_variant = b->variant;
+    }
     return TLED_OK;
 }
 

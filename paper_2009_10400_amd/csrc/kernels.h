@@ -74,13 +74,23 @@ struct PatchArgs {
     const long long *step_base;
     unsigned *status;
     double *part_elem, *part_node;
+    // scenario tables (a single problem is a batch of one scenario)
+    const KMat *km;             // per scenario
+    const NodeParams *np;       // per scenario
+    const int *patch_scen;      // per patch
+    const int *shared_scen;     // per shared node
+    const long long *scen_end;  // per scenario: steps to run (the scenario holds afterwards)
 };
 
 void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s);
 void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
-void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m,
-                  const NodeParams &p, int j, hipStream_t s);
-void launch_shared_nodes(bool mon, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s);
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s);
+void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s);
+// Per-scenario maximum temperature and lumped volume at or above T_abl, over the
+// scenario's interior node range [int_lo, int_hi) and shared range [sh_lo, sh_hi).
+void launch_scenario_monitors(const float4 *nu4, const float *Vl, const long long *ranges /* 4 per scenario */,
+                              const NodeParams *np, int n_scen, float T_abl, double *out /* 2 per scenario */,
+                              hipStream_t s);
 void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,
                    long long *step_base, int k, const unsigned *status, DevMonitors *mon, hipStream_t s);
 size_t patch_lds_bytes(int npe, bool geox, const PatchArgs &a);

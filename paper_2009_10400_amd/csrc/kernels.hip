@@ -499,11 +499,22 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
 // (float4 per element slot).  GEOX: element geometry rebuilt from the staged
 // coordinates (else read from the precomputed planes).
 template <int NPE, int NP, bool MON, int BS, bool GEOX>
-__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, KMat m, NodeParams p, int j) {
+__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     extern __shared__ float4 lds[];
     __shared__ double shd[BS / 64];
     __shared__ float shf[BS / 64];
     const int pid = xcd_block(blockIdx.x, gridDim.x);
+    const int sc = A.patch_scen[pid];
+    if (*A.step_base + j >= A.scen_end[sc]) {   // this scenario has finished: hold it
+        if (MON && threadIdx.x == 0) {
+            A.part_elem[pid] = 0.0;
+            double *pp = A.part_node + 4 * size_t(pid);
+            pp[0] = 0.0; pp[1] = -INFINITY; pp[2] = INFINITY; pp[3] = 0.0;
+        }
+        return;
+    }
+    const KMat m = A.km[sc];
+    const NodeParams p = A.np[sc];
     const int e0 = A.elem_begin[pid], e1 = A.elem_begin[pid + 1];
     const int ib = A.int_begin[pid], ie = A.int_begin[pid + 1];
     const int sb = A.shared_begin[pid], se = A.shared_begin[pid + 1];
@@ -604,15 +615,18 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, KMat m, NodePara
 }
 
 template <bool MON>
-__global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, NodeParams p, int j) {
+__global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j) {
     __shared__ double shd[kBlock / 64];
     __shared__ float shf[kBlock / 64];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int s = blk * kBlock + threadIdx.x;
-    const float src = source_switch(p, A.step_base, j);
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
     bool nf = false;
-    if (s < A.n_shared) {
+    const int sc = (s < A.n_shared) ? A.shared_scen[s] : 0;
+    const long long step = *A.step_base + j;
+    if (s < A.n_shared && step < A.scen_end[sc]) {
+        const NodeParams p = A.np[sc];
+        const float src = (step >= p.n_on && step < p.n_off) ? 1.0f : 0.0f;
         const int a = A.n_interior + s;
         const float4 u0 = A.nu4[a], v0 = A.nv4[a], th = A.nth[a];   // independent of the partials
         const unsigned mk = A.mask[a];
@@ -700,22 +714,20 @@ void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_
 }
 
 template <int NPE, int NP, int BS, bool GEOX>
-void launch_patch_g(bool mon, const PatchArgs &a, const KMat &m, const NodeParams &p, int j, size_t lds,
-                    hipStream_t s) {
+void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s) {
     dim3 grid(a.n_patches);
-    if (mon) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, BS, GEOX>), grid, dim3(BS), lds, s, a, m, p, j);
-    else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, BS, GEOX>), grid, dim3(BS), lds, s, a, m, p, j);
+    if (mon) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
+    else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
 }
 
 template <int NPE, int NP>
-void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m, const NodeParams &p, int j,
-                     size_t lds, hipStream_t s) {
+void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, int j, size_t lds, hipStream_t s) {
     if (NPE == 4 && bs == 512) {
-        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, m, p, j, lds, s);
-        else launch_patch_g<NPE, NP, 512, false>(mon, a, m, p, j, lds, s);
+        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, j, lds, s);
+        else launch_patch_g<NPE, NP, 512, false>(mon, a, j, lds, s);
     } else {
-        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, m, p, j, lds, s);
-        else launch_patch_g<NPE, NP, 256, false>(mon, a, m, p, j, lds, s);
+        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, j, lds, s);
+        else launch_patch_g<NPE, NP, 256, false>(mon, a, j, lds, s);
     }
 }
 }  // namespace
@@ -749,34 +761,67 @@ void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hip
                             a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
 }
 
-void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, const KMat &m,
-                  const NodeParams &p, int j, hipStream_t s) {
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s) {
     const size_t lds = patch_lds_bytes(npe, geox, a);
     if (npe == 4) {
         switch (np) {
-            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, m, p, j, lds, s); break;
-            default: launch_patch_np<4, 4>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, j, lds, s); break;
+            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, j, lds, s); break;
+            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, j, lds, s); break;
+            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, j, lds, s); break;
+            default: launch_patch_np<4, 4>(mon, geox, bs, a, j, lds, s); break;
         }
     } else {
         switch (np) {
-            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, m, p, j, lds, s); break;
-            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, m, p, j, lds, s); break;
-            default: launch_patch_np<8, 4>(mon, geox, bs, a, m, p, j, lds, s); break;
+            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, j, lds, s); break;
+            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, j, lds, s); break;
+            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, j, lds, s); break;
+            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, j, lds, s); break;
+            default: launch_patch_np<8, 4>(mon, geox, bs, a, j, lds, s); break;
         }
     }
 }
 
-void launch_shared_nodes(bool mon, const PatchArgs &a, const NodeParams &p, int j, hipStream_t s) {
+void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s) {
     const int nb = int((a.n_shared + kBlock - 1) / kBlock);
     if (nb == 0) return;
     dim3 grid(nb);
-    if (mon) hipLaunchKernelGGL((shared_node_kernel<true>), grid, dim3(kBlock), 0, s, a, p, j);
-    else hipLaunchKernelGGL((shared_node_kernel<false>), grid, dim3(kBlock), 0, s, a, p, j);
+    if (mon) hipLaunchKernelGGL((shared_node_kernel<true>), grid, dim3(kBlock), 0, s, a, j);
+    else hipLaunchKernelGGL((shared_node_kernel<false>), grid, dim3(kBlock), 0, s, a, j);
+}
+
+// One block per scenario: max T and the lumped volume at or above T_abl (fixed-order reduction).
+__global__ __launch_bounds__(kBlock) void scenario_monitor_kernel(const float4 *__restrict__ nu4,
+                                                                  const float *__restrict__ Vl,
+                                                                  const long long *__restrict__ ranges,
+                                                                  const NodeParams *__restrict__ np, float T_abl,
+                                                                  double *__restrict__ out) {
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    const int sc = blockIdx.x;
+    const float T0 = np[sc].T0;
+    float tmax = -INFINITY;
+    double vol = 0.0;
+    for (int r = 0; r < 2; ++r) {
+        const long long lo = ranges[4 * sc + 2 * r], hi = ranges[4 * sc + 2 * r + 1];
+        for (long long a = lo + threadIdx.x; a < hi; a += kBlock) {
+            const float T = T0 + nu4[a].w;
+            tmax = fmaxf(tmax, T);
+            if (T >= T_abl) vol += double(Vl[a]);
+        }
+    }
+    vol = block_sum<kBlock>(vol, shd);
+    tmax = block_max<kBlock>(tmax, shf);
+    if (threadIdx.x == 0) {
+        out[2 * sc] = tmax;
+        out[2 * sc + 1] = vol;
+    }
+}
+
+void launch_scenario_monitors(const float4 *nu4, const float *Vl, const long long *ranges, const NodeParams *np,
+                              int n_scen, float T_abl, double *out, hipStream_t s) {
+    if (n_scen <= 0) return;
+    hipLaunchKernelGGL(scenario_monitor_kernel, dim3(n_scen), dim3(kBlock), 0, s, nu4, Vl, ranges, np, T_abl, out);
 }
 
 void launch_finish(const double *part_elem, int n_elem_parts, const double *part_node, int n_node_parts,

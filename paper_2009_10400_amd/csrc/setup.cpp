@@ -509,4 +509,114 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
     return TLED_OK;
 }
 
+tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
+                             bool reorder, Precomputed *out, std::vector<ScenRange> *ranges,
+                             std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
+                             std::string *err) {
+    const size_t S = ps.size();
+    if (S == 0) { *err = "empty batch"; return TLED_E_ARG; }
+    const int npe = ps[0].npe;
+    std::vector<Precomputed> pcs(S);
+    for (size_t k = 0; k < S; ++k) {
+        if (ps[k].npe != npe) { *err = "a batch needs one element type"; return TLED_E_ARG; }
+        if (ps[k].mat.n_prony != ps[0].mat.n_prony) { *err = "a batch needs one Prony term count"; return TLED_E_ARG; }
+        SetupOptions so;
+        so.reorder = reorder;
+        so.build_patches = true;
+        so.patch_elems = patch_elems[k];
+        std::string e;
+        tled_status st = precompute(ps[k], so, &pcs[k], &e);
+        if (st != TLED_OK) { *err = "scenario " + std::to_string(k) + ": " + e; return st; }
+    }
+    // offsets
+    int64_t NE = 0, NI = 0, NS = 0;
+    for (auto &pc : pcs) { NE += pc.ne; NI += pc.patches.n_interior; NS += pc.nn - pc.patches.n_interior; }
+    Precomputed &U = *out;
+    U = Precomputed();
+    U.npe = npe;
+    U.ne = NE;
+    U.nn = NI + NS;
+    ranges->assign(S, ScenRange());
+    patch_scen->clear();
+    shared_scen->assign(NS, 0);
+    Patches &P = U.patches;
+    P.n_interior = NI;
+    int32_t stride = 0;
+    for (auto &pc : pcs) stride = std::max(stride, pc.patches.slot_stride);
+    P.slot_stride = stride;
+    U.Vl.assign(U.nn, 0); U.M.assign(U.nn, 0); U.C.assign(U.nn, 0); U.Kb.assign(U.nn, 0);
+    U.Qm.assign(U.nn, 0); U.Qr.assign(U.nn, 0); U.fix.assign(U.nn, 0); U.Tfix.assign(U.nn, 0);
+    U.node_new2old.assign(U.nn, -1);   // caller index within its scenario
+    int64_t eo = 0, io = 0, so_ = 0;
+    for (size_t k = 0; k < S; ++k) {
+        const Precomputed &pc = pcs[k];
+        const Patches &Q = pc.patches;
+        ScenRange &R = (*ranges)[k];
+        const int64_t nint = Q.n_interior, nsh = pc.nn - nint;
+        auto map = [&](int64_t n) { return n < nint ? io + n : NI + so_ + (n - nint); };
+        R.elem_lo = eo; R.elem_hi = eo + pc.ne;
+        R.int_lo = io; R.int_hi = io + nint;
+        R.sh_lo = NI + so_; R.sh_hi = NI + so_ + nsh;
+        R.patch_lo = P.n; R.patch_hi = P.n + Q.n;
+        R.dt_cr = pc.dt_cr;
+        R.n_swapped = pc.n_swapped;
+        R.node_of.resize(pc.nn);
+        for (int64_t a = 0; a < pc.nn; ++a) R.node_of[pc.node_new2old[a]] = map(a);
+        R.elem_of.resize(pc.ne);
+        for (int64_t e = 0; e < pc.ne; ++e) R.elem_of[pc.elem_new2old[e]] = eo + e;
+        for (int64_t a = 0; a < pc.nn; ++a) {
+            int64_t g = map(a);
+            U.Vl[g] = pc.Vl[a]; U.M[g] = pc.M[a]; U.C[g] = pc.C[a]; U.Kb[g] = pc.Kb[a];
+            U.Qm[g] = pc.Qm[a]; U.Qr[g] = pc.Qr[a]; U.fix[g] = pc.fix[a]; U.Tfix[g] = pc.Tfix[a];
+            U.node_new2old[g] = pc.node_new2old[a];
+        }
+        for (int64_t j = 0; j < nsh; ++j) (*shared_scen)[so_ + j] = int32_t(k);
+        for (auto c : pc.conn) U.conn.push_back(int32_t(map(c)));
+        U.geo.insert(U.geo.end(), pc.geo.begin(), pc.geo.end());
+        U.V0.insert(U.V0.end(), pc.V0.begin(), pc.V0.end());
+        U.hgc.insert(U.hgc.end(), pc.hgc.begin(), pc.hgc.end());
+        U.khg.insert(U.khg.end(), pc.khg.begin(), pc.khg.end());
+        U.a0.insert(U.a0.end(), pc.a0.begin(), pc.a0.end());
+        for (int64_t e = 0; e < pc.ne; ++e) U.elem_new2old.push_back(pc.elem_new2old[e]);
+        // patches
+        const int32_t sid0 = int32_t(P.shared_ids.size()), lr0 = int32_t(P.lrow.size()),
+                      lx0 = int32_t(P.lX.size() / 3);
+        for (int32_t q = 0; q < Q.n; ++q) {
+            P.elem_begin.push_back(int32_t(eo + Q.elem_begin[q]));
+            P.int_begin.push_back(int32_t(io + Q.int_begin[q]));
+            P.shared_begin.push_back(sid0 + Q.shared_begin[q]);
+            P.lrow_begin.push_back(lr0 + Q.lrow_begin[q]);
+            P.lx_begin.push_back(lx0 + Q.lx_begin[q]);
+            P.lslot_begin.push_back(int32_t((eo + Q.elem_begin[q]) * npe));
+            patch_scen->push_back(int32_t(k));
+        }
+        for (auto id : Q.shared_ids) P.shared_ids.push_back(int32_t(map(id)));
+        P.lconn.insert(P.lconn.end(), Q.lconn.begin(), Q.lconn.end());
+        P.lrow.insert(P.lrow.end(), Q.lrow.begin(), Q.lrow.end());
+        for (auto v : Q.lslot) {
+            const int a = v / Q.slot_stride, el = v % Q.slot_stride;
+            P.lslot.push_back(uint16_t(a * stride + el));
+        }
+        for (int64_t j = 0; j < nsh; ++j) P.srow.push_back(sid0 + Q.srow[j]);
+        for (auto v : Q.ppos) P.ppos.push_back(sid0 + v);
+        P.lX.insert(P.lX.end(), Q.lX.begin(), Q.lX.end());
+        P.max_nodes = std::max(P.max_nodes, Q.max_nodes);
+        P.max_elems = std::max(P.max_elems, Q.max_elems);
+        P.n += Q.n;
+        eo += pc.ne;
+        io += nint;
+        so_ += nsh;
+    }
+    P.elem_begin.push_back(int32_t(NE));
+    P.int_begin.push_back(int32_t(NI));
+    P.shared_begin.push_back(int32_t(P.shared_ids.size()));
+    P.lrow_begin.push_back(int32_t(P.lrow.size()));
+    P.lx_begin.push_back(int32_t(P.lX.size() / 3));
+    P.lslot_begin.push_back(int32_t(NE * npe));
+    P.srow.push_back(int32_t(P.shared_ids.size()));
+    if (P.max_elems * npe > 65535 || P.slot_stride * npe > 65535) { *err = "patch too large"; return TLED_E_ARG; }
+    U.dt_cr = 0.0;
+    return TLED_OK;
+}
+
 }  // namespace tled

@@ -82,6 +82,18 @@ struct Precomputed {
     Patches patches;
 };
 
+// Node and element ranges of one scenario of a batch in the union numbering.
+struct ScenRange {
+    int64_t elem_lo = 0, elem_hi = 0;     // elements
+    int64_t int_lo = 0, int_hi = 0;       // patch-interior nodes
+    int64_t sh_lo = 0, sh_hi = 0;         // shared nodes
+    int32_t patch_lo = 0, patch_hi = 0;   // patches
+    std::vector<int64_t> node_of;         // caller node index -> union internal index
+    std::vector<int64_t> elem_of;         // caller element index -> union internal index
+    double dt_cr = 0.0;
+    int64_t n_swapped = 0;
+};
+
 struct SetupOptions {
     bool reorder = true;
     bool build_patches = false;
@@ -95,5 +107,15 @@ tled_status critical_dt(const HostProblem &p, double *dt_cr, std::string *err);
 // Full precompute.  Returns TLED_OK, TLED_E_MESH or TLED_E_ARG with a message.
 tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precomputed *out,
                        std::string *err);
+
+// Batch of independent scenarios (same element type): each is precomputed with
+// its own patch size, then all are concatenated into one union problem whose
+// patch partition never mixes scenarios.  Node order of the union: all
+// patch-interior nodes scenario by scenario, then all shared nodes scenario by
+// scenario.  patch_scen / shared_scen give the scenario of each patch / shared node.
+tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
+                             bool reorder, Precomputed *out, std::vector<ScenRange> *ranges,
+                             std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
+                             std::string *err);
 
 }  // namespace tled

@@ -77,6 +77,15 @@ class Monitors(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_scenarios", _i32), ("n_patches", _i32), ("n_elems", _i64), ("n_nodes", _i64),
+                ("n_shared_nodes", _i64), ("max_steps", _i64), ("step", _i64), ("device_bytes", _i64),
+                ("kernel_variant", _i32), ("reserved", _i32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("n_nodes", _i64), ("n_elems", _i64), ("elem_type", _i32), ("n_prony", _i32),
                 ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
@@ -121,6 +130,16 @@ _SIGS = {
     "tled_get_state": ([_P, _P], ctypes.c_int),
     "tled_set_state": ([_P, _P], ctypes.c_int),
     "tled_kernel_times": ([_P, _i64, _dp], ctypes.c_int),
+    "tled_batch_create": ([ctypes.POINTER(_P), ctypes.c_int], ctypes.c_int),
+    "tled_batch_destroy": ([_P], None),
+    "tled_batch_add": ([_P, ctypes.c_int, _i64, _dp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(Material), _dp, _dp,
+                        _d, _d, _i64, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint8), _d, _d, _i64, _i32,
+                        ctypes.POINTER(_i32)], ctypes.c_int),
+    "tled_batch_finalize": ([_P], ctypes.c_int),
+    "tled_batch_run": ([_P], ctypes.c_int),
+    "tled_batch_read": ([_P, _i32, _dp, _dp], ctypes.c_int),
+    "tled_batch_monitors": ([_P, _d, _dp, _dp], ctypes.c_int),
+    "tled_batch_get_info": ([_P, ctypes.POINTER(BatchInfo)], ctypes.c_int),
     "tled_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "tled_last_error": ([_P], ctypes.c_char_p),
 }
@@ -364,3 +383,62 @@ def from_problem(problem, dt=None, device: int = 0, stream=None, finalize: bool 
     if finalize:
         s.finalize()
     return s
+
+
+class Batch(Sim):
+    """Many independent scenarios advanced together by the fused kernels."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = _P()
+        st = _lib.tled_batch_create(ctypes.byref(h), int(device))
+        if st != OK:
+            raise TledError(st, f"tled_batch_create(device={device}) failed")
+        self._h = h
+        self.device = device
+        self._cb = None
+        self.sizes = []
+        if stream is not None:
+            self._check(_lib.tled_set_stream(h, _P(int(stream))))
+
+    def add(self, problem, dt: float, n_steps: int, patch_elems: int = 0) -> int:
+        X = _f64(problem.X)
+        conn = np.ascontiguousarray(problem.conn, dtype=np.int32)
+        m = material(problem.params)
+        self.n_prony = m.n_prony
+        fix = problem.fix if problem.fix is not None else np.zeros(len(X), np.uint8)
+        nodes = np.ascontiguousarray(np.nonzero(fix & 7)[0], dtype=np.int32)
+        masks = np.ascontiguousarray(fix[nodes] & 7, dtype=np.uint8)
+        idx = _i32()
+        self._check(_lib.tled_batch_add(
+            self._h, int(problem.npe), len(X), _ptr(X), len(conn), conn.ctypes.data_as(ctypes.POINTER(_i32)),
+            ctypes.byref(m), _ptr(_f64(problem.a0)), _ptr(_f64(problem.q)), float(problem.t_on),
+            float(problem.t_off), len(nodes), nodes.ctypes.data_as(ctypes.POINTER(_i32)),
+            masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), float(dt), float(problem.gamma), int(n_steps),
+            int(patch_elems), ctypes.byref(idx)))
+        self.sizes.append(len(X))
+        return idx.value
+
+    def finalize(self):
+        self._check(_lib.tled_batch_finalize(self._h))
+
+    def run(self):
+        self._check(_lib.tled_batch_run(self._h))
+
+    def read(self, k: int):
+        n = self.sizes[k]
+        u = np.zeros((n, 3))
+        T = np.zeros(n)
+        self._check(_lib.tled_batch_read(self._h, int(k), _ptr(u), _ptr(T)))
+        return u, T
+
+    def scenario_monitors(self, ablation_T: float = 333.15):
+        S = len(self.sizes)
+        tmax = np.zeros(S)
+        vol = np.zeros(S)
+        self._check(_lib.tled_batch_monitors(self._h, float(ablation_T), _ptr(tmax), _ptr(vol)))
+        return tmax, vol
+
+    def batch_info(self) -> dict:
+        i = BatchInfo()
+        self._check(_lib.tled_batch_get_info(self._h, ctypes.byref(i)))
+        return i.as_dict()

@@ -342,6 +342,49 @@ def spheres_t4(n: int = 16, L: float = 0.06, steps: int = 1000, centres=None) ->
                    meta=dict(n=n, L=L))
 
 
+def planning_scenarios(n: int = 256, seed: int = 3, lo: int = 5000, hi: int = 200000, duration_scale: float = 1.0):
+    """Batched planning sweep: tet cubes (0.04 m) and noisy ellipsoids (0.05 x 0.0375 x 0.025 m,
+    no jitter) with log-uniform element counts in [lo, hi]; probe (1/r^2 point source, r0 = h)
+    uniform inside the body, power U(20, 80) W, heating duration U(30, 300) s (times
+    duration_scale), E U(2, 6) kPa; one Prony term (0.5, 0.5 s), bottom face fixed.
+    Returns a list of (Problem, duration)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        ne_target = float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        kind = "cube" if rng.random() < 0.5 else "ellipsoid"
+        power = rng.uniform(20.0, 80.0)
+        duration = rng.uniform(30.0, 300.0) * duration_scale
+        E = rng.uniform(2000.0, 6000.0)
+        if kind == "cube":
+            m = max(2, int(round((ne_target / 6.0) ** (1.0 / 3.0))))
+            L = 0.04
+            X, conn, h = box_mesh("t4", m, L)
+            lo_b, hi_b = np.zeros(3), np.full(3, L)
+        else:
+            p = ellipsoid_t4(int(ne_target), semi=(0.05, 0.0375, 0.025), jitter=0.0, permute=False,
+                             seed_shape=int(rng.integers(1 << 30)))
+            X, conn, h = p.X, p.conn, p.h
+            lo_b, hi_b = X.min(0), X.max(0)
+        P = centroids(X, conn)
+        # probe: a centroid drawn uniformly among the elements in the middle 60 % of the body
+        mid = np.all((P > lo_b + 0.2 * (hi_b - lo_b)) & (P < hi_b - 0.2 * (hi_b - lo_b)), axis=1)
+        cands = np.nonzero(mid)[0] if mid.any() else np.arange(len(P))
+        probe = P[rng.choice(cands)]
+        r = np.sqrt(((P - probe) ** 2).sum(1))
+        w = 1.0 / np.maximum(r, h) ** 2
+        vols = _tet_volumes(X, conn)
+        q = _normalise_power(w, vols, power)
+        params = base_material(E=E)
+        fix = np.where(np.isclose(X[:, 2], X[:, 2].min()), 7, 0).astype(np.uint8)
+        a0 = np.tile(np.array([1.0, 0.0, 0.0]), (len(conn), 1))
+        prob = Problem(f"plan{k}_{kind}", 4, X, conn.astype(np.int32), params, a0=a0, q=q, fix=fix, gamma=80.0,
+                       t_on=0.0, t_off=math.inf, h=h,
+                       meta=dict(kind=kind, power=power, duration=duration, E=E, probe=probe.tolist()))
+        out.append((prob, duration))
+    return out
+
+
 def random_state(problem: Problem, seed: int, u_scale: float, dT_scale: float):
     """A smooth-ish random state (u, u_prev, T) for single-step checks."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,85 @@
+"""Batched planning sweep on the GPU: many scenarios advanced together by the fused kernels.
+
+Each scenario of a batch must give bit for bit what the same scenario gives when run on its own
+(same patch size), hold its state after its own step count, and agree with the FP64 oracle."""
+import numpy as np
+import pytest
+
+from harness import T_ABS_TOL, U_REL_TOL, errors, log, oracle_sim
+from paper_2009_10400_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch():
+    sc = W.planning_scenarios(6, seed=11, lo=1500, hi=9000, duration_scale=1.0)
+    steps = [150, 310, 90, 240, 200, 275]
+    return sc, steps
+
+
+def critical_dt(problem):
+    from paper_2009_10400_amd import tled
+    s = tled.from_problem(problem, device=-1, finalize=False)
+    dt = s.critical_dt()
+    s.close()
+    return dt
+
+
+def test_batch_equals_single_runs_bitwise_and_holds():
+    from paper_2009_10400_amd import tled
+    sc, steps = small_batch()
+    b = tled.Batch(0)
+    b.set_options(graph_steps=40)
+    dts = []
+    for (p, _), n in zip(sc, steps):
+        dt = 0.8 * critical_dt(p)
+        dts.append(dt)
+        b.add(p, dt, n)
+    b.finalize()
+    b.run()
+    b.sync()
+    info = b.batch_info()
+    log("  batch", info)
+    assert info["step"] == max(steps)
+    for k, ((p, _), n) in enumerate(zip(sc, steps)):
+        ub, Tb = b.read(k)
+        s = tled.from_problem(p, dt=dts[k], device=0, kernel_variant=2, graph_steps=40)
+        s.step(n)
+        us, Ts = s.read_u(), s.read_T()
+        assert np.array_equal(ub, us), k
+        assert np.array_equal(Tb, Ts), k
+        assert Tb.max() > p.params["T0"]
+    # stepping further changes nothing: every scenario has reached its end
+    before = [b.read(k) for k in range(len(sc))]
+    b.step(25)
+    for k in range(len(sc)):
+        u2, T2 = b.read(k)
+        assert np.array_equal(before[k][0], u2) and np.array_equal(before[k][1], T2)
+
+
+def test_batch_scenarios_against_oracle_and_monitors():
+    from paper_2009_10400_amd import tled
+    sc, steps = small_batch()
+    sc, steps = sc[:3], steps[:3]
+    b = tled.Batch(0)
+    dts = []
+    for (p, _), n in zip(sc, steps):
+        dt = 0.8 * critical_dt(p)
+        dts.append(dt)
+        b.add(p, dt, n)
+    b.finalize()
+    b.run()
+    thr = W.T_BODY + 0.05
+    tmax, vol = b.scenario_monitors(thr)
+    for k, ((p, _), n) in enumerate(zip(sc, steps)):
+        u, T = b.read(k)
+        o = oracle_sim(p, dts[k])
+        st = o.initial_state(p.params["T0"])
+        o.run(st, n)
+        err = errors(st["u"], u, st["T"], T)
+        log(f"  scenario {k} ({p.meta['kind']}, ne={p.ne}, E={p.meta['E']:.0f}, P={p.meta['power']:.1f} W)", err)
+        assert err["u_rel"] <= U_REL_TOL and err["T_abs"] <= T_ABS_TOL
+        assert tmax[k] == pytest.approx(T.max(), abs=1e-4)
+        Vl = o.lumped()["Vl"]
+        hot = T >= thr
+        assert vol[k] == pytest.approx(Vl[hot].sum(), rel=1e-5, abs=1e-15)

@@ -137,3 +137,33 @@ def test_host_handle_refuses_stepping():
     with pytest.raises(tled.TledError) as e:
         s.read_u()
     assert e.value.status == tled.E_STATE
+
+
+def test_batch_host_setup_and_errors():
+    from paper_2009_10400_amd import tled
+    sc = W.planning_scenarios(4, seed=5, lo=1000, hi=4000)
+    b = tled.Batch(-1)
+    ne = nn = 0
+    for p, _ in sc:
+        b.add(p, 1e-5, 10)
+        ne += p.ne
+        nn += p.nn
+    b.finalize()
+    info = b.batch_info()
+    assert info["n_scenarios"] == 4 and info["n_elems"] == ne and info["n_nodes"] == nn
+    assert info["max_steps"] == 10 and info["n_patches"] >= 4
+    # mixed element types and a too-large dt are refused
+    b2 = tled.Batch(-1)
+    b2.add(sc[0][0], 1e-5, 10)
+    with pytest.raises(tled.TledError) as e:
+        b2.add(W.cube_h8(n=3), 1e-5, 10)
+    assert e.value.status == tled.E_ARG
+    b3 = tled.Batch(-1)
+    b3.add(sc[0][0], 0.01, 10)          # above the critical step (~1e-3 s)
+    with pytest.raises(tled.TledError) as e:
+        b3.finalize()
+    assert e.value.status == tled.E_ARG
+    # the single-problem calls refuse a batch handle
+    with pytest.raises(tled.TledError) as e:
+        b.set_time(1e-5, 0.0)
+    assert e.value.status == tled.E_STATE
