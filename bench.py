@@ -59,6 +59,18 @@ def parse():
     ap.add_argument("--duration-scale", type=float, default=1e-3,
                     help="sweep heating durations are U(30, 300) s times this factor")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--surrogate", type=int, default=0, metavar="N_TRAIN",
+                    help="instead of the headline run: train the surrogate ensemble on N_TRAIN planning runs and "
+                         "compare scenarios/s of surrogate-with-fallback against the solver (one JSON line)")
+    ap.add_argument("--holdout", type=int, default=200)
+    ap.add_argument("--calib", type=int, default=100, help="solver runs held back to calibrate the disagreement")
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--members", type=int, default=4)
+    ap.add_argument("--snapshots", type=int, default=5)
+    ap.add_argument("--threshold", type=float, default=0.5, help="K")
+    ap.add_argument("--train-batch", type=int, default=16384)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--sigma", type=float, default=1.0, help="Fourier frequency standard deviation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches) to calibrate HBM counters")
     return ap.parse_args()
@@ -163,6 +175,110 @@ def sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def surrogate_bench(args):
+    """Learned surrogate against the solver on held-out planning scenarios.
+
+    Training data: N_TRAIN scenarios of the planning distribution (its own seed), each
+    run by the batched solver with snapshots; calibration: --calib further runs; test:
+    --holdout runs never seen in training.  The solver alone runs the test set in one
+    batch (set-up + run + read); the surrogate predicts all of them with the ensemble
+    and hands those whose disagreement estimate exceeds the threshold to the solver."""
+    import torch
+    from paper_2009_10400_amd import surrogate as S, workloads as W
+
+    ds = args.duration_scale
+    t_ref = 300.0 * ds
+    t = time.time()
+    train_sc = W.planning_scenarios(args.surrogate, seed=5, duration_scale=ds)
+    calib_sc = W.planning_scenarios(args.calib, seed=9, duration_scale=ds)
+    test_sc = W.planning_scenarios(args.holdout, seed=7, duration_scale=ds)
+    log(f"[surrogate] scenarios built in {time.time() - t:.1f}s")
+    stream = torch.cuda.Stream(device=0)
+    st = stream.cuda_stream
+
+    t = time.time()
+    snaps, t_solve_train = S.solve_snapshots(train_sc, n_snap=args.snapshots, stream=st, log=log)
+    data = S.make_dataset(train_sc, snaps, t_ref)
+    log(f"[surrogate] training data: {len(snaps)} fields, {len(data.x)} samples in {time.time() - t:.1f}s "
+        f"(solver {t_solve_train:.2f}s)")
+    del snaps
+    net = dict(n_freq=64, width=256, depth=5, n_out=4, sigma=args.sigma)
+    ens = S.Ensemble(args.members, t_ref=t_ref, stream=st, **net)
+    hist, t_train = ens.fit(data, args.epochs, batch=args.train_batch, lr=args.lr, log=log)
+    log(f"[surrogate] trained {args.members} members x {args.epochs} epochs in {t_train:.1f}s")
+
+    # MFMA roofline of the GEMM kernel: timed training steps of a separate network at the training batch size
+    m0 = S.MLP(0, seed=77, stream=st, **net)
+    dev = torch.device("cuda", 0)
+    n = args.train_batch
+    X = torch.from_numpy(data.x[:n]).to(dev)
+    P = torch.from_numpy(data.p[:n]).to(dev)
+    Y = torch.from_numpy(data.y[:n] / ens.y_std).to(dev)
+    m0.set_timing(True)
+    for _ in range(10):
+        m0.train_step(X, P, Y, 1e-4)
+    gemm_ms, gemm_flops = m0.timing()
+    m0.set_timing(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        m0.train_step(X, P, Y, 1e-4)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) / 20 * 1e3
+    fwd_flops = 2.0 * sum(a * b for a, b in [(160, 256)] + [(256, 256)] * 4 + [(256, 4)])
+    n_samples = len(data.x)
+    m0.close()
+    del data, X, P, Y
+
+    cal = S.solve(calib_sc, stream=st)[0]
+    c = ens.calibrate(calib_sc, cal)
+    log(f"[surrogate] calibration factor {c:.3g} from {len(calib_sc)} runs")
+
+    # solver alone on the test set
+    torch.cuda.synchronize()
+    ref, t_solver = S.solve(test_sc, stream=st)
+    rep = S.plan(ens, test_sc, threshold_K=args.threshold, stream=st)
+    t_plan = rep["t_surrogate"] + rep["t_fallback"]
+    errs, acc_err = [], []
+    for k, ((kind, u, T), (ur, Tr)) in enumerate(zip(rep["results"], ref)):
+        e = float(np.abs(T - Tr).max())
+        errs.append(e)
+        if kind == "surrogate":
+            acc_err.append(e)
+    rise = [float((Tr - p.params["T0"]).max()) for (p, _), (_, Tr) in zip(test_sc, ref)]
+    sur_only = [float(np.abs(Tm - Tr).max()) for (Tm, _, _), (_, Tr) in zip(ens.predict_many(test_sc), ref)]
+    n_acc = len(acc_err)
+    out = {
+        "metric": "scenarios/s surrogate vs solver @0.5K", "value": len(test_sc) / t_plan, "unit": "scenarios/s",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "solver_value": len(test_sc) / t_solver, "gain": t_solver / t_plan,
+        "seconds": {"surrogate": rep["t_surrogate"], "fallback_solver": rep["t_fallback"], "solver_alone": t_solver,
+                    "training": t_train, "training_data_solver": t_solve_train},
+        "accepted": n_acc, "fallback": len(rep["rejected"]),
+        "max_err_accepted_K": max(acc_err) if acc_err else None,
+        "accepted_over_threshold": int(sum(e > args.threshold for e in acc_err)),
+        "max_err_all_K": max(errs),
+        "surrogate_only_within_threshold": float(np.mean([e <= args.threshold for e in sur_only])),
+        "surrogate_only_median_err_K": float(np.median(sur_only)),
+        "zero_rise_within_threshold": float(np.mean([r <= args.threshold for r in rise])),
+        "max_rise_K": {"median": float(np.median(rise)), "max": float(max(rise))},
+        "calibration_factor": c,
+        "config": {"workload": f"planning scenarios (tet cubes and noisy ellipsoids, 5k-200k elements, probe 1/r^2 "
+                               f"source U(20,80) W, E U(2,6) kPa, heating U(30,300) s x {ds:g}); "
+                               f"{len(train_sc)} training runs x {args.snapshots} snapshots, {len(calib_sc)} "
+                               f"calibration runs, {len(test_sc)} held-out test runs",
+                   "train_samples": n_samples, "members": args.members, "epochs": args.epochs,
+                   "net": "64 Fourier frequencies + 11 parameters (160 padded) -> 5 x 256 SiLU -> 4",
+                   "threshold_K": args.threshold, "duration_scale": ds, "train_batch": args.train_batch},
+        "training_loss_final": [h[-1] for h in hist],
+        "roofline": {"bound": "mfma", "achieved": gemm_flops / (gemm_ms * 1e-3) / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": gemm_flops / (gemm_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                     "kernel": "gemm_kernel (all GEMMs of a training step)", "gemm_ms_per_step": gemm_ms / 10,
+                     "train_step_ms": step_ms, "flops_per_sample_forward": fwd_flops},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -174,6 +290,9 @@ def main():
         return
     if args.sweep:
         sweep(args)
+        return
+    if args.surrogate:
+        surrogate_bench(args)
         return
     import torch
     from paper_2009_10400_amd import tled, workloads as W

@@ -266,6 +266,10 @@ tled_status tled_batch_run(tled_batch *b);
 /* Displacement (n_nodes x 3) and temperature (n_nodes, K) of one scenario in its
  * caller numbering; either pointer may be NULL. */
 tled_status tled_batch_read(tled_batch *b, int32_t scenario, double *u, double *T);
+/* Every scenario's displacement and temperature at once (one device-to-host
+ * copy), concatenated in the order the scenarios were added, each in its
+ * caller numbering: u (sum of n_nodes) x 3, T sum of n_nodes.  Either may be NULL. */
+tled_status tled_batch_read_all(tled_batch *b, double *u, double *T);
 /* Per scenario: maximum nodal temperature and lumped volume of the nodes at or
  * above ablation_T (e.g. 333.15 K, the 60 C isotherm). */
 tled_status tled_batch_monitors(tled_batch *b, double ablation_T, double *T_max, double *ablated_volume);

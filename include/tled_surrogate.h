@@ -1,0 +1,89 @@
+/*
+ * tled_surrogate.h -- C-ABI of the learned surrogate of the coupled TLED +
+ * Pennes solver: a multilayer perceptron that maps node coordinates (random
+ * Fourier features) and scenario parameters to the nodal temperature and
+ * displacement at the end of a heating scenario, trained on solver runs.
+ * (The paper's discussion names learned acceleration as a route to cheaper
+ * planning runs, Section 7; the network itself is this library's design.)
+ *
+ * Network: features f = [sin(2 pi B x), cos(2 pi B x), p, 0...] with B an
+ * n_freq x 3 matrix drawn once from N(0, sigma^2), x the sample's coordinates
+ * and p its scenario parameters, zero-padded to a multiple of 32; then `depth`
+ * hidden layers of `width` units with SiLU, z = W a + b, a' = z sigmoid(z);
+ * then a linear output layer of n_out units.
+ *
+ * Arithmetic: weights and activations in bfloat16, products accumulated in
+ * FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16); FP32 master weights,
+ * biases, loss and Adam moments.  Loss: mean over samples and outputs of the
+ * squared error.
+ *
+ * Parameter layout (FP32, host arrays of tled_mlp_param_count floats): for
+ * each layer in order, W (rows = outputs, row-major over inputs incl. the
+ * zero padding of the first layer's inputs), then b.
+ *
+ * Data pointers of forward/train/gradient calls are DEVICE pointers (FP32,
+ * row-major): coords n x 3, params n x n_param, target n x n_out, out
+ * n x n_out.  Calls run on the handle's stream; forward and train_step are
+ * asynchronous except when a loss is requested.  Workspace grows on demand
+ * to the largest n seen (hipMalloc), so the first call at a new size allocates.
+ * Errors are tled_status codes (tled.h); messages via tled_mlp_last_error.
+ */
+#ifndef TLED_SURROGATE_H
+#define TLED_SURROGATE_H
+
+#include <stdint.h>
+
+#include "tled.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tled_mlp tled_mlp;
+
+typedef struct {
+    int32_t n_param;   /* scenario parameters per sample                   */
+    int32_t n_freq;    /* Fourier frequencies (2 n_freq features)           */
+    int32_t width;     /* hidden width, multiple of 64                     */
+    int32_t depth;     /* number of hidden layers (>= 1)                   */
+    int32_t n_out;     /* outputs (<= 64)                                  */
+    int32_t reserved;
+    float sigma;       /* standard deviation of the frequencies            */
+    float init_scale;  /* uniform weight init bound factor (0: 1)          */
+    uint64_t seed;     /* frequencies and initial weights                  */
+} tled_mlp_config;
+
+tled_status tled_mlp_create(tled_mlp **out, int device, const tled_mlp_config *cfg);
+void        tled_mlp_destroy(tled_mlp *mlp);
+tled_status tled_mlp_set_stream(tled_mlp *mlp, void *hip_stream);
+tled_status tled_mlp_param_count(const tled_mlp *mlp, int64_t *n);
+tled_status tled_mlp_get_params(tled_mlp *mlp, float *host);
+tled_status tled_mlp_set_params(tled_mlp *mlp, const float *host);
+/* The Fourier frequency matrix B (n_freq x 3, host). */
+tled_status tled_mlp_get_frequencies(tled_mlp *mlp, float *host);
+/* Inference on n samples. */
+tled_status tled_mlp_forward(tled_mlp *mlp, int64_t n, const float *coords, const float *params, float *out);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on the
+ * minibatch; *loss (host, optional) receives the minibatch loss before the step. */
+tled_status tled_mlp_train_step(tled_mlp *mlp, int64_t n, const float *coords, const float *params,
+                                const float *target, float lr, float *loss);
+/* Gradient of the minibatch loss with respect to the FP32 parameters (host
+ * array in the parameter layout), without a step; *loss optional. */
+tled_status tled_mlp_gradient(tled_mlp *mlp, int64_t n, const float *coords, const float *params,
+                              const float *target, float *grad_host, float *loss);
+/* Plain GEMM on the matrix cores, for tests of the kernel itself:
+ * C[m][n] = sum_k A[m][k] B[k][n], A (m x k) and B (k x n) bfloat16 bit
+ * patterns (device, row-major), C FP32 (device, row-major). */
+tled_status tled_mlp_gemm(tled_mlp *mlp, int32_t m, int32_t n, int32_t k, const uint16_t *A, const uint16_t *B,
+                          float *C);
+/* Measurement: with timing on, every GEMM launch is bracketed by HIP events on
+ * the handle's stream (and waited for); tled_mlp_last_timing returns the summed
+ * GEMM time (ms[0], ms; ms[1] unused) and GEMM flops since timing was switched on. */
+tled_status tled_mlp_set_timing(tled_mlp *mlp, int on);
+tled_status tled_mlp_last_timing(tled_mlp *mlp, double ms[2], double flops[1]);
+const char *tled_mlp_last_error(const tled_mlp *mlp);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLED_SURROGATE_H */

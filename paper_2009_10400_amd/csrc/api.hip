@@ -1093,20 +1093,57 @@ tled_status tled_batch_run(tled_batch *b) {
     return mx > b->step ? tled_step(b, mx - b->step) : TLED_OK;
 }
 
+namespace {
+// Copies the two node ranges of one scenario (patch-interior and shared) to the
+// host and scatters them into caller numbering.
+tled_status batch_read_one(tled_batch *b, int32_t scenario, double *u, double *T) {
+    const ScenRange &R = b->ranges[scenario];
+    const int64_t ni = R.int_hi - R.int_lo, ns = R.sh_hi - R.sh_lo;
+    std::vector<float4> hi(size_t(std::max<int64_t>(ni, 0))), hs(size_t(std::max<int64_t>(ns, 0)));
+    if (ni > 0)
+        HIPCHK(b, hipMemcpyAsync(hi.data(), b->tp.nu4 + R.int_lo, sizeof(float4) * ni, hipMemcpyDeviceToHost,
+                                 b->stream));
+    if (ns > 0)
+        HIPCHK(b, hipMemcpyAsync(hs.data(), b->tp.nu4 + R.sh_lo, sizeof(float4) * ns, hipMemcpyDeviceToHost,
+                                 b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    const double T0 = b->scen[scenario].mat.T0;
+    for (size_t i = 0; i < R.node_of.size(); ++i) {
+        const int64_t g = R.node_of[i];
+        const float4 v = (g >= R.int_lo && g < R.int_hi) ? hi[g - R.int_lo] : hs[g - R.sh_lo];
+        if (u) { u[3 * i] = v.x; u[3 * i + 1] = v.y; u[3 * i + 2] = v.z; }
+        if (T) T[i] = T0 + double(v.w);
+    }
+    return TLED_OK;
+}
+}  // namespace
+
 tled_status tled_batch_read(tled_batch *b, int32_t scenario, double *u, double *T) {
     TRY(need_device(b));
     if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
     if (scenario < 0 || size_t(scenario) >= b->scen.size()) return fail(b, TLED_E_ARG, "scenario out of range");
+    TRY(batch_read_one(b, scenario, u, T));
+    return check_status(b);
+}
+
+tled_status tled_batch_read_all(tled_batch *b, double *u, double *T) {
+    TRY(need_device(b));
+    if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
     const int64_t nn = b->pc.nn;
-    std::vector<float4> h(nn);
+    std::vector<float4> h(size_t(std::max<int64_t>(nn, 0)));
     HIPCHK(b, hipMemcpyAsync(h.data(), b->tp.nu4, sizeof(float4) * nn, hipMemcpyDeviceToHost, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
-    const ScenRange &R = b->ranges[scenario];
-    const double T0 = b->scen[scenario].mat.T0;
-    for (size_t i = 0; i < R.node_of.size(); ++i) {
-        const float4 v = h[R.node_of[i]];
-        if (u) { u[3 * i] = v.x; u[3 * i + 1] = v.y; u[3 * i + 2] = v.z; }
-        if (T) T[i] = T0 + double(v.w);
+    int64_t off = 0;
+    for (size_t k = 0; k < b->scen.size(); ++k) {
+        const ScenRange &R = b->ranges[k];
+        const double T0 = b->scen[k].mat.T0;
+        for (size_t i = 0; i < R.node_of.size(); ++i) {
+            const float4 v = h[R.node_of[i]];
+            const int64_t o = off + int64_t(i);
+            if (u) { u[3 * o] = v.x; u[3 * o + 1] = v.y; u[3 * o + 2] = v.z; }
+            if (T) T[o] = T0 + double(v.w);
+        }
+        off += int64_t(R.node_of.size());
     }
     return check_status(b);
 }

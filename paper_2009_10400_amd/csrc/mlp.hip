@@ -1,0 +1,706 @@
+// Learned surrogate: a bfloat16 multilayer perceptron trained and evaluated on
+// the matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+// C-ABI in include/tled_surrogate.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tled_surrogate.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;   // LDS rows padded against bank conflicts
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet).
+__host__ __device__ inline uint16_t f2bf(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2 };
+// How an operand tile is read from global memory: element by element (any
+// strides), 16-byte vectors along k (k contiguous), or 16-byte vectors along
+// the tile's rows (rows contiguous).  Chosen on the host from strides and alignment.
+enum { LD_SCALAR = 0, LD_KVEC = 1, LD_RVEC = 2 };
+
+// One thread's share (8 values) of a 64 x 32 operand tile X(r, k) = X[r*sr + k*sk],
+// rows r0.., k in [k0, k0 + 32), zero outside r < R, k < ke.
+struct TileRegs {
+    uint16_t v[8];
+};
+
+template <int MODE>
+__device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, long sr, long sk, int r0, int R,
+                                 int k0, int ke, int t) {
+    if (MODE == LD_KVEC) {
+        const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+        if (r < R && k + 8 <= ke) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(X + r * sr + k);
+            std::memcpy(q.v, &w, 16);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + k + i] : uint16_t(0);
+        }
+    } else if (MODE == LD_RVEC) {
+        const int k = k0 + (t >> 3), r = r0 + (t & 7) * 8;
+        if (k < ke && r + 8 <= R) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(X + k * sk + r);
+            std::memcpy(q.v, &w, 16);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q.v[i] = (k < ke && r + i < R) ? X[k * sk + r + i] : uint16_t(0);
+        }
+    } else {
+        const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + (k + i) * sk] : uint16_t(0);
+    }
+}
+
+// Stores a thread's share into the LDS tile S[r][k] (row pitch BKP).
+template <int MODE>
+__device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t) {
+    if (MODE == LD_RVEC) {
+        const int k = t >> 3, r = (t & 7) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[r + i][k] = q.v[i];
+    } else {
+        const int r = t >> 2, k = (t & 3) * 8;
+        uint4 w;
+        std::memcpy(&w, q.v, 16);
+        *reinterpret_cast<uint4 *>(&S[r][k]) = w;
+    }
+}
+
+// C = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (bfloat16 bits).
+// 64x64 output tile per workgroup of four wavefronts, each wavefront 32x32 as
+// 2x2 MFMA 16x16x32 tiles.  Lane l of a 16x16x32 MFMA supplies A[l%16][8(l/16)..+7]
+// and B[8(l/16)..+7][l%16] and receives D[4(l/16)+r][l%16], r = 0..3.  The next
+// k-tile is read from global memory into registers while the current one is
+// multiplied out of LDS.
+// Epilogues: EPI_F32 C(m,n) = acc; EPI_BIAS_F32 C = acc + bias[n];
+// EPI_BIAS_SILU Z = acc + bias[n] (FP32 into C) and Act[m*N+n] = bf16(Z sigmoid(Z)).
+// Split-K: workgroup z covers k in [z*kchunk, (z+1)*kchunk) and (EPI_F32 only)
+// writes its partial tile to C + z*M*N (row-major M x N); a reduction follows.
+template <int EPI, int AM, int BMODE>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A,
+                                                        long sam, long sak, const uint16_t *__restrict__ B, long sbk,
+                                                        long sbn, float *__restrict__ C, long scm, long scn,
+                                                        uint16_t *__restrict__ Act, const float *__restrict__ bias,
+                                                        int kchunk) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][BKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][BKP];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    if (gridDim.z > 1) C += size_t(blockIdx.z) * M * N;
+    TileRegs qa, qb;
+    if (kb < ke) {
+        tile_load<AM>(qa, A, sam, sak, m0, M, kb, ke, t);
+        tile_load<BMODE>(qb, B, sbn, sbk, n0, N, kb, ke, t);
+    }
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        tile_store<AM>(qa, As, t);
+        tile_store<BMODE>(qb, Bt, t);
+        __syncthreads();
+        if (k0 + BK < ke) {
+            tile_load<AM>(qa, A, sam, sak, m0, M, k0 + BK, ke, t);
+            tile_load<BMODE>(qb, B, sbn, sbk, n0, N, k0 + BK, ke, t);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + (l & 15)][8 * (l >> 4)]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bt[wn + 16 * j + (l & 15)][8 * (l >> 4)]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * (l >> 4) + r;
+                const int n = n0 + wn + 16 * j + (l & 15);
+                if (m >= M || n >= N) continue;
+                float v = acc[i][j][r];
+                if (EPI == EPI_F32) {
+                    if (gridDim.z > 1) C[size_t(m) * N + n] = v;
+                    else C[m * scm + n * scn] = v;
+                } else if (EPI == EPI_BIAS_F32) {
+                    C[m * scm + n * scn] = v + bias[n];
+                } else {
+                    const float z = v + bias[n];
+                    C[m * scm + n * scn] = z;
+                    Act[size_t(m) * N + n] = f2bf(z / (1.0f + expf(-z)));
+                }
+            }
+}
+
+// Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n).
+__global__ void splitk_reduce_kernel(int nz, int M, int N, const float *__restrict__ part, float *__restrict__ C,
+                                     long scm, long scn) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= long(M) * N) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += part[size_t(z) * M * N + i];
+    const long m = i / N, n = i % N;
+    C[m * scm + n * scn] = s;
+}
+
+// Features of sample i: [sin(2 pi B x_i), cos(2 pi B x_i), p_i, 0 ...] as bfloat16 (row of K0).
+__global__ void features_kernel(long n, const float *__restrict__ x, const float *__restrict__ p,
+                                const float *__restrict__ Bf, int nf, int np, int K0, uint16_t *__restrict__ out) {
+    const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * K0) return;
+    const long i = idx / K0;
+    const int j = int(idx % K0);
+    float v = 0.f;
+    if (j < 2 * nf) {
+        const int f = j < nf ? j : j - nf;
+        const float a = 6.283185307179586f *
+                        (Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2]);
+        v = j < nf ? sinf(a) : cosf(a);
+    } else if (j < 2 * nf + np) {
+        v = p[i * np + (j - 2 * nf)];
+    }
+    out[idx] = f2bf(v);
+}
+
+// dZ = dA * d(SiLU)/dz = dA s (1 + z (1 - s)), s = sigmoid(z); bfloat16 out.
+__global__ void silu_back_kernel(long n, const float *__restrict__ dA, const float *__restrict__ Z,
+                                 uint16_t *__restrict__ dZ) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float z = Z[i], s = 1.0f / (1.0f + expf(-z));
+    dZ[i] = f2bf(dA[i] * s * (1.0f + z * (1.0f - s)));
+}
+
+// dY = 2 (Y - T) / (n n_out) (bfloat16) and per-block sums of (Y - T)^2.
+__global__ void loss_grad_kernel(long n, int nout, const float *__restrict__ Y, const float *__restrict__ T,
+                                 uint16_t *__restrict__ dY, float *__restrict__ part) {
+    __shared__ float sh[kThreads];
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    float e2 = 0.f;
+    if (i < n * nout) {
+        const float d = Y[i] - T[i];
+        e2 = d * d;
+        dY[i] = f2bf(2.0f * d / float(n * nout));
+    }
+    sh[threadIdx.x] = e2;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Fixed-order sum of nparts partials, times scale, into out[0].
+__global__ void sum_kernel(int nparts, const float *__restrict__ part, float scale, float *__restrict__ out) {
+    __shared__ float sh[kThreads];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kThreads / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0] * scale;
+}
+
+// Column sums of a bfloat16 M x N matrix in chunks of rows: part[c][j].
+constexpr int kColChunk = 512;
+__global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict__ X, float *__restrict__ part) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const long r0 = long(blockIdx.y) * kColChunk;
+    if (j >= N) return;
+    float s = 0.f;
+    const long r1 = std::min(M, r0 + kColChunk);
+    for (long r = r0; r < r1; ++r) s += bf2f(X[r * N + j]);
+    part[size_t(blockIdx.y) * N + j] = s;
+}
+
+__global__ void colsum_final_kernel(int nchunks, int N, const float *__restrict__ part, float *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += part[size_t(c) * N + j];
+    out[j] = s;
+}
+
+// Adam on the FP32 master parameters; refreshes the bfloat16 copy.
+__global__ void adam_kernel(long P, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, float lr, float c1, float c2, uint16_t *__restrict__ wb) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+__global__ void to_bf16_kernel(long n, const float *__restrict__ x, uint16_t *__restrict__ y) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+inline unsigned blocks(long n) { return unsigned((n + kThreads - 1) / kThreads); }
+
+struct Layer {
+    int in, out;      // in: padded input width
+    long w_off, b_off;
+};
+
+}  // namespace
+
+struct tled_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tled_mlp_config cfg{};
+    int K0 = 0;
+    std::vector<Layer> layers;
+    long P = 0;
+    std::vector<float> freq;
+    float *d_w = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr, *d_freq = nullptr;
+    uint16_t *d_wb = nullptr;
+    long adam_t = 0;
+    // workspace for up to cap samples
+    long cap = 0;
+    uint16_t *d_x0 = nullptr;
+    std::vector<float *> d_z;        // per hidden layer, cap x width
+    std::vector<uint16_t *> d_a;     // per hidden layer, cap x width
+    float *d_y = nullptr, *d_da = nullptr, *d_part = nullptr, *d_loss = nullptr, *d_cpart = nullptr;
+    uint16_t *d_dy = nullptr, *d_dz = nullptr;
+    std::vector<void *> ws;
+    std::string err;
+    float *d_split = nullptr;        // split-K partials
+    size_t split_cap = 0;
+    // timing
+    bool timing = false;
+    double gemm_ms = 0.0, other_ms = 0.0, gemm_flops = 0.0;
+};
+
+namespace {
+
+tled_status mfail(tled_mlp *s, tled_status st, const std::string &m) {
+    if (s) s->err = m;
+    return st;
+}
+
+#define MCHK(s, expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return mfail(s, TLED_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define MTRY(expr)                        \
+    do {                                  \
+        tled_status st_ = (expr);         \
+        if (st_ != TLED_OK) return st_;   \
+    } while (0)
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+double uniform01(uint64_t &s) { return double(splitmix(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+void free_ws(tled_mlp *s) {
+    for (void *p : s->ws) (void)hipFree(p);
+    s->ws.clear();
+    s->d_z.clear();
+    s->d_a.clear();
+    s->cap = 0;
+}
+
+template <typename T>
+tled_status walloc(tled_mlp *s, T **p, size_t n) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return mfail(s, TLED_E_OOM, "hipMalloc failed");
+    s->ws.push_back(q);
+    *p = static_cast<T *>(q);
+    return TLED_OK;
+}
+
+tled_status ensure_workspace(tled_mlp *s, long n) {
+    if (n <= s->cap) return TLED_OK;
+    MCHK(s, hipStreamSynchronize(s->stream));
+    free_ws(s);
+    const long W = s->cfg.width, no = s->cfg.n_out;
+    const long cap = std::max<long>(n, 1024);
+    MTRY(walloc(s, &s->d_x0, size_t(cap) * s->K0));
+    for (int l = 0; l < s->cfg.depth; ++l) {
+        float *z;
+        uint16_t *a;
+        MTRY(walloc(s, &z, size_t(cap) * W));
+        MTRY(walloc(s, &a, size_t(cap) * W));
+        s->d_z.push_back(z);
+        s->d_a.push_back(a);
+    }
+    MTRY(walloc(s, &s->d_y, size_t(cap) * no));
+    MTRY(walloc(s, &s->d_dy, size_t(cap) * no));
+    MTRY(walloc(s, &s->d_da, size_t(cap) * W));
+    MTRY(walloc(s, &s->d_dz, size_t(cap) * W));
+    MTRY(walloc(s, &s->d_part, size_t(blocks(cap * no))));
+    MTRY(walloc(s, &s->d_loss, 1));
+    MTRY(walloc(s, &s->d_cpart, size_t((cap + kColChunk - 1) / kColChunk) * std::max<long>(W, no)));
+    s->cap = cap;
+    return TLED_OK;
+}
+
+// Vector loads need 16-byte aligned vectors: base aligned and the strided axis a multiple of 8.
+int load_mode(const uint16_t *X, long sr, long sk) {
+    if (reinterpret_cast<uintptr_t>(X) % 16 != 0) return LD_SCALAR;
+    if (sk == 1 && sr % 8 == 0) return LD_KVEC;
+    if (sr == 1 && sk % 8 == 0) return LD_RVEC;
+    return LD_SCALAR;
+}
+
+template <int EPI>
+tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, long sak, const uint16_t *B,
+                 long sbk, long sbn, float *C, long scm, long scn, uint16_t *Act, const float *bias) {
+    const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    int nz = 1;
+    if (EPI == EPI_F32 && tiles < 256 && K >= 4 * BK) nz = int(std::min<long>(64, std::max<long>(1, 512 / tiles)));
+    int kchunk = ((K + nz - 1) / nz + BK - 1) / BK * BK;
+    nz = (K + kchunk - 1) / kchunk;
+    if (nz > 1) {
+        const size_t need = size_t(nz) * M * N;
+        if (need > s->split_cap) {
+            if (s->d_split) (void)hipFree(s->d_split);
+            s->d_split = nullptr;
+            s->split_cap = 0;
+            MCHK(s, hipStreamSynchronize(s->stream));
+            void *p = nullptr;
+            if (hipMalloc(&p, need * sizeof(float)) != hipSuccess) return mfail(s, TLED_E_OOM, "hipMalloc failed");
+            s->d_split = static_cast<float *>(p);
+            s->split_cap = need;
+        }
+    }
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz);
+    const int am = load_mode(A, sam, sak), bmode = load_mode(B, sbn, sbk);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->timing) {
+        MCHK(s, hipEventCreate(&e0));
+        MCHK(s, hipEventCreate(&e1));
+        MCHK(s, hipEventRecord(e0, s->stream));
+    }
+    float *Cout = nz > 1 ? s->d_split : C;
+#define TLED_GEMM_LAUNCH(AMODE, BMODE_)                                                                       \
+    hipLaunchKernelGGL((gemm_kernel<EPI, AMODE, BMODE_>), grid, dim3(kThreads), 0, s->stream, M, N, K, A, sam, sak, \
+                       B, sbk, sbn, Cout, scm, scn, Act, bias, kchunk)
+    if (am == LD_KVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_KVEC);
+    else if (am == LD_KVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_RVEC);
+    else if (am == LD_RVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_RVEC);
+    else if (am == LD_RVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_KVEC);
+    else TLED_GEMM_LAUNCH(LD_SCALAR, LD_SCALAR);
+#undef TLED_GEMM_LAUNCH
+    if (nz > 1)
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks(long(M) * N)), dim3(kThreads), 0, s->stream, nz, M, N,
+                           s->d_split, C, scm, scn);
+    MCHK(s, hipGetLastError());
+    if (s->timing) {
+        MCHK(s, hipEventRecord(e1, s->stream));
+        MCHK(s, hipEventSynchronize(e1));
+        float ms = 0.f;
+        MCHK(s, hipEventElapsedTime(&ms, e0, e1));
+        s->gemm_ms += ms;
+        s->gemm_flops += 2.0 * double(M) * N * K;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return TLED_OK;
+}
+
+// Forward pass for n samples: features, hidden layers (Z, activations kept), output into d_y.
+tled_status forward(tled_mlp *s, long n, const float *coords, const float *params) {
+    MTRY(ensure_workspace(s, n));
+    const int W = s->cfg.width;
+    hipLaunchKernelGGL(features_kernel, dim3(blocks(n * s->K0)), dim3(kThreads), 0, s->stream, n, coords, params,
+                       s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->d_x0);
+    MCHK(s, hipGetLastError());
+    const uint16_t *a = s->d_x0;
+    int in = s->K0;
+    for (int l = 0; l < s->cfg.depth; ++l) {
+        const Layer &L = s->layers[l];
+        MTRY(gemm<EPI_BIAS_SILU>(s, int(n), W, in, a, in, 1, s->d_wb + L.w_off, 1, in, s->d_z[l], W, 1, s->d_a[l],
+                                 s->d_w + L.b_off));
+        a = s->d_a[l];
+        in = W;
+    }
+    const Layer &O = s->layers.back();
+    MTRY(gemm<EPI_BIAS_F32>(s, int(n), s->cfg.n_out, W, a, W, 1, s->d_wb + O.w_off, 1, W, s->d_y, s->cfg.n_out, 1,
+                            nullptr, s->d_w + O.b_off));
+    return TLED_OK;
+}
+
+// Loss and gradient into d_g (and *loss on the host if requested).
+tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
+    const int W = s->cfg.width, no = s->cfg.n_out, D = s->cfg.depth;
+    const unsigned nb = blocks(n * no);
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(kThreads), 0, s->stream, n, no, s->d_y, target, s->d_dy,
+                       s->d_part);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s->stream, int(nb), s->d_part,
+                       1.0f / float(n * no), s->d_loss);
+    MCHK(s, hipGetLastError());
+    const unsigned nchunk = unsigned((n + kColChunk - 1) / kColChunk);
+    // output layer
+    const Layer &O = s->layers.back();
+    MTRY(gemm<EPI_F32>(s, no, W, int(n), s->d_dy, 1, no, s->d_a[D - 1], W, 1, s->d_g + O.w_off, W, 1, nullptr,
+                       nullptr));
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((no + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
+                       s->stream, n, no, s->d_dy, s->d_cpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((no + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
+                       int(nchunk), no, s->d_cpart, s->d_g + O.b_off);
+    MTRY(gemm<EPI_F32>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, s->d_da, W, 1, nullptr, nullptr));
+    for (int l = D - 1; l >= 0; --l) {
+        const Layer &L = s->layers[l];
+        hipLaunchKernelGGL(silu_back_kernel, dim3(blocks(n * W)), dim3(kThreads), 0, s->stream, n * W, s->d_da,
+                           s->d_z[l], s->d_dz);
+        const uint16_t *ain = l > 0 ? s->d_a[l - 1] : s->d_x0;
+        const int in = L.in;
+        MTRY(gemm<EPI_F32>(s, W, in, int(n), s->d_dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr));
+        hipLaunchKernelGGL(colsum_partial_kernel, dim3((W + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
+                           s->stream, n, W, s->d_dz, s->d_cpart);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((W + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
+                           int(nchunk), W, s->d_cpart, s->d_g + L.b_off);
+        if (l > 0)
+            MTRY(gemm<EPI_F32>(s, int(n), in, W, s->d_dz, W, 1, s->d_wb + L.w_off, in, 1, s->d_da, in, 1, nullptr,
+                               nullptr));
+    }
+    MCHK(s, hipGetLastError());
+    if (loss) {
+        MCHK(s, hipMemcpyAsync(loss, s->d_loss, sizeof(float), hipMemcpyDeviceToHost, s->stream));
+        MCHK(s, hipStreamSynchronize(s->stream));
+    }
+    return TLED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tled_mlp_last_error(const tled_mlp *mlp) { return mlp ? mlp->err.c_str() : "null handle"; }
+
+tled_status tled_mlp_create(tled_mlp **out, int device, const tled_mlp_config *cfg) {
+    if (!out || !cfg) return TLED_E_ARG;
+    *out = nullptr;
+    if (cfg->n_param < 0 || cfg->n_freq < 1 || cfg->width < 64 || cfg->width % 64 || cfg->depth < 1 ||
+        cfg->n_out < 1 || cfg->n_out > 64 || !(cfg->sigma > 0))
+        return TLED_E_ARG;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return TLED_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return TLED_E_HIP;
+    tled_mlp *s = new (std::nothrow) tled_mlp();
+    if (!s) return TLED_E_OOM;
+    s->device = device;
+    s->cfg = *cfg;
+    s->K0 = ((2 * cfg->n_freq + cfg->n_param + 31) / 32) * 32;
+    long off = 0;
+    int in = s->K0;
+    for (int l = 0; l <= cfg->depth; ++l) {
+        const int o = l < cfg->depth ? cfg->width : cfg->n_out;
+        Layer L{in, o, off, off + long(o) * in};
+        off += long(o) * in + o;
+        s->layers.push_back(L);
+        in = cfg->width;
+    }
+    s->P = off;
+    // frequencies ~ N(0, sigma^2) (Box-Muller) and uniform Glorot initial weights
+    uint64_t rs = cfg->seed ^ 0x5eedf00dULL;
+    s->freq.resize(3 * size_t(cfg->n_freq));
+    for (auto &f : s->freq) {
+        const double u1 = std::max(uniform01(rs), 1e-300), u2 = uniform01(rs);
+        f = float(cfg->sigma * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+    }
+    std::vector<float> w(s->P, 0.f);
+    const double scale = cfg->init_scale > 0 ? cfg->init_scale : 1.0;
+    for (int l = 0; l <= cfg->depth; ++l) {
+        const Layer &L = s->layers[l];
+        const int fan_in = l == 0 ? 2 * cfg->n_freq + cfg->n_param : L.in;
+        const double lim = scale * std::sqrt(6.0 / double(fan_in + L.out));
+        for (int o = 0; o < L.out; ++o)
+            for (int i = 0; i < L.in; ++i)
+                w[L.w_off + long(o) * L.in + i] = (l == 0 && i >= fan_in) ? 0.f : float(lim * (2.0 * uniform01(rs) - 1.0));
+    }
+    auto fail_free = [&](tled_status st) {
+        tled_mlp_destroy(s);
+        return st;
+    };
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return fail_free(TLED_E_HIP);
+    s->own_stream = true;
+    void *p;
+    if (hipMalloc(&p, sizeof(float) * s->P) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_w = static_cast<float *>(p);
+    if (hipMalloc(&p, sizeof(float) * s->P) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_g = static_cast<float *>(p);
+    if (hipMalloc(&p, sizeof(float) * s->P) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_m = static_cast<float *>(p);
+    if (hipMalloc(&p, sizeof(float) * s->P) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_v = static_cast<float *>(p);
+    if (hipMalloc(&p, sizeof(uint16_t) * s->P) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_wb = static_cast<uint16_t *>(p);
+    if (hipMalloc(&p, sizeof(float) * s->freq.size()) != hipSuccess) return fail_free(TLED_E_OOM);
+    s->d_freq = static_cast<float *>(p);
+    if (hipMemcpy(s->d_freq, s->freq.data(), sizeof(float) * s->freq.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(s->d_m, 0, sizeof(float) * s->P) != hipSuccess ||
+        hipMemset(s->d_v, 0, sizeof(float) * s->P) != hipSuccess)
+        return fail_free(TLED_E_HIP);
+    *out = s;
+    if (tled_mlp_set_params(s, w.data()) != TLED_OK) {
+        *out = nullptr;
+        return fail_free(TLED_E_HIP);
+    }
+    return TLED_OK;
+}
+
+void tled_mlp_destroy(tled_mlp *s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_ws(s);
+    if (s->d_split) (void)hipFree(s->d_split);
+    for (void *p : {static_cast<void *>(s->d_w), static_cast<void *>(s->d_g), static_cast<void *>(s->d_m),
+                    static_cast<void *>(s->d_v), static_cast<void *>(s->d_wb), static_cast<void *>(s->d_freq)})
+        if (p) (void)hipFree(p);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+tled_status tled_mlp_set_stream(tled_mlp *s, void *hip_stream) {
+    if (!s) return TLED_E_ARG;
+    MCHK(s, hipStreamSynchronize(s->stream));
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    s->own_stream = false;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    if (!s->stream) {
+        MCHK(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    return TLED_OK;
+}
+
+tled_status tled_mlp_param_count(const tled_mlp *s, int64_t *n) {
+    if (!s || !n) return TLED_E_ARG;
+    *n = s->P;
+    return TLED_OK;
+}
+
+tled_status tled_mlp_get_params(tled_mlp *s, float *host) {
+    if (!s || !host) return TLED_E_ARG;
+    MCHK(s, hipSetDevice(s->device));
+    MCHK(s, hipMemcpyAsync(host, s->d_w, sizeof(float) * s->P, hipMemcpyDeviceToHost, s->stream));
+    MCHK(s, hipStreamSynchronize(s->stream));
+    return TLED_OK;
+}
+
+tled_status tled_mlp_set_params(tled_mlp *s, const float *host) {
+    if (!s || !host) return TLED_E_ARG;
+    MCHK(s, hipSetDevice(s->device));
+    MCHK(s, hipMemcpyAsync(s->d_w, host, sizeof(float) * s->P, hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(s->P)), dim3(kThreads), 0, s->stream, s->P, s->d_w, s->d_wb);
+    MCHK(s, hipGetLastError());
+    MCHK(s, hipStreamSynchronize(s->stream));
+    return TLED_OK;
+}
+
+tled_status tled_mlp_get_frequencies(tled_mlp *s, float *host) {
+    if (!s || !host) return TLED_E_ARG;
+    std::memcpy(host, s->freq.data(), sizeof(float) * s->freq.size());
+    return TLED_OK;
+}
+
+tled_status tled_mlp_forward(tled_mlp *s, int64_t n, const float *coords, const float *params, float *out) {
+    if (!s || n < 0 || (n > 0 && (!coords || !out || (s->cfg.n_param > 0 && !params)))) return TLED_E_ARG;
+    if (n == 0) return TLED_OK;
+    MCHK(s, hipSetDevice(s->device));
+    MTRY(forward(s, long(n), coords, params));
+    MCHK(s, hipMemcpyAsync(out, s->d_y, sizeof(float) * size_t(n) * s->cfg.n_out, hipMemcpyDeviceToDevice, s->stream));
+    return TLED_OK;
+}
+
+tled_status tled_mlp_gradient(tled_mlp *s, int64_t n, const float *coords, const float *params, const float *target,
+                              float *grad_host, float *loss) {
+    if (!s || n <= 0 || !coords || !target || (s->cfg.n_param > 0 && !params)) return TLED_E_ARG;
+    MCHK(s, hipSetDevice(s->device));
+    MTRY(forward(s, long(n), coords, params));
+    MTRY(backward(s, long(n), target, loss));
+    if (grad_host) {
+        MCHK(s, hipMemcpyAsync(grad_host, s->d_g, sizeof(float) * s->P, hipMemcpyDeviceToHost, s->stream));
+        MCHK(s, hipStreamSynchronize(s->stream));
+    }
+    return TLED_OK;
+}
+
+tled_status tled_mlp_train_step(tled_mlp *s, int64_t n, const float *coords, const float *params,
+                                const float *target, float lr, float *loss) {
+    if (!s || n <= 0 || !coords || !target || (s->cfg.n_param > 0 && !params) || !(lr > 0)) return TLED_E_ARG;
+    MCHK(s, hipSetDevice(s->device));
+    MTRY(forward(s, long(n), coords, params));
+    MTRY(backward(s, long(n), target, loss));
+    s->adam_t += 1;
+    const float c1 = float(1.0 / (1.0 - std::pow(0.9, double(s->adam_t))));
+    const float c2 = float(1.0 / (1.0 - std::pow(0.999, double(s->adam_t))));
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks(s->P)), dim3(kThreads), 0, s->stream, s->P, s->d_w, s->d_g, s->d_m,
+                       s->d_v, lr, c1, c2, s->d_wb);
+    MCHK(s, hipGetLastError());
+    return TLED_OK;
+}
+
+tled_status tled_mlp_gemm(tled_mlp *s, int32_t m, int32_t n, int32_t k, const uint16_t *A, const uint16_t *B,
+                          float *C) {
+    if (!s || m <= 0 || n <= 0 || k <= 0 || !A || !B || !C) return TLED_E_ARG;
+    MCHK(s, hipSetDevice(s->device));
+    s->gemm_ms = s->other_ms = s->gemm_flops = 0.0;
+    MTRY(gemm<EPI_F32>(s, m, n, k, A, k, 1, B, n, 1, C, n, 1, nullptr, nullptr));
+    return TLED_OK;
+}
+
+tled_status tled_mlp_set_timing(tled_mlp *s, int on) {
+    if (!s) return TLED_E_ARG;
+    s->timing = on != 0;
+    s->gemm_ms = s->other_ms = s->gemm_flops = 0.0;
+    return TLED_OK;
+}
+
+tled_status tled_mlp_last_timing(tled_mlp *s, double ms[2], double flops[1]) {
+    if (!s || !ms || !flops) return TLED_E_ARG;
+    ms[0] = s->gemm_ms;
+    ms[1] = s->other_ms;
+    flops[0] = s->gemm_flops;
+    return TLED_OK;
+}
+
+}  // extern "C"

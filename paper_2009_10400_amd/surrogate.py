@@ -1,0 +1,374 @@
+"""Learned surrogate of the solver: binding of the BF16 MFMA network and its workflow.
+
+The network (``include/tled_surrogate.h``) maps a node's coordinates relative to
+the probe (random Fourier features) and its scenario's parameters to the node's
+temperature rise and displacement at the end of the heating.  It is trained on
+the library's own batched solver runs (:func:`make_dataset`) by the library's
+forward/backward MFMA kernels (:meth:`MLP.train_step`).  An ensemble of members
+trained from different seeds estimates its own uncertainty: a scenario whose
+members disagree by more than a threshold on temperature is handed back to the
+solver (:func:`plan`).
+
+Every array operation of the network runs in the library's kernels; this module
+marshals arguments and runs the training loop.  PyTorch holds device memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import tled
+from .tled import TledError, _lib
+
+_P = ctypes.c_void_p
+_f = ctypes.c_float
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+class MLPConfig(ctypes.Structure):
+    _fields_ = [("n_param", ctypes.c_int32), ("n_freq", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("n_out", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("init_scale", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+_SIGS = {
+    "tled_mlp_create": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(MLPConfig)], ctypes.c_int),
+    "tled_mlp_destroy": ([_P], None),
+    "tled_mlp_set_stream": ([_P, _P], ctypes.c_int),
+    "tled_mlp_param_count": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "tled_mlp_get_params": ([_P, _fp], ctypes.c_int),
+    "tled_mlp_set_params": ([_P, _fp], ctypes.c_int),
+    "tled_mlp_get_frequencies": ([_P, _fp], ctypes.c_int),
+    "tled_mlp_forward": ([_P, ctypes.c_int64, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_train_step": ([_P, ctypes.c_int64, _P, _P, _P, _f, _fp], ctypes.c_int),
+    "tled_mlp_gradient": ([_P, ctypes.c_int64, _P, _P, _P, _fp, _fp], ctypes.c_int),
+    "tled_mlp_gemm": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "tled_mlp_last_timing": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                             ctypes.c_int),
+    "tled_mlp_last_error": ([_P], ctypes.c_char_p),
+}
+for _name, (_a, _r) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _a
+    _fn.restype = _r
+
+EXPORTED = tuple(_SIGS)
+
+# Inputs.  Coordinates: node position relative to the probe in units of
+# XI_SCALE element sizes (the source is 1/r^2 with core radius h, so the field near
+# the probe has a shape common to all resolutions in these units).  Scenario
+# parameters (normalised): node position (3, /0.05 m), probe position (3, /0.05 m),
+# power (/50 W), heating time (/t_ref), Young's modulus (/4 kPa), element size
+# (/2 mm), body (0 cube, 1 ellipsoid).
+N_PARAM = 11
+XI_SCALE = 8.0
+R_REF = 0.02            # m: length in the temperature scale below
+
+
+def _dp(t):
+    return _P(t.data_ptr())
+
+
+class MLP:
+    """One network on one device (device tensors via torch)."""
+
+    def __init__(self, device: int = 0, n_param: int = N_PARAM, n_freq: int = 64, width: int = 256, depth: int = 5,
+                 n_out: int = 4, sigma: float = 1.0, seed: int = 0, init_scale: float = 1.0, stream=None):
+        self.cfg = dict(n_param=n_param, n_freq=n_freq, width=width, depth=depth, n_out=n_out)
+        c = MLPConfig(n_param, n_freq, width, depth, n_out, 0, sigma, init_scale, seed)
+        h = _P()
+        st = _lib.tled_mlp_create(ctypes.byref(h), int(device), ctypes.byref(c))
+        if st != 0:
+            raise TledError(st, "tled_mlp_create failed")
+        self._h = h
+        self.device = device
+        if stream is not None:
+            self._check(_lib.tled_mlp_set_stream(h, _P(int(stream))))
+        n = ctypes.c_int64()
+        self._check(_lib.tled_mlp_param_count(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def _check(self, st):
+        if st != 0:
+            raise TledError(st, _lib.tled_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tled_mlp_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        self._check(_lib.tled_mlp_get_params(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        self._check(_lib.tled_mlp_set_params(self._h, theta.ctypes.data_as(_fp)))
+
+    def frequencies(self) -> np.ndarray:
+        out = np.zeros((self.cfg["n_freq"], 3), np.float32)
+        self._check(_lib.tled_mlp_get_frequencies(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def forward(self, x, p):
+        import torch
+        out = torch.empty((x.shape[0], self.cfg["n_out"]), dtype=torch.float32, device=x.device)
+        self._check(_lib.tled_mlp_forward(self._h, x.shape[0], _dp(x), _dp(p), _dp(out)))
+        return out
+
+    def train_step(self, x, p, y, lr: float, want_loss: bool = False):
+        loss = _f(0.0)
+        self._check(_lib.tled_mlp_train_step(self._h, x.shape[0], _dp(x), _dp(p), _dp(y), float(lr),
+                                             ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradient(self, x, p, y):
+        g = np.zeros(self.n_params, np.float32)
+        loss = _f(0.0)
+        self._check(_lib.tled_mlp_gradient(self._h, x.shape[0], _dp(x), _dp(p), _dp(y), g.ctypes.data_as(_fp),
+                                           ctypes.byref(loss)))
+        return loss.value, g
+
+    def gemm(self, A_bits, B_bits, C):
+        """C = A B on the matrix cores; A, B int16 tensors of bfloat16 bits, C float32."""
+        m, k = A_bits.shape
+        n = B_bits.shape[1]
+        self._check(_lib.tled_mlp_gemm(self._h, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C)))
+
+    def set_timing(self, on: bool):
+        self._check(_lib.tled_mlp_set_timing(self._h, int(on)))
+
+    def timing(self):
+        ms = (ctypes.c_double * 2)()
+        fl = (ctypes.c_double * 1)()
+        self._check(_lib.tled_mlp_last_timing(self._h, ms, fl))
+        return ms[0], fl[0]
+
+
+# --------------------------------------------------------------------------- data
+
+def temperature_scale(problem, duration: float) -> float:
+    """K: P t / (rho c h^2 R_REF).  The temperature rise near the probe is this
+    scale times a shape of order one (energy P t deposited by a 1/r^2 source of
+    core radius h, before conduction spreads it)."""
+    m = problem.params
+    return problem.meta["power"] * duration / (m["rho"] * m["c"] * problem.h ** 2 * R_REF)
+
+
+def scenario_inputs(problem, duration: float, t_ref: float):
+    probe = np.asarray(problem.meta["probe"])
+    x = (problem.X - probe) / (XI_SCALE * problem.h)
+    prm = np.array([*(probe / 0.05), problem.meta["power"] / 50.0, duration / t_ref,
+                    problem.meta["E"] / 4000.0, problem.h / 2e-3,
+                    1.0 if problem.meta["kind"] == "ellipsoid" else 0.0])
+    p = np.concatenate([problem.X / 0.05, np.tile(prm, (problem.nn, 1))], axis=1)
+    return x.astype(np.float32), p.astype(np.float32)
+
+
+def scaled_targets(problem, duration: float, u, T):
+    """Network targets before standardisation: temperature rise / s_T and
+    displacement / (alpha s_T h), s_T = temperature_scale."""
+    sT = temperature_scale(problem, duration)
+    su = problem.params["alpha"] * sT * problem.h
+    return np.concatenate([((T - problem.params["T0"]) / sT)[:, None], u / su], axis=1)
+
+
+def unscale(problem, duration: float, y):
+    sT = temperature_scale(problem, duration)
+    su = problem.params["alpha"] * sT * problem.h
+    return problem.params["T0"] + sT * y[..., 0], su * y[..., 1:]
+
+
+def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, graph_steps: int = 50, log=None):
+    """Runs scenarios [(Problem, duration)] in one batch, each to the end of its heating,
+    and reads every scenario's fields at n_snap evenly spaced batch steps.  A snapshot
+    of a scenario at heating time t is the solution of the same scenario with
+    duration t (the source is on from t = 0 and the past does not depend on a later
+    switch-off).  Returns (list of (scenario index, duration, u, T), solver seconds)."""
+    b = tled.Batch(device, stream=stream)
+    b.set_options(graph_steps=graph_steps)
+    dts, steps = [], []
+    for p, dur in scenarios:
+        h = tled.from_problem(p, device=-1, finalize=False)
+        dt = p.cfl * h.critical_dt()
+        h.close()
+        n = max(1, int(round(dur / dt)))
+        dts.append(dt)
+        steps.append(n)
+        b.add(p, dt, n)
+    b.finalize()
+    S = max(steps)
+    marks = sorted(set(max(1, int(round(S * j / n_snap))) for j in range(1, n_snap + 1)))
+    snaps, last, done, el = [], [0] * len(scenarios), 0, 0.0
+    for k in marks:
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(k - done)
+        b.sync()
+        el += time.perf_counter() - t0
+        done = k
+        fields = b.read_all()
+        for s, (u, T) in enumerate(fields):
+            n = min(k, steps[s])
+            if n > last[s]:
+                snaps.append((s, n * dts[s], u.copy(), T.copy()))
+                last[s] = n
+        if log:
+            log(f"[surrogate] snapshot at batch step {k}/{S}: {len(snaps)} fields")
+    b.close()
+    return snaps, el
+
+
+def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 50):
+    """Solver alone: one batch, every scenario to the end of its heating.
+    Returns ([(u, T)], seconds of set-up + run + read)."""
+    t0 = time.perf_counter()
+    b = tled.Batch(device, stream=stream)
+    b.set_options(graph_steps=graph_steps)
+    for p, dur in scenarios:
+        h = tled.from_problem(p, device=-1, finalize=False)
+        dt = p.cfl * h.critical_dt()
+        h.close()
+        b.add(p, dt, max(1, int(round(dur / dt))))
+    b.finalize()
+    b.run()
+    out = [(u.copy(), T.copy()) for u, T in b.read_all()]
+    el = time.perf_counter() - t0
+    b.close()
+    return out, el
+
+
+@dataclass
+class Dataset:
+    x: np.ndarray        # samples x 3
+    p: np.ndarray        # samples x N_PARAM
+    y: np.ndarray        # samples x 4 (scaled targets)
+    field: np.ndarray    # snapshot index per sample
+
+
+def make_dataset(scenarios, snaps, t_ref: float) -> Dataset:
+    xs, ps, ys, fs = [], [], [], []
+    for j, (s, dur, u, T) in enumerate(snaps):
+        prob = scenarios[s][0]
+        x, p = scenario_inputs(prob, dur, t_ref)
+        xs.append(x)
+        ps.append(p)
+        ys.append(scaled_targets(prob, dur, u, T).astype(np.float32))
+        fs.append(np.full(len(x), j, np.int32))
+    return Dataset(np.concatenate(xs), np.concatenate(ps), np.concatenate(ys), np.concatenate(fs))
+
+
+class Ensemble:
+    """K networks trained from different seeds on standardised targets; the
+    spread of their temperature predictions, times a factor calibrated on
+    held-back solver runs, is the disagreement estimate."""
+
+    def __init__(self, k: int = 4, device: int = 0, t_ref: float = 0.3, stream=None, **net):
+        self.models = [MLP(device, seed=1000 + i, stream=stream, **net) for i in range(k)]
+        self.device = device
+        self.t_ref = t_ref
+        self.y_std = np.ones(4, np.float32)
+        self.calib = 1.0
+
+    def fit(self, data: Dataset, epochs: int, batch: int = 16384, lr: float = 2e-3, log=None):
+        self.y_std = data.y.std(0).astype(np.float32) + np.float32(1e-12)
+        d = Dataset(data.x, data.p, (data.y / self.y_std).astype(np.float32), data.field)
+        t0 = time.perf_counter()
+        hist = [train(m, d, epochs, batch=batch, lr=lr, seed=i, log=log) for i, m in enumerate(self.models)]
+        return hist, time.perf_counter() - t0
+
+    def _forward_all(self, x, p):
+        import torch
+        dev = torch.device("cuda", self.device)
+        X = torch.from_numpy(x).to(dev)
+        Pm = torch.from_numpy(p).to(dev)
+        ys = torch.stack([m.forward(X, Pm) for m in self.models])      # K x n x 4
+        return (ys * torch.from_numpy(self.y_std).to(dev)).cpu().numpy()
+
+    def predict_many(self, items):
+        """items [(Problem, duration)] -> [(T mean, u mean, T spread)], one forward call per member."""
+        xs, ps = zip(*(scenario_inputs(p, d, self.t_ref) for p, d in items))
+        ys = self._forward_all(np.concatenate(xs), np.concatenate(ps))
+        out, o = [], 0
+        for (p, d), x in zip(items, xs):
+            y = ys[:, o:o + len(x)]
+            o += len(x)
+            T, u = unscale(p, d, y)
+            out.append((T.mean(0), u.mean(0), T.max(0) - T.min(0)))
+        return out
+
+    def calibrate(self, items, fields):
+        """Factor c with max|T - T_solver| <= c * max spread on every calibration field."""
+        preds = self.predict_many(items)
+        r = [np.abs(Tm - T).max() / max(sp.max(), 1e-12) for (Tm, _, sp), (_, T) in zip(preds, fields)]
+        self.calib = float(max(r)) if r else 1.0
+        return self.calib
+
+    def disagreement(self, spread):
+        return self.calib * float(spread.max())
+
+
+def train(model: MLP, data: Dataset, epochs: int, batch: int = 16384, lr: float = 2e-3, seed: int = 0, log=None):
+    """Minibatch Adam over the dataset (device-resident); cosine learning-rate decay."""
+    import torch
+    dev = torch.device("cuda", model.device)
+    X = torch.from_numpy(data.x).to(dev)
+    Pm = torch.from_numpy(data.p).to(dev)
+    Y = torch.from_numpy(data.y).to(dev)
+    n = X.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    it = 0
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(dev)
+        for s in range(steps_per_epoch):
+            idx = perm[s * batch:(s + 1) * batch]
+            xb, pb, yb = X[idx].contiguous(), Pm[idx].contiguous(), Y[idx].contiguous()
+            lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * it / total))
+            want = (s == steps_per_epoch - 1)
+            loss = model.train_step(xb, pb, yb, lr_t, want_loss=want)
+            if want:
+                losses.append(loss)
+            it += 1
+        if log and (ep % max(1, epochs // 5) == 0 or ep == epochs - 1):
+            log(f"[surrogate] seed {seed} epoch {ep + 1}/{epochs} loss {losses[-1]:.4g}")
+    return losses
+
+
+def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream=None):
+    """Surrogate-first planning of items [(Problem, duration)]: every scenario is
+    predicted by the ensemble; those whose disagreement estimate exceeds
+    threshold_K are run by the solver instead.  Returns results and timings."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    preds = ens.predict_many(items)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    est = [ens.disagreement(sp) for _, _, sp in preds]
+    reject = [k for k, e in enumerate(est) if e > threshold_K]
+    t_fb, fallback = 0.0, {}
+    if reject:
+        fields, t_fb = solve([items[k] for k in reject], device=device, stream=stream)
+        fallback = dict(zip(reject, fields))
+    results = []
+    for k, (Tm, um, _) in enumerate(preds):
+        if k in fallback:
+            u, T = fallback[k]
+            results.append(("solver", u, T))
+        else:
+            results.append(("surrogate", um, Tm))
+    return {"results": results, "t_surrogate": t_sur, "t_fallback": t_fb, "rejected": reject, "estimate": est}

@@ -138,6 +138,7 @@ _SIGS = {
     "tled_batch_finalize": ([_P], ctypes.c_int),
     "tled_batch_run": ([_P], ctypes.c_int),
     "tled_batch_read": ([_P, _i32, _dp, _dp], ctypes.c_int),
+    "tled_batch_read_all": ([_P, _dp, _dp], ctypes.c_int),
     "tled_batch_monitors": ([_P, _d, _dp, _dp], ctypes.c_int),
     "tled_batch_get_info": ([_P, ctypes.POINTER(BatchInfo)], ctypes.c_int),
     "tled_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -430,6 +431,18 @@ class Batch(Sim):
         T = np.zeros(n)
         self._check(_lib.tled_batch_read(self._h, int(k), _ptr(u), _ptr(T)))
         return u, T
+
+    def read_all(self):
+        """[(u, T)] of every scenario, from one device-to-host copy."""
+        n = sum(self.sizes)
+        u = np.zeros((n, 3))
+        T = np.zeros(n)
+        self._check(_lib.tled_batch_read_all(self._h, _ptr(u), _ptr(T)))
+        out, o = [], 0
+        for s in self.sizes:
+            out.append((u[o:o + s], T[o:o + s]))
+            o += s
+        return out
 
     def scenario_monitors(self, ablation_T: float = 333.15):
         S = len(self.sizes)

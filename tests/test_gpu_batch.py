@@ -55,6 +55,9 @@ def test_batch_equals_single_runs_bitwise_and_holds():
     for k in range(len(sc)):
         u2, T2 = b.read(k)
         assert np.array_equal(before[k][0], u2) and np.array_equal(before[k][1], T2)
+    # the bulk read returns the same fields, scenario by scenario
+    for k, (ua, Ta) in enumerate(b.read_all()):
+        assert np.array_equal(before[k][0], ua) and np.array_equal(before[k][1], Ta)
 
 
 def test_batch_scenarios_against_oracle_and_monitors():

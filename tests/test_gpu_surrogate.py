@@ -1,0 +1,157 @@
+"""GPU tests of the surrogate network: MFMA GEMM, forward, gradient, training.
+
+The GEMM is checked against an FP64 product of the same bfloat16 inputs; the
+network's forward pass and gradient against the FP64 reference of
+oracle/mlp_ref.py evaluated with the same (bfloat16-rounded) weights.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_bits(a):
+    """float32 -> bfloat16 bits, round to nearest even (finite inputs)."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def _bf16_round(a):
+    return (_bf16_bits(a).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda", 0)
+
+
+def _mlp(**kw):
+    from paper_2009_10400_amd import surrogate
+    return surrogate.MLP(0, **kw)
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 64, 32), (100, 70, 45), (1, 1, 1), (5, 256, 8192), (8192, 256, 256),
+                                   (257, 129, 300), (4, 200, 4096), (100, 72, 48),
+                                   (130, 136, 1000)])
+def test_gemm_matches_fp64_product(torch_dev, m, n, k):
+    import torch
+    print(f"[gemm] m={m} n={n} k={k}", flush=True)
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((m, k)).astype(np.float32)
+    B = rng.standard_normal((k, n)).astype(np.float32)
+    Ab, Bb = _bf16_bits(A), _bf16_bits(B)
+    ref = _bf16_round(A) @ _bf16_round(B)
+    mlp = _mlp(n_param=1, n_freq=4, width=64, depth=1, n_out=4)
+    dA = torch.from_numpy(Ab.view(np.int16)).to(torch_dev)
+    dB = torch.from_numpy(Bb.view(np.int16)).to(torch_dev)
+    C = torch.full((m, n), float("nan"), dtype=torch.float32, device=torch_dev)
+    mlp.gemm(dA, dB, C)
+    got = C.cpu().numpy().astype(np.float64)
+    # products of bfloat16 values are exact in FP32; only the FP32 summation rounds
+    tol = 4e-7 * np.sqrt(k) * (np.abs(_bf16_round(A)) @ np.abs(_bf16_round(B))) + 1e-30
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+def _small_case(seed, n=300, cfg=None):
+    cfg = cfg or dict(n_param=3, n_freq=16, width=64, depth=2, n_out=4)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    p = rng.uniform(-1, 1, (n, cfg["n_param"])).astype(np.float32)
+    t = rng.standard_normal((n, cfg["n_out"])).astype(np.float32)
+    return cfg, x, p, t
+
+
+def _ref_theta(mlp):
+    """FP64 reference parameters: weights rounded to bfloat16 as the kernels use them, FP32 biases."""
+    theta = mlp.params().astype(np.float64)
+    lay, _, _ = R.layout(**mlp.cfg)
+    for ws, _, _ in lay:
+        theta[ws] = _bf16_round(theta[ws].astype(np.float32))
+    return theta
+
+
+@pytest.mark.parametrize("n", [1, 300, 1000])
+def test_forward_matches_reference(torch_dev, n):
+    import torch
+    print(f"[forward] n={n}", flush=True)
+    cfg, x, p, t = _small_case(11, n)
+    mlp = _mlp(**cfg, sigma=0.7, seed=3)
+    B = mlp.frequencies().astype(np.float64)
+    y = mlp.forward(torch.from_numpy(x).to(torch_dev), torch.from_numpy(p).to(torch_dev)).cpu().numpy()
+    yr, _, _ = R.forward(_ref_theta(mlp), x.astype(np.float64), p.astype(np.float64), B, cfg)
+    scale = np.abs(yr).max()
+    assert np.abs(y - yr).max() <= 2e-2 * scale, (np.abs(y - yr).max(), scale)
+
+
+def test_frequencies_are_gaussian():
+    """The Fourier frequencies are N(0, sigma^2): moments of 3 x 4096 draws."""
+    mlp = _mlp(n_param=0, n_freq=4096, width=64, depth=1, n_out=1, sigma=2.0, seed=9)
+    B = mlp.frequencies()
+    assert abs(B.mean()) < 0.06 and abs(B.std() - 2.0) < 0.05
+
+
+@pytest.mark.parametrize("depth,width", [(2, 64), (5, 256)])
+def test_gradient_matches_fp64_reference(torch_dev, depth, width):
+    import torch
+    print(f"[gradient] depth={depth} width={width}", flush=True)
+    cfg, x, p, t = _small_case(21, 700, dict(n_param=8, n_freq=64, width=width, depth=depth, n_out=4))
+    mlp = _mlp(**cfg, sigma=1.0, seed=5)
+    B = mlp.frequencies().astype(np.float64)
+    dx, dp, dt = (torch.from_numpy(a).to(torch_dev) for a in (x, p, t))
+    loss, g = mlp.gradient(dx, dp, dt)
+    lr, gr = R.loss_and_grad(_ref_theta(mlp), x.astype(np.float64), p.astype(np.float64), t.astype(np.float64),
+                             B, cfg)
+    assert abs(loss - lr) <= 1e-2 * lr
+    lay, _, _ = R.layout(**cfg)
+    for l, (ws, _, bs) in enumerate(lay):
+        for sl in (ws, bs):
+            a, b = g[sl].astype(np.float64), gr[sl]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+            print(f"  layer {l} {'W' if sl is ws else 'b'}: rel {rel:.2e} cos {cos:.6f}", flush=True)
+            assert rel < 4e-2 and cos > 0.999, (l, rel, cos)
+
+
+def test_training_reduces_loss_and_is_deterministic(torch_dev):
+    import torch
+    rng = np.random.default_rng(7)
+    n = 4096
+    x = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    p = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+    t = np.stack([np.sin(2 * x[:, 0]) * p[:, 0], np.exp(-(x ** 2).sum(1)), x[:, 1] * x[:, 2], p[:, 1] ** 2],
+                 axis=1).astype(np.float32)
+    dx, dp, dt = (torch.from_numpy(a).to(torch_dev) for a in (x, p, t))
+    cfg = dict(n_param=2, n_freq=32, width=128, depth=3, n_out=4)
+    a, b = _mlp(**cfg, seed=1, sigma=0.5), _mlp(**cfg, seed=1, sigma=0.5)
+    l0 = a.train_step(dx, dp, dt, 2e-3, want_loss=True)
+    for _ in range(300):
+        a.train_step(dx, dp, dt, 2e-3)
+    l1 = a.train_step(dx, dp, dt, 1e-3, want_loss=True)
+    print(f"[train] loss {l0:.4g} -> {l1:.4g}", flush=True)
+    assert l1 < 0.05 * l0
+    b.train_step(dx, dp, dt, 2e-3)
+    for _ in range(300):
+        b.train_step(dx, dp, dt, 2e-3)
+    b.train_step(dx, dp, dt, 1e-3)
+    assert np.array_equal(a.params(), b.params())
+
+
+def test_argument_errors(torch_dev):
+    import torch
+    from paper_2009_10400_amd import surrogate
+    from paper_2009_10400_amd.tled import TledError
+    with pytest.raises(TledError):
+        surrogate.MLP(0, width=100)
+    with pytest.raises(TledError):
+        surrogate.MLP(0, n_out=65)
+    m = _mlp(n_param=2, n_freq=4, width=64, depth=1, n_out=2)
+    x = torch.zeros((0, 3), device=torch_dev)
+    assert m.forward(x, torch.zeros((0, 2), device=torch_dev)).shape == (0, 2)
+    with pytest.raises(TledError):
+        m.train_step(torch.zeros((4, 3), device=torch_dev), torch.zeros((4, 2), device=torch_dev),
+                     torch.zeros((4, 2), device=torch_dev), -1.0)

@@ -13,10 +13,11 @@ from paper_2009_10400_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "tled.h")
+SURROGATE_HEADER = os.path.join(ROOT, "include", "tled_surrogate.h")
 
 
-def declared_symbols():
-    text = open(HEADER).read()
+def declared_symbols(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(tled_[A-Za-z_]+)\s*\(", text)))
 
@@ -29,6 +30,16 @@ def test_library_exports_every_declared_symbol():
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) == set(tled.EXPORTED)
+
+
+def test_library_exports_every_surrogate_symbol():
+    from paper_2009_10400_amd import surrogate, tled
+    lib = ctypes.CDLL(tled.LIB_PATH)
+    syms = declared_symbols(SURROGATE_HEADER)
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(surrogate.EXPORTED)
 
 
 def test_binding_refuses_without_library(tmp_path, monkeypatch):
