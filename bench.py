@@ -71,6 +71,10 @@ def parse():
     ap.add_argument("--train-batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--sigma", type=float, default=1.0, help="Fourier frequency standard deviation")
+    ap.add_argument("--counters-summary", nargs=6, default=None,
+                    metavar=("WORKLOAD", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "COPY_MIB"),
+                    help="write profiles/traffic_WORKLOAD.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
+                         "databases of a bench run and of a --copy-calibration run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches) to calibrate HBM counters")
     return ap.parse_args()
@@ -87,6 +91,59 @@ def copy_calibration(mib: int):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+
+
+def _counter_means(db_path: str, counter: str):
+    """Mean value per dispatch of one counter, per kernel name, from a rocprofv3 database."""
+    import sqlite3
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select kernel_name, avg(value), count(*) from "
+                       "(select dispatch_id, kernel_name, sum(value) as value from counters_collection "
+                       " where counter_name = ? group by dispatch_id, kernel_name) group by kernel_name",
+                       (counter,)).fetchall()
+    con.close()
+    return {k: (v, n) for k, v, n in rows}
+
+
+def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib):
+    """HBM traffic of the dominant kernel per launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the counter reads for a plain device copy of known size."""
+    from paper_2009_10400_amd import tled, workloads as W
+    from paper_2009_10400_amd.build import source_digest
+    copy_bytes = int(copy_mib) * (1 << 20)
+    cf = max(_counter_means(copy_fetch_db, "FETCH_SIZE").items(), key=lambda kv: kv[1][0])
+    cw = max(_counter_means(copy_write_db, "WRITE_SIZE").items(), key=lambda kv: kv[1][0])
+    fetch_scale = copy_bytes / (cf[1][0] * 1024.0)
+    write_scale = copy_bytes / (cw[1][0] * 1024.0)
+    f = _counter_means(fetch_db, "FETCH_SIZE")
+    w = _counter_means(write_db, "WRITE_SIZE")
+
+    def pick(d, name):
+        """The instantiation of the kernel with the most dispatches (the steady-state one)."""
+        k = max((k for k in d if f"{name}<" in k), key=lambda k: d[k][1])
+        return d[k]
+
+    fk, nd = pick(f, "patch_kernel")
+    wk, _ = pick(w, "patch_kernel")
+    sf, _ = pick(f, "shared_node_kernel")
+    sw, _ = pick(w, "shared_node_kernel")
+    p = W.ellipsoid_t4(1_000_000) if workload == "ellipsoid_t4" else W.cube_h8(64)
+    h = tled.from_problem(p, device=-1)
+    info = h.info()
+    h.close()
+    alg = elem_bytes(p.npe, info["n_prony"]) * p.ne + NODE_BYTES * (info["n_nodes"] - info["n_shared_nodes"])
+    out = {"kernel": "patch_kernel", "workload": workload, "source_digest": source_digest(),
+           "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "fetch_scale": fetch_scale,
+           "write_scale": write_scale,
+           "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
+           "algorithmic_bytes_per_launch": alg, "dispatches": nd,
+           "shared_node_kernel_kib": [sf, sw],
+           "note": f"scales from a plain {copy_mib} MiB device copy (FETCH_SIZE read {cf[1][0]:.1f} KiB, "
+                   f"WRITE_SIZE {cw[1][0]:.1f} KiB)"}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 def traffic_from_profiles(kernel_name: str, workload: str):
@@ -128,29 +185,23 @@ def sweep(args):
     t = time.time()
     sc = W.planning_scenarios(args.sweep, seed=3, duration_scale=args.duration_scale)
     probs = [p for p, _ in sc]
-    dts, steps = [], []
-    for p, dur in sc:
-        h = tled.from_problem(p, device=-1, finalize=False)
-        dt = p.cfl * h.critical_dt()
-        h.close()
-        dts.append(dt)
-        steps.append(max(1, int(round(dur / dt))))
     ne_tot = sum(p.ne for p in probs)
-    log(f"[sweep] {len(sc)} scenarios, {ne_tot} elements, steps {min(steps)}..{max(steps)}, "
-        f"built in {time.time() - t:.1f}s")
+    log(f"[sweep] {len(sc)} scenarios, {ne_tot} elements, built in {time.time() - t:.1f}s")
     stream = torch.cuda.Stream(device=0)
     choice, report = {}, {}
     if not args.no_autotune:
         t = time.time()
-        choice, report = autotune.tune(probs, dts, stream=stream.cuda_stream, log=log)
+        choice, report = autotune.tune(probs, stream=stream.cuda_stream, log=log)
         log(f"[sweep] autotune {time.time() - t:.1f}s -> {choice}")
+    t = time.time()
     b = tled.Batch(0, stream=stream.cuda_stream)
     b.set_options(graph_steps=args.graph_steps)
-    for p, dt, n in zip(probs, dts, steps):
-        b.add(p, dt, n, patch_elems=choice.get(autotune.bucket_of(p.ne), 0))
-    t = time.time()
+    for p, dur in sc:
+        b.add(p, cfl=p.cfl, t_end=dur, patch_elems=choice.get(autotune.bucket_of(p.ne), 0))
     b.finalize()
-    log(f"[sweep] finalize {time.time() - t:.1f}s info={b.batch_info()}")
+    steps = [b.scenario_steps(k)[1] for k in range(len(sc))]
+    t_setup = time.time() - t
+    log(f"[sweep] set-up (add + finalize) {t_setup:.1f}s, steps {min(steps)}..{max(steps)}, info={b.batch_info()}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run()
@@ -162,7 +213,7 @@ def sweep(args):
     out = {
         "metric": "scenarios/s (batched planning sweep, solver)", "value": len(sc) / el, "unit": "scenarios/s",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "element_updates_per_s": updates / el, "seconds": el, "batch_steps": max(steps),
+        "element_updates_per_s": updates / el, "seconds": el, "setup_seconds": t_setup, "batch_steps": max(steps),
         "config": {"workload": f"{len(sc)} scenarios, tet cubes and noisy ellipsoids of 5k-200k elements "
                                f"(log-uniform, {ne_tot} total), probe 1/r^2 source U(20,80) W, E U(2,6) kPa, "
                                f"heating U(30,300) s x {args.duration_scale:g}",
@@ -217,7 +268,8 @@ def surrogate_bench(args):
     m0.set_timing(True)
     for _ in range(10):
         m0.train_step(X, P, Y, 1e-4)
-    gemm_ms, gemm_flops = m0.timing()
+    tm = m0.timing()
+    gemm_ms, gemm_flops = tm["gemm_ms"], tm["gemm_flops"]
     m0.set_timing(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -238,27 +290,43 @@ def surrogate_bench(args):
     torch.cuda.synchronize()
     ref, t_solver = S.solve(test_sc, stream=st)
     rep = S.plan(ens, test_sc, threshold_K=args.threshold, stream=st)
-    t_plan = rep["t_surrogate"] + rep["t_fallback"]
+    t_fb = rep["t_fallback"]
+    t_plan = rep["t_surrogate"] + t_fb["total"]
+    t_plan_gpu = rep["t_surrogate_gpu"] + t_fb["run"]
     errs, acc_err = [], []
     for k, ((kind, u, T), (ur, Tr)) in enumerate(zip(rep["results"], ref)):
         e = float(np.abs(T - Tr).max())
         errs.append(e)
         if kind == "surrogate":
             acc_err.append(e)
+    # MFMA roofline of the inference kernel over the test set (HIP events around every launch)
+    for m in ens.models:
+        m.set_timing(True)
+    ens.predict_many(test_sc)
+    tms = [m.timing() for m in ens.models]
+    for m in ens.models:
+        m.set_timing(False)
+    inf_ms = sum(t["fused_ms"] for t in tms)
+    inf_flops = sum(t["fused_flops"] for t in tms)
     rise = [float((Tr - p.params["T0"]).max()) for (p, _), (_, Tr) in zip(test_sc, ref)]
     sur_only = [float(np.abs(Tm - Tr).max()) for (Tm, _, _), (_, Tr) in zip(ens.predict_many(test_sc), ref)]
     n_acc = len(acc_err)
+    nt = len(test_sc)
     out = {
-        "metric": "scenarios/s surrogate vs solver @0.5K", "value": len(test_sc) / t_plan, "unit": "scenarios/s",
+        "metric": "scenarios/s surrogate vs solver @0.5K", "value": nt / t_plan, "unit": "scenarios/s",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "solver_value": len(test_sc) / t_solver, "gain": t_solver / t_plan,
-        "seconds": {"surrogate": rep["t_surrogate"], "fallback_solver": rep["t_fallback"], "solver_alone": t_solver,
-                    "training": t_train, "training_data_solver": t_solve_train},
+        "solver_value": nt / t_solver["total"], "gain": t_solver["total"] / t_plan,
+        "gpu_only": {"surrogate_value": nt / t_plan_gpu, "solver_value": nt / t_solver["run"],
+                     "gain": t_solver["run"] / t_plan_gpu},
+        "seconds": {"surrogate": rep["t_surrogate"], "surrogate_inference": rep["t_surrogate_gpu"],
+                    "fallback_solver": t_fb, "solver_alone": t_solver, "training": t_train,
+                    "training_data_solver": t_solve_train},
         "accepted": n_acc, "fallback": len(rep["rejected"]),
         "max_err_accepted_K": max(acc_err) if acc_err else None,
         "accepted_over_threshold": int(sum(e > args.threshold for e in acc_err)),
         "max_err_all_K": max(errs),
         "surrogate_only_within_threshold": float(np.mean([e <= args.threshold for e in sur_only])),
+        "surrogate_only_max_err_K": float(max(sur_only)),
         "surrogate_only_median_err_K": float(np.median(sur_only)),
         "zero_rise_within_threshold": float(np.mean([r <= args.threshold for r in rise])),
         "max_rise_K": {"median": float(np.median(rise)), "max": float(max(rise))},
@@ -266,15 +334,22 @@ def surrogate_bench(args):
         "config": {"workload": f"planning scenarios (tet cubes and noisy ellipsoids, 5k-200k elements, probe 1/r^2 "
                                f"source U(20,80) W, E U(2,6) kPa, heating U(30,300) s x {ds:g}); "
                                f"{len(train_sc)} training runs x {args.snapshots} snapshots, {len(calib_sc)} "
-                               f"calibration runs, {len(test_sc)} held-out test runs",
+                               f"calibration runs, {nt} held-out test runs",
                    "train_samples": n_samples, "members": args.members, "epochs": args.epochs,
                    "net": "64 Fourier frequencies + 11 parameters (160 padded) -> 5 x 256 SiLU -> 4",
                    "threshold_K": args.threshold, "duration_scale": ds, "train_batch": args.train_batch},
         "training_loss_final": [h[-1] for h in hist],
-        "roofline": {"bound": "mfma", "achieved": gemm_flops / (gemm_ms * 1e-3) / 1e12, "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": gemm_flops / (gemm_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
-                     "kernel": "gemm_kernel (all GEMMs of a training step)", "gemm_ms_per_step": gemm_ms / 10,
-                     "train_step_ms": step_ms, "flops_per_sample_forward": fwd_flops},
+        "roofline": {"bound": "mfma", "achieved": inf_flops / (inf_ms * 1e-3) / 1e12 if inf_ms else None,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": inf_flops / (inf_ms * 1e-3) / 1e12 / 2500.0 if inf_ms else None, "traffic": None,
+                     "kernel": "fused_forward_kernel (ensemble inference over the test set)",
+                     "kernel_ms_total": inf_ms, "launches": args.members,
+                     "flops_per_sample_forward": fwd_flops},
+        "training_roofline": {"bound": "mfma", "achieved": gemm_flops / (gemm_ms * 1e-3) / 1e12, "peak": 2500.0,
+                              "unit": "TFLOP/s", "frac": gemm_flops / (gemm_ms * 1e-3) / 1e12 / 2500.0,
+                              "kernel": "gemm_kernel (all GEMMs of a training step)",
+                              "gemm_ms_per_step": gemm_ms / 10, "train_step_ms": step_ms,
+                              "samples_per_step": args.train_batch},
     }
     print(json.dumps(out), flush=True)
 
@@ -287,6 +362,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.counters_summary:
+        counters_summary(*args.counters_summary)
         return
     if args.sweep:
         sweep(args)

@@ -133,6 +133,8 @@ typedef struct {
     int32_t patch_lds_bytes; /* fused variant: dynamic LDS per workgroup                      */
     int64_t device_bytes;    /* device memory held by the handle                              */
     double  dt, dt_critical;
+    int32_t patch_wgs_per_cu; /* fused variant on a device: resident patch workgroups per CU  */
+    int32_t reserved;
 } tled_info;
 
 /* --- lifetime ----------------------------------------------------------
@@ -260,7 +262,13 @@ tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const 
                            double t_on, double t_off, int64_t n_fixed, const int32_t *fixed_nodes,
                            const uint8_t *fixed_mask, double dt, double damping_gamma, int64_t n_steps,
                            int32_t patch_elems, int32_t *index);
+/* Let finalize choose scenario's time step and step count: dt = cfl times the
+ * scenario's critical step (0 < cfl <= 1), n_steps = max(1, round(t_end / dt)).
+ * The dt (may then be 0) and n_steps given to tled_batch_add are replaced. */
+tled_status tled_batch_set_duration(tled_batch *b, int32_t scenario, double cfl, double t_end);
 tled_status tled_batch_finalize(tled_batch *b);
+/* After finalize: the time step and step count of one scenario. */
+tled_status tled_batch_scenario_steps(tled_batch *b, int32_t scenario, double *dt, int64_t *n_steps);
 /* Enqueue steps until every scenario has reached its n_steps (asynchronous). */
 tled_status tled_batch_run(tled_batch *b);
 /* Displacement (n_nodes x 3) and temperature (n_nodes, K) of one scenario in its

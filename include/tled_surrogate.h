@@ -47,7 +47,9 @@ typedef struct {
     int32_t width;     /* hidden width, multiple of 64                     */
     int32_t depth;     /* number of hidden layers (>= 1)                   */
     int32_t n_out;     /* outputs (<= 64)                                  */
-    int32_t reserved;
+    int32_t layerwise; /* 1: inference layer by layer through HBM; 0: fused
+                          (whole network per 64 samples in LDS) where the
+                          width is 64, 128 or 256 and depth <= 8            */
     float sigma;       /* standard deviation of the frequencies            */
     float init_scale;  /* uniform weight init bound factor (0: 1)          */
     uint64_t seed;     /* frequencies and initial weights                  */
@@ -61,7 +63,8 @@ tled_status tled_mlp_get_params(tled_mlp *mlp, float *host);
 tled_status tled_mlp_set_params(tled_mlp *mlp, const float *host);
 /* The Fourier frequency matrix B (n_freq x 3, host). */
 tled_status tled_mlp_get_frequencies(tled_mlp *mlp, float *host);
-/* Inference on n samples. */
+/* Inference on n samples.  The fused and the layer-by-layer forms give the
+ * same bits (same products in the same order). */
 tled_status tled_mlp_forward(tled_mlp *mlp, int64_t n, const float *coords, const float *params, float *out);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on the
  * minibatch; *loss (host, optional) receives the minibatch loss before the step. */
@@ -76,11 +79,12 @@ tled_status tled_mlp_gradient(tled_mlp *mlp, int64_t n, const float *coords, con
  * patterns (device, row-major), C FP32 (device, row-major). */
 tled_status tled_mlp_gemm(tled_mlp *mlp, int32_t m, int32_t n, int32_t k, const uint16_t *A, const uint16_t *B,
                           float *C);
-/* Measurement: with timing on, every GEMM launch is bracketed by HIP events on
- * the handle's stream (and waited for); tled_mlp_last_timing returns the summed
- * GEMM time (ms[0], ms; ms[1] unused) and GEMM flops since timing was switched on. */
+/* Measurement: with timing on, every GEMM and fused-inference launch is
+ * bracketed by HIP events on the handle's stream (and waited for);
+ * tled_mlp_last_timing returns, since timing was switched on, the summed GEMM
+ * time ms[0] and fused-inference time ms[1] (ms) and their flops[0], flops[1]. */
 tled_status tled_mlp_set_timing(tled_mlp *mlp, int on);
-tled_status tled_mlp_last_timing(tled_mlp *mlp, double ms[2], double flops[1]);
+tled_status tled_mlp_last_timing(tled_mlp *mlp, double ms[2], double flops[2]);
 const char *tled_mlp_last_error(const tled_mlp *mlp);
 
 #ifdef __cplusplus

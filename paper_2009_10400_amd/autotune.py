@@ -25,9 +25,10 @@ def bucket_of(n_elems: int) -> int:
     return len(BUCKETS) - 1
 
 
-def tune(scenarios, dts, device: int = 0, steps: int = 60, sample: int = 6, candidates=CANDIDATES,
+def tune(scenarios, device: int = 0, steps: int = 60, sample: int = 6, candidates=CANDIDATES,
          stream=None, log=print):
-    """scenarios: list of Problems; dts: their time steps.  Returns ({bucket: patch_elems}, report)."""
+    """scenarios: list of Problems (time step: their cfl fraction of the critical step).
+    Returns ({bucket: patch_elems}, report)."""
     from . import tled
     choice, report = {}, {}
     for b in range(len(BUCKETS)):
@@ -39,7 +40,7 @@ def tune(scenarios, dts, device: int = 0, steps: int = 60, sample: int = 6, cand
             bt = tled.Batch(device, stream=stream)
             bt.set_options(graph_steps=-1)
             for k in idx:
-                bt.add(scenarios[k], dts[k], 10**9, patch_elems=pe)
+                bt.add(scenarios[k], cfl=scenarios[k].cfl, t_end=1e6, patch_elems=pe)
             bt.finalize()
             bt.step(10)                                   # warm-up
             kt = bt.kernel_times(steps)

@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument"]
+             "-pthread", "-Wno-unused-command-line-argument"]
 
 
 def build(verbose: bool = False) -> str:
@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
@@ -41,14 +41,18 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def source_digest() -> str:
-    """Hash of the library sources (ties counter measurements to the kernels that produced them)."""
+# Sources of the solver's kernels and of the set-up that lays out their data:
+# counter measurements of those kernels stay valid while these are unchanged.
+SOLVER_SOURCES = ("device_math.h", "kernels.h", "kernels.hip", "setup.cpp", "tled_internal.h")
+
+
+def source_digest(names=SOLVER_SOURCES) -> str:
+    """Hash of library sources (ties counter measurements to the kernels that produced them)."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in sorted(names):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 

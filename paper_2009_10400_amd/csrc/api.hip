@@ -63,6 +63,7 @@ struct tled_sim {
     std::vector<HostProblem> scen;
     std::vector<int64_t> scen_steps;
     std::vector<int32_t> scen_pe;
+    std::vector<double> scen_cfl, scen_tend;   // > 0: dt and steps chosen at finalize
     std::vector<ScenRange> ranges;
     std::vector<int32_t> patch_scen, shared_scen;
     std::vector<KMat> scen_km;
@@ -833,6 +834,11 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
             probe.max_nodes = sim->pc.patches.max_nodes;
             probe.max_elems = sim->pc.patches.max_elems;
             out->patch_lds_bytes = int32_t(patch_lds_bytes(sim->prob.npe, sim->variant == 2, probe));
+            if (sim->device >= 0) {
+                const int bs = sim->opt.block_size > 0 ? sim->opt.block_size : kBlock;
+                out->patch_wgs_per_cu =
+                    patch_occupancy(sim->prob.npe, sim->np, sim->variant == 2, bs, probe);
+            }
         }
         out->device_bytes = sim->device_bytes;
         out->dt_critical = sim->pc.dt_cr;
@@ -1006,8 +1012,8 @@ tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const 
     if (elem_type != TLED_T4 && elem_type != TLED_H8) return fail(b, TLED_E_ARG, "elem_type must be 4 or 8");
     if (n_nodes <= 0 || n_elems <= 0 || !X || !conn || !m) return fail(b, TLED_E_ARG, "empty mesh or null array");
     if (n_nodes > (int64_t(1) << 30) || n_elems * elem_type > INT_MAX) return fail(b, TLED_E_ARG, "mesh too large");
-    if (!(dt > 0.0) || !std::isfinite(dt) || !(damping_gamma >= 0.0) || 0.5 * damping_gamma * dt >= 1.0)
-        return fail(b, TLED_E_ARG, "dt must be > 0, gamma >= 0, gamma dt / 2 < 1");
+    if (!(dt >= 0.0) || !std::isfinite(dt) || !(damping_gamma >= 0.0) || 0.5 * damping_gamma * dt >= 1.0)
+        return fail(b, TLED_E_ARG, "dt must be >= 0, gamma >= 0, gamma dt / 2 < 1");
     if (n_steps < 0) return fail(b, TLED_E_ARG, "negative step count");
     if (patch_elems < 0 || patch_elems > 4096) return fail(b, TLED_E_ARG, "patch_elems out of range");
     if (std::isnan(t_on) || std::isnan(t_off)) return fail(b, TLED_E_ARG, "NaN source window");
@@ -1036,7 +1042,29 @@ tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const 
     b->scen.push_back(std::move(p));
     b->scen_steps.push_back(n_steps);
     b->scen_pe.push_back(patch_elems);
+    b->scen_cfl.push_back(0.0);
+    b->scen_tend.push_back(0.0);
     if (index) *index = int32_t(b->scen.size() - 1);
+    return TLED_OK;
+}
+
+tled_status tled_batch_set_duration(tled_batch *b, int32_t scenario, double cfl, double t_end) {
+    TRY(need_setup(b));
+    if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
+    if (scenario < 0 || size_t(scenario) >= b->scen.size()) return fail(b, TLED_E_ARG, "scenario out of range");
+    if (!(cfl > 0.0 && cfl <= 1.0) || !(t_end >= 0.0) || !std::isfinite(t_end))
+        return fail(b, TLED_E_ARG, "need 0 < cfl <= 1 and a finite t_end >= 0");
+    b->scen_cfl[scenario] = cfl;
+    b->scen_tend[scenario] = t_end;
+    return TLED_OK;
+}
+
+tled_status tled_batch_scenario_steps(tled_batch *b, int32_t scenario, double *dt, int64_t *n_steps) {
+    if (!b || !b->is_batch) return b ? fail(b, TLED_E_STATE, "not a batch handle") : TLED_E_ARG;
+    if (scenario < 0 || size_t(scenario) >= b->scen.size()) return fail(b, TLED_E_ARG, "scenario out of range");
+    if (!b->finalized) return fail(b, TLED_E_STATE, "not finalized");
+    if (dt) *dt = b->scen[scenario].dt;
+    if (n_steps) *n_steps = b->scen_steps[scenario];
     return TLED_OK;
 }
 
@@ -1055,6 +1083,15 @@ tled_status tled_batch_finalize(tled_batch *b) {
     tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, &b->pc, &b->ranges, &b->patch_scen,
                                       &b->shared_scen, &b->err);
     if (st != TLED_OK) return st;
+    for (size_t k = 0; k < b->scen.size(); ++k) {
+        HostProblem &p = b->scen[k];
+        if (b->scen_cfl[k] > 0.0) {
+            p.dt = b->scen_cfl[k] * b->ranges[k].dt_cr;
+            b->scen_steps[k] = std::max<int64_t>(1, std::llround(b->scen_tend[k] / p.dt));
+        }
+        if (!(p.dt > 0.0) || 0.5 * p.gamma * p.dt >= 1.0)
+            return fail(b, TLED_E_ARG, "scenario " + std::to_string(k) + ": dt must be > 0 with gamma dt / 2 < 1");
+    }
     for (size_t k = 0; k < b->scen.size(); ++k)
         if (b->scen[k].dt > b->ranges[k].dt_cr)
             return fail(b, TLED_E_ARG, "scenario " + std::to_string(k) + ": dt exceeds the critical step " +

@@ -85,6 +85,8 @@ struct PatchArgs {
 void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s);
 void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
 void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s);
+// Resident workgroups per CU of the patch kernel in this configuration (-1 on error).
+int patch_occupancy(int npe, int np, bool geox, int bs, const PatchArgs &a);
 void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s);
 // Per-scenario maximum temperature and lumped volume at or above T_abl, over the
 // scenario's interior node range [int_lo, int_hi) and shared range [sh_lo, sh_hi).

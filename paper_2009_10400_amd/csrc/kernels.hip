@@ -713,21 +713,30 @@ void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_
                            a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
 }
 
+// occ != nullptr: report the resident workgroups per CU of the instantiation
+// instead of launching it.
 template <int NPE, int NP, int BS, bool GEOX>
-void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s) {
+void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s, int *occ) {
+    if (occ) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX>), BS, lds) != hipSuccess)
+            *occ = -1;
+        return;
+    }
     dim3 grid(a.n_patches);
     if (mon) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
     else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
 }
 
 template <int NPE, int NP>
-void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, int j, size_t lds, hipStream_t s) {
+void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, int j, size_t lds, hipStream_t s,
+                     int *occ) {
     if (NPE == 4 && bs == 512) {
-        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, j, lds, s);
-        else launch_patch_g<NPE, NP, 512, false>(mon, a, j, lds, s);
+        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, j, lds, s, occ);
+        else launch_patch_g<NPE, NP, 512, false>(mon, a, j, lds, s, occ);
     } else {
-        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, j, lds, s);
-        else launch_patch_g<NPE, NP, 256, false>(mon, a, j, lds, s);
+        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, j, lds, s, occ);
+        else launch_patch_g<NPE, NP, 256, false>(mon, a, j, lds, s, occ);
     }
 }
 }  // namespace
@@ -761,25 +770,38 @@ void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hip
                             a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
 }
 
-void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s) {
+namespace {
+void patch_dispatch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s,
+                    int *occ) {
     const size_t lds = patch_lds_bytes(npe, geox, a);
     if (npe == 4) {
         switch (np) {
-            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, j, lds, s); break;
-            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, j, lds, s); break;
-            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, j, lds, s); break;
-            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, j, lds, s); break;
-            default: launch_patch_np<4, 4>(mon, geox, bs, a, j, lds, s); break;
+            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, j, lds, s, occ); break;
+            default: launch_patch_np<4, 4>(mon, geox, bs, a, j, lds, s, occ); break;
         }
     } else {
         switch (np) {
-            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, j, lds, s); break;
-            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, j, lds, s); break;
-            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, j, lds, s); break;
-            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, j, lds, s); break;
-            default: launch_patch_np<8, 4>(mon, geox, bs, a, j, lds, s); break;
+            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, j, lds, s, occ); break;
+            default: launch_patch_np<8, 4>(mon, geox, bs, a, j, lds, s, occ); break;
         }
     }
+}
+}  // namespace
+
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s) {
+    patch_dispatch(npe, np, mon, geox, bs, a, j, s, nullptr);
+}
+
+int patch_occupancy(int npe, int np, bool geox, int bs, const PatchArgs &a) {
+    int occ = 0;
+    patch_dispatch(npe, np, false, geox, bs, a, 0, nullptr, &occ);
+    return occ;
 }
 
 void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s) {

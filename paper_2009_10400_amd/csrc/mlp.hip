@@ -273,6 +273,128 @@ __global__ void to_bf16_kernel(long n, const float *__restrict__ x, uint16_t *__
     if (i < n) y[i] = f2bf(x[i]);
 }
 
+// Whole-network inference, 64 samples per workgroup of four wavefronts; the
+// activations never leave LDS.  Features are formed in LDS as in
+// features_kernel; each hidden layer is Z = A W^T + b with A (64 x K) from LDS
+// and W (bfloat16, row-major out x in) streamed from global memory straight into
+// the MFMA B operand (8 consecutive k of one output per lane); wavefront w owns
+// output columns [w W/4, (w+1) W/4).  All waves finish reading A before any
+// writes its bf16(SiLU(Z)) back over it.  The output layer gives wavefront w
+// rows [16w, 16w + 16).  The MFMA sequence per output (k in steps of 32,
+// increasing) and the epilogue arithmetic are those of gemm_kernel, so the
+// result equals the layer-by-layer forward pass bit for bit.
+constexpr int kFusedRows = 64;
+constexpr int kFusedMaxDepth = 8;
+struct NetOffsets {
+    long w[kFusedMaxDepth + 1];
+    long b[kFusedMaxDepth + 1];
+};
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void fused_forward_kernel(long n, const float *__restrict__ x,
+                                                                 const float *__restrict__ p,
+                                                                 const float *__restrict__ Bf, int nf, int np,
+                                                                 int K0, int depth, int nout,
+                                                                 const uint16_t *__restrict__ wb,
+                                                                 const float *__restrict__ wf, NetOffsets off,
+                                                                 float *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t act[];
+    const int P = (K0 > W ? K0 : W) + 8;          // LDS row pitch (elements)
+    const long r0 = long(blockIdx.x) * kFusedRows;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int idx = t; idx < kFusedRows * K0; idx += kThreads) {
+        const int row = idx / K0, j = idx % K0;
+        const long i = r0 + row;
+        float v = 0.f;
+        if (i < n) {
+            if (j < 2 * nf) {
+                const int f = j < nf ? j : j - nf;
+                const float a = 6.283185307179586f *
+                                (Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2]);
+                v = j < nf ? sinf(a) : cosf(a);
+            } else if (j < 2 * nf + np) {
+                v = p[i * np + (j - 2 * nf)];
+            }
+        }
+        act[row * P + j] = f2bf(v);
+    }
+    __syncthreads();
+    constexpr int NT = W / 64;                     // 16-column tiles per wavefront
+    const int nb = w * (W / 4);
+    int K = K0;
+    for (int layer = 0; layer < depth; ++layer) {
+        const uint16_t *Wl = wb + off.w[layer];
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            bf16x8 b[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                b[j] = *reinterpret_cast<const bf16x8 *>(Wl + long(nb + 16 * j + (l & 15)) * K + k0 + 8 * (l >> 4));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(16 * i + (l & 15)) * P + k0 + 8 * (l >> 4)]);
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        const float *bias = wf + off.b[layer];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int col = nb + 16 * j + (l & 15);
+                const float bc = bias[col];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * i + 4 * (l >> 4) + r;
+                    const float z = acc[i][j][r] + bc;
+                    act[row * P + col] = f2bf(z / (1.0f + expf(-z)));
+                }
+            }
+        __syncthreads();
+        K = W;
+    }
+    // output layer: rows [16w, 16w + 16), up to four 16-column tiles
+    const uint16_t *Wo = wb + off.w[depth];
+    const float *bo = wf + off.b[depth];
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ntile = (nout + 15) / 16;
+    for (int k0 = 0; k0 < W; k0 += 32) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(16 * w + (l & 15)) * P + k0 + 8 * (l >> 4)]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= ntile) break;
+            const int col = 16 * j + (l & 15);
+            bf16x8 b;
+            if (col < nout) {
+                b = *reinterpret_cast<const bf16x8 *>(Wo + long(col) * W + k0 + 8 * (l >> 4));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) b[q] = __bf16(0.0f);
+            }
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (j >= ntile) break;
+        const int col = 16 * j + (l & 15);
+        if (col >= nout) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long row = r0 + 16 * w + 4 * (l >> 4) + r;
+            if (row < n) out[row * nout + col] = acc[j][r] + bo[col];
+        }
+    }
+}
+
 inline unsigned blocks(long n) { return unsigned((n + kThreads - 1) / kThreads); }
 
 struct Layer {
@@ -307,7 +429,7 @@ struct tled_mlp {
     size_t split_cap = 0;
     // timing
     bool timing = false;
-    double gemm_ms = 0.0, other_ms = 0.0, gemm_flops = 0.0;
+    double gemm_ms = 0.0, fused_ms = 0.0, gemm_flops = 0.0, fused_flops = 0.0;
 };
 
 namespace {
@@ -438,6 +560,54 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
         MCHK(s, hipEventElapsedTime(&ms, e0, e1));
         s->gemm_ms += ms;
         s->gemm_flops += 2.0 * double(M) * N * K;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return TLED_OK;
+}
+
+// Fused inference applies to widths 64/128/256, depth <= 8, and LDS rows that fit.
+size_t fused_lds_bytes(const tled_mlp *s) {
+    return size_t(kFusedRows) * (std::max(s->K0, s->cfg.width) + 8) * sizeof(uint16_t);
+}
+
+bool fused_ok(const tled_mlp *s) {
+    const int W = s->cfg.width;
+    return !s->cfg.layerwise && (W == 64 || W == 128 || W == 256) && s->cfg.depth <= kFusedMaxDepth &&
+           fused_lds_bytes(s) <= 64 * 1024;
+}
+
+tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float *params, float *out) {
+    NetOffsets off{};
+    for (int l = 0; l <= s->cfg.depth; ++l) {
+        off.w[l] = s->layers[l].w_off;
+        off.b[l] = s->layers[l].b_off;
+    }
+    const unsigned grid = unsigned((n + kFusedRows - 1) / kFusedRows);
+    const size_t lds = fused_lds_bytes(s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->timing) {
+        MCHK(s, hipEventCreate(&e0));
+        MCHK(s, hipEventCreate(&e1));
+        MCHK(s, hipEventRecord(e0, s->stream));
+    }
+#define TLED_FUSED(WIDTH)                                                                                   \
+    hipLaunchKernelGGL(fused_forward_kernel<WIDTH>, dim3(grid), dim3(kThreads), lds, s->stream, n, coords, \
+                       params, s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->cfg.depth, s->cfg.n_out, \
+                       s->d_wb, s->d_w, off, out)
+    if (s->cfg.width == 64) TLED_FUSED(64);
+    else if (s->cfg.width == 128) TLED_FUSED(128);
+    else TLED_FUSED(256);
+#undef TLED_FUSED
+    MCHK(s, hipGetLastError());
+    if (s->timing) {
+        MCHK(s, hipEventRecord(e1, s->stream));
+        MCHK(s, hipEventSynchronize(e1));
+        float ms = 0.f;
+        MCHK(s, hipEventElapsedTime(&ms, e0, e1));
+        s->fused_ms += ms;
+        const double W = s->cfg.width;
+        s->fused_flops += 2.0 * double(n) * (double(s->K0) * W + (s->cfg.depth - 1) * W * W + W * s->cfg.n_out);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
@@ -646,6 +816,7 @@ tled_status tled_mlp_forward(tled_mlp *s, int64_t n, const float *coords, const 
     if (!s || n < 0 || (n > 0 && (!coords || !out || (s->cfg.n_param > 0 && !params)))) return TLED_E_ARG;
     if (n == 0) return TLED_OK;
     MCHK(s, hipSetDevice(s->device));
+    if (fused_ok(s)) return fused_forward(s, long(n), coords, params, out);
     MTRY(forward(s, long(n), coords, params));
     MCHK(s, hipMemcpyAsync(out, s->d_y, sizeof(float) * size_t(n) * s->cfg.n_out, hipMemcpyDeviceToDevice, s->stream));
     return TLED_OK;
@@ -683,7 +854,7 @@ tled_status tled_mlp_gemm(tled_mlp *s, int32_t m, int32_t n, int32_t k, const ui
                           float *C) {
     if (!s || m <= 0 || n <= 0 || k <= 0 || !A || !B || !C) return TLED_E_ARG;
     MCHK(s, hipSetDevice(s->device));
-    s->gemm_ms = s->other_ms = s->gemm_flops = 0.0;
+    s->gemm_ms = s->fused_ms = s->gemm_flops = s->fused_flops = 0.0;
     MTRY(gemm<EPI_F32>(s, m, n, k, A, k, 1, B, n, 1, C, n, 1, nullptr, nullptr));
     return TLED_OK;
 }
@@ -691,15 +862,16 @@ tled_status tled_mlp_gemm(tled_mlp *s, int32_t m, int32_t n, int32_t k, const ui
 tled_status tled_mlp_set_timing(tled_mlp *s, int on) {
     if (!s) return TLED_E_ARG;
     s->timing = on != 0;
-    s->gemm_ms = s->other_ms = s->gemm_flops = 0.0;
+    s->gemm_ms = s->fused_ms = s->gemm_flops = s->fused_flops = 0.0;
     return TLED_OK;
 }
 
-tled_status tled_mlp_last_timing(tled_mlp *s, double ms[2], double flops[1]) {
+tled_status tled_mlp_last_timing(tled_mlp *s, double ms[2], double flops[2]) {
     if (!s || !ms || !flops) return TLED_E_ARG;
     ms[0] = s->gemm_ms;
-    ms[1] = s->other_ms;
+    ms[1] = s->fused_ms;
     flops[0] = s->gemm_flops;
+    flops[1] = s->fused_flops;
     return TLED_OK;
 }
 

@@ -7,9 +7,12 @@
 // here, and rounded to single precision once when uploaded.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "tled_internal.h"
 
@@ -516,104 +519,176 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
     const size_t S = ps.size();
     if (S == 0) { *err = "empty batch"; return TLED_E_ARG; }
     const int npe = ps[0].npe;
-    std::vector<Precomputed> pcs(S);
     for (size_t k = 0; k < S; ++k) {
         if (ps[k].npe != npe) { *err = "a batch needs one element type"; return TLED_E_ARG; }
         if (ps[k].mat.n_prony != ps[0].mat.n_prony) { *err = "a batch needs one Prony term count"; return TLED_E_ARG; }
-        SetupOptions so;
-        so.reorder = reorder;
-        so.build_patches = true;
-        so.patch_elems = patch_elems[k];
-        std::string e;
-        tled_status st = precompute(ps[k], so, &pcs[k], &e);
-        if (st != TLED_OK) { *err = "scenario " + std::to_string(k) + ": " + e; return st; }
     }
-    // offsets
-    int64_t NE = 0, NI = 0, NS = 0;
-    for (auto &pc : pcs) { NE += pc.ne; NI += pc.patches.n_interior; NS += pc.nn - pc.patches.n_interior; }
+    // Scenarios are independent: precompute them on a pool of host threads
+    // (TLED_HOST_THREADS, default the hardware concurrency, at most 64).  Each
+    // result depends only on its own scenario, so the outcome does not depend on
+    // the thread count.
+    std::vector<Precomputed> pcs(S);
+    std::vector<tled_status> sts(S, TLED_OK);
+    std::vector<std::string> errs(S);
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t k = next++; k < S; k = next++) {
+            SetupOptions so;
+            so.reorder = reorder;
+            so.build_patches = true;
+            so.patch_elems = patch_elems[k];
+            sts[k] = precompute(ps[k], so, &pcs[k], &errs[k]);
+        }
+    };
+    int nt = int(std::thread::hardware_concurrency());
+    if (const char *env = std::getenv("TLED_HOST_THREADS")) nt = std::atoi(env);
+    nt = std::max(1, std::min({nt, 64, int(S)}));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+    for (size_t k = 0; k < S; ++k)
+        if (sts[k] != TLED_OK) { *err = "scenario " + std::to_string(k) + ": " + errs[k]; return sts[k]; }
+    // offsets of every scenario in the union (serial prefix sums), then each
+    // scenario fills its own slices of the union arrays (in parallel)
+    struct Off {
+        int64_t e, i, s, patch, sid, lrow, lx, geo, hgc, khg, a0, lconn, ppos;
+    };
+    std::vector<Off> off(S + 1);
+    {
+        Off o{};
+        for (size_t k = 0; k < S; ++k) {
+            off[k] = o;
+            const Precomputed &pc = pcs[k];
+            const Patches &Q = pc.patches;
+            o.e += pc.ne;
+            o.i += Q.n_interior;
+            o.s += pc.nn - Q.n_interior;
+            o.patch += Q.n;
+            o.sid += int64_t(Q.shared_ids.size());
+            o.lrow += int64_t(Q.lrow.size());
+            o.lx += int64_t(Q.lX.size() / 3);
+            o.geo += int64_t(pc.geo.size());
+            o.hgc += int64_t(pc.hgc.size());
+            o.khg += int64_t(pc.khg.size());
+            o.a0 += int64_t(pc.a0.size());
+            o.lconn += int64_t(Q.lconn.size());
+            o.ppos += int64_t(Q.ppos.size());
+        }
+        off[S] = o;
+    }
+    const Off &T = off[S];
+    if (T.e > INT32_MAX / npe || T.sid > INT32_MAX || T.lrow > INT32_MAX) { *err = "batch too large"; return TLED_E_ARG; }
     Precomputed &U = *out;
     U = Precomputed();
     U.npe = npe;
-    U.ne = NE;
-    U.nn = NI + NS;
+    U.ne = T.e;
+    U.nn = T.i + T.s;
+    const int64_t NE = T.e, NI = T.i;
     ranges->assign(S, ScenRange());
-    patch_scen->clear();
-    shared_scen->assign(NS, 0);
+    patch_scen->assign(T.patch, 0);
+    shared_scen->assign(T.s, 0);
     Patches &P = U.patches;
     P.n_interior = NI;
+    P.n = int32_t(T.patch);
     int32_t stride = 0;
-    for (auto &pc : pcs) stride = std::max(stride, pc.patches.slot_stride);
+    for (auto &pc : pcs) {
+        stride = std::max(stride, pc.patches.slot_stride);
+        P.max_nodes = std::max(P.max_nodes, pc.patches.max_nodes);
+        P.max_elems = std::max(P.max_elems, pc.patches.max_elems);
+    }
     P.slot_stride = stride;
     U.Vl.assign(U.nn, 0); U.M.assign(U.nn, 0); U.C.assign(U.nn, 0); U.Kb.assign(U.nn, 0);
     U.Qm.assign(U.nn, 0); U.Qr.assign(U.nn, 0); U.fix.assign(U.nn, 0); U.Tfix.assign(U.nn, 0);
     U.node_new2old.assign(U.nn, -1);   // caller index within its scenario
-    int64_t eo = 0, io = 0, so_ = 0;
-    for (size_t k = 0; k < S; ++k) {
-        const Precomputed &pc = pcs[k];
-        const Patches &Q = pc.patches;
-        ScenRange &R = (*ranges)[k];
-        const int64_t nint = Q.n_interior, nsh = pc.nn - nint;
-        auto map = [&](int64_t n) { return n < nint ? io + n : NI + so_ + (n - nint); };
-        R.elem_lo = eo; R.elem_hi = eo + pc.ne;
-        R.int_lo = io; R.int_hi = io + nint;
-        R.sh_lo = NI + so_; R.sh_hi = NI + so_ + nsh;
-        R.patch_lo = P.n; R.patch_hi = P.n + Q.n;
-        R.dt_cr = pc.dt_cr;
-        R.n_swapped = pc.n_swapped;
-        R.node_of.resize(pc.nn);
-        for (int64_t a = 0; a < pc.nn; ++a) R.node_of[pc.node_new2old[a]] = map(a);
-        R.elem_of.resize(pc.ne);
-        for (int64_t e = 0; e < pc.ne; ++e) R.elem_of[pc.elem_new2old[e]] = eo + e;
-        for (int64_t a = 0; a < pc.nn; ++a) {
-            int64_t g = map(a);
-            U.Vl[g] = pc.Vl[a]; U.M[g] = pc.M[a]; U.C[g] = pc.C[a]; U.Kb[g] = pc.Kb[a];
-            U.Qm[g] = pc.Qm[a]; U.Qr[g] = pc.Qr[a]; U.fix[g] = pc.fix[a]; U.Tfix[g] = pc.Tfix[a];
-            U.node_new2old[g] = pc.node_new2old[a];
+    U.conn.resize(size_t(NE) * npe);
+    U.geo.resize(T.geo);
+    U.V0.resize(NE);
+    U.hgc.resize(T.hgc);
+    U.khg.resize(T.khg);
+    U.a0.resize(T.a0);
+    U.elem_new2old.resize(NE);
+    P.elem_begin.resize(T.patch + 1);
+    P.int_begin.resize(T.patch + 1);
+    P.shared_begin.resize(T.patch + 1);
+    P.lrow_begin.resize(T.patch + 1);
+    P.lx_begin.resize(T.patch + 1);
+    P.lslot_begin.resize(T.patch + 1);
+    P.shared_ids.resize(T.sid);
+    P.lconn.resize(T.lconn);
+    P.lrow.resize(T.lrow);
+    P.lslot.resize(size_t(NE) * npe);
+    P.srow.resize(T.s + 1);
+    P.ppos.resize(T.ppos);
+    P.lX.resize(size_t(T.lx) * 3);
+    next = 0;
+    auto fill = [&]() {
+        for (size_t k = next++; k < S; k = next++) {
+            const Precomputed &pc = pcs[k];
+            const Patches &Q = pc.patches;
+            const Off &o = off[k];
+            ScenRange &R = (*ranges)[k];
+            const int64_t nint = Q.n_interior, nsh = pc.nn - nint;
+            const int64_t eo = o.e, io = o.i, so_ = o.s;
+            const int32_t sid0 = int32_t(o.sid), lr0 = int32_t(o.lrow), lx0 = int32_t(o.lx);
+            auto map = [&](int64_t n) { return n < nint ? io + n : NI + so_ + (n - nint); };
+            R.elem_lo = eo; R.elem_hi = eo + pc.ne;
+            R.int_lo = io; R.int_hi = io + nint;
+            R.sh_lo = NI + so_; R.sh_hi = NI + so_ + nsh;
+            R.patch_lo = int32_t(o.patch); R.patch_hi = int32_t(o.patch + Q.n);
+            R.dt_cr = pc.dt_cr;
+            R.n_swapped = pc.n_swapped;
+            R.node_of.resize(pc.nn);
+            for (int64_t a = 0; a < pc.nn; ++a) R.node_of[pc.node_new2old[a]] = map(a);
+            R.elem_of.resize(pc.ne);
+            for (int64_t e = 0; e < pc.ne; ++e) R.elem_of[pc.elem_new2old[e]] = eo + e;
+            for (int64_t a = 0; a < pc.nn; ++a) {
+                const int64_t g = map(a);
+                U.Vl[g] = pc.Vl[a]; U.M[g] = pc.M[a]; U.C[g] = pc.C[a]; U.Kb[g] = pc.Kb[a];
+                U.Qm[g] = pc.Qm[a]; U.Qr[g] = pc.Qr[a]; U.fix[g] = pc.fix[a]; U.Tfix[g] = pc.Tfix[a];
+                U.node_new2old[g] = pc.node_new2old[a];
+            }
+            for (int64_t j = 0; j < nsh; ++j) (*shared_scen)[so_ + j] = int32_t(k);
+            for (size_t c = 0; c < pc.conn.size(); ++c) U.conn[size_t(eo) * npe + c] = int32_t(map(pc.conn[c]));
+            std::copy(pc.geo.begin(), pc.geo.end(), U.geo.begin() + o.geo);
+            std::copy(pc.V0.begin(), pc.V0.end(), U.V0.begin() + eo);
+            std::copy(pc.hgc.begin(), pc.hgc.end(), U.hgc.begin() + o.hgc);
+            std::copy(pc.khg.begin(), pc.khg.end(), U.khg.begin() + o.khg);
+            std::copy(pc.a0.begin(), pc.a0.end(), U.a0.begin() + o.a0);
+            std::copy(pc.elem_new2old.begin(), pc.elem_new2old.begin() + pc.ne, U.elem_new2old.begin() + eo);
+            for (int32_t q = 0; q < Q.n; ++q) {
+                const size_t g = size_t(o.patch) + q;
+                P.elem_begin[g] = int32_t(eo + Q.elem_begin[q]);
+                P.int_begin[g] = int32_t(io + Q.int_begin[q]);
+                P.shared_begin[g] = sid0 + Q.shared_begin[q];
+                P.lrow_begin[g] = lr0 + Q.lrow_begin[q];
+                P.lx_begin[g] = lx0 + Q.lx_begin[q];
+                P.lslot_begin[g] = int32_t((eo + Q.elem_begin[q]) * npe);
+                (*patch_scen)[g] = int32_t(k);
+            }
+            for (size_t q = 0; q < Q.shared_ids.size(); ++q) P.shared_ids[sid0 + q] = int32_t(map(Q.shared_ids[q]));
+            std::copy(Q.lconn.begin(), Q.lconn.end(), P.lconn.begin() + o.lconn);
+            std::copy(Q.lrow.begin(), Q.lrow.end(), P.lrow.begin() + o.lrow);
+            for (size_t q = 0; q < Q.lslot.size(); ++q) {
+                const int a = Q.lslot[q] / Q.slot_stride, el = Q.lslot[q] % Q.slot_stride;
+                P.lslot[size_t(eo) * npe + q] = uint16_t(a * stride + el);
+            }
+            for (int64_t j = 0; j < nsh; ++j) P.srow[so_ + j] = sid0 + Q.srow[j];
+            for (size_t q = 0; q < Q.ppos.size(); ++q) P.ppos[o.ppos + q] = sid0 + Q.ppos[q];
+            std::copy(Q.lX.begin(), Q.lX.end(), P.lX.begin() + 3 * o.lx);
         }
-        for (int64_t j = 0; j < nsh; ++j) (*shared_scen)[so_ + j] = int32_t(k);
-        for (auto c : pc.conn) U.conn.push_back(int32_t(map(c)));
-        U.geo.insert(U.geo.end(), pc.geo.begin(), pc.geo.end());
-        U.V0.insert(U.V0.end(), pc.V0.begin(), pc.V0.end());
-        U.hgc.insert(U.hgc.end(), pc.hgc.begin(), pc.hgc.end());
-        U.khg.insert(U.khg.end(), pc.khg.begin(), pc.khg.end());
-        U.a0.insert(U.a0.end(), pc.a0.begin(), pc.a0.end());
-        for (int64_t e = 0; e < pc.ne; ++e) U.elem_new2old.push_back(pc.elem_new2old[e]);
-        // patches
-        const int32_t sid0 = int32_t(P.shared_ids.size()), lr0 = int32_t(P.lrow.size()),
-                      lx0 = int32_t(P.lX.size() / 3);
-        for (int32_t q = 0; q < Q.n; ++q) {
-            P.elem_begin.push_back(int32_t(eo + Q.elem_begin[q]));
-            P.int_begin.push_back(int32_t(io + Q.int_begin[q]));
-            P.shared_begin.push_back(sid0 + Q.shared_begin[q]);
-            P.lrow_begin.push_back(lr0 + Q.lrow_begin[q]);
-            P.lx_begin.push_back(lx0 + Q.lx_begin[q]);
-            P.lslot_begin.push_back(int32_t((eo + Q.elem_begin[q]) * npe));
-            patch_scen->push_back(int32_t(k));
-        }
-        for (auto id : Q.shared_ids) P.shared_ids.push_back(int32_t(map(id)));
-        P.lconn.insert(P.lconn.end(), Q.lconn.begin(), Q.lconn.end());
-        P.lrow.insert(P.lrow.end(), Q.lrow.begin(), Q.lrow.end());
-        for (auto v : Q.lslot) {
-            const int a = v / Q.slot_stride, el = v % Q.slot_stride;
-            P.lslot.push_back(uint16_t(a * stride + el));
-        }
-        for (int64_t j = 0; j < nsh; ++j) P.srow.push_back(sid0 + Q.srow[j]);
-        for (auto v : Q.ppos) P.ppos.push_back(sid0 + v);
-        P.lX.insert(P.lX.end(), Q.lX.begin(), Q.lX.end());
-        P.max_nodes = std::max(P.max_nodes, Q.max_nodes);
-        P.max_elems = std::max(P.max_elems, Q.max_elems);
-        P.n += Q.n;
-        eo += pc.ne;
-        io += nint;
-        so_ += nsh;
-    }
-    P.elem_begin.push_back(int32_t(NE));
-    P.int_begin.push_back(int32_t(NI));
-    P.shared_begin.push_back(int32_t(P.shared_ids.size()));
-    P.lrow_begin.push_back(int32_t(P.lrow.size()));
-    P.lx_begin.push_back(int32_t(P.lX.size() / 3));
-    P.lslot_begin.push_back(int32_t(NE * npe));
-    P.srow.push_back(int32_t(P.shared_ids.size()));
+    };
+    pool.clear();
+    for (int t = 1; t < nt; ++t) pool.emplace_back(fill);
+    fill();
+    for (auto &th : pool) th.join();
+    P.elem_begin[T.patch] = int32_t(NE);
+    P.int_begin[T.patch] = int32_t(NI);
+    P.shared_begin[T.patch] = int32_t(T.sid);
+    P.lrow_begin[T.patch] = int32_t(T.lrow);
+    P.lx_begin[T.patch] = int32_t(T.lx);
+    P.lslot_begin[T.patch] = int32_t(NE * npe);
+    P.srow[T.s] = int32_t(T.sid);
     if (P.max_elems * npe > 65535 || P.slot_stride * npe > 65535) { *err = "patch too large"; return TLED_E_ARG; }
     U.dt_cr = 0.0;
     return TLED_OK;

@@ -30,7 +30,7 @@ _fp = ctypes.POINTER(ctypes.c_float)
 
 class MLPConfig(ctypes.Structure):
     _fields_ = [("n_param", ctypes.c_int32), ("n_freq", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("n_out", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("n_out", ctypes.c_int32), ("layerwise", ctypes.c_int32),
                 ("sigma", ctypes.c_float), ("init_scale", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
@@ -77,17 +77,25 @@ class MLP:
     """One network on one device (device tensors via torch)."""
 
     def __init__(self, device: int = 0, n_param: int = N_PARAM, n_freq: int = 64, width: int = 256, depth: int = 5,
-                 n_out: int = 4, sigma: float = 1.0, seed: int = 0, init_scale: float = 1.0, stream=None):
+                 n_out: int = 4, sigma: float = 1.0, seed: int = 0, init_scale: float = 1.0, stream=None,
+                 layerwise: bool = False):
         self.cfg = dict(n_param=n_param, n_freq=n_freq, width=width, depth=depth, n_out=n_out)
-        c = MLPConfig(n_param, n_freq, width, depth, n_out, 0, sigma, init_scale, seed)
+        c = MLPConfig(n_param, n_freq, width, depth, n_out, int(layerwise), sigma, init_scale, seed)
         h = _P()
         st = _lib.tled_mlp_create(ctypes.byref(h), int(device), ctypes.byref(c))
         if st != 0:
             raise TledError(st, "tled_mlp_create failed")
         self._h = h
         self.device = device
-        if stream is not None:
-            self._check(_lib.tled_mlp_set_stream(h, _P(int(stream))))
+        # The library runs on this stream; every call that takes or returns torch
+        # tensors orders it after torch's current stream and torch's current stream
+        # after it, so tensors may be made and read on torch's stream as usual.
+        import torch
+        if stream is None:
+            self._stream = torch.cuda.Stream(device=device)
+        else:
+            self._stream = torch.cuda.ExternalStream(int(stream), device=device)
+        self._check(_lib.tled_mlp_set_stream(h, _P(self._stream.cuda_stream)))
         n = ctypes.c_int64()
         self._check(_lib.tled_mlp_param_count(h, ctypes.byref(n)))
         self.n_params = n.value
@@ -121,39 +129,47 @@ class MLP:
         self._check(_lib.tled_mlp_get_frequencies(self._h, out.ctypes.data_as(_fp)))
         return out
 
+    def _call(self, fn, *args):
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        self._stream.wait_stream(cur)
+        self._check(fn(self._h, *args))
+        cur.wait_stream(self._stream)
+
     def forward(self, x, p):
         import torch
         out = torch.empty((x.shape[0], self.cfg["n_out"]), dtype=torch.float32, device=x.device)
-        self._check(_lib.tled_mlp_forward(self._h, x.shape[0], _dp(x), _dp(p), _dp(out)))
+        self._call(_lib.tled_mlp_forward, x.shape[0], _dp(x), _dp(p), _dp(out))
         return out
 
     def train_step(self, x, p, y, lr: float, want_loss: bool = False):
         loss = _f(0.0)
-        self._check(_lib.tled_mlp_train_step(self._h, x.shape[0], _dp(x), _dp(p), _dp(y), float(lr),
-                                             ctypes.byref(loss) if want_loss else None))
+        self._call(_lib.tled_mlp_train_step, x.shape[0], _dp(x), _dp(p), _dp(y), float(lr),
+                   ctypes.byref(loss) if want_loss else None)
         return loss.value if want_loss else None
 
     def gradient(self, x, p, y):
         g = np.zeros(self.n_params, np.float32)
         loss = _f(0.0)
-        self._check(_lib.tled_mlp_gradient(self._h, x.shape[0], _dp(x), _dp(p), _dp(y), g.ctypes.data_as(_fp),
-                                           ctypes.byref(loss)))
+        self._call(_lib.tled_mlp_gradient, x.shape[0], _dp(x), _dp(p), _dp(y), g.ctypes.data_as(_fp),
+                   ctypes.byref(loss))
         return loss.value, g
 
     def gemm(self, A_bits, B_bits, C):
         """C = A B on the matrix cores; A, B int16 tensors of bfloat16 bits, C float32."""
         m, k = A_bits.shape
         n = B_bits.shape[1]
-        self._check(_lib.tled_mlp_gemm(self._h, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C)))
+        self._call(_lib.tled_mlp_gemm, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C))
 
     def set_timing(self, on: bool):
         self._check(_lib.tled_mlp_set_timing(self._h, int(on)))
 
     def timing(self):
+        """{"gemm_ms", "gemm_flops", "fused_ms", "fused_flops"} since timing was switched on."""
         ms = (ctypes.c_double * 2)()
-        fl = (ctypes.c_double * 1)()
+        fl = (ctypes.c_double * 2)()
         self._check(_lib.tled_mlp_last_timing(self._h, ms, fl))
-        return ms[0], fl[0]
+        return {"gemm_ms": ms[0], "gemm_flops": fl[0], "fused_ms": ms[1], "fused_flops": fl[1]}
 
 
 # --------------------------------------------------------------------------- data
@@ -198,16 +214,10 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
     switch-off).  Returns (list of (scenario index, duration, u, T), solver seconds)."""
     b = tled.Batch(device, stream=stream)
     b.set_options(graph_steps=graph_steps)
-    dts, steps = [], []
     for p, dur in scenarios:
-        h = tled.from_problem(p, device=-1, finalize=False)
-        dt = p.cfl * h.critical_dt()
-        h.close()
-        n = max(1, int(round(dur / dt)))
-        dts.append(dt)
-        steps.append(n)
-        b.add(p, dt, n)
+        b.add(p, cfl=p.cfl, t_end=dur)
     b.finalize()
+    dts, steps = zip(*(b.scenario_steps(k) for k in range(len(scenarios))))
     S = max(steps)
     marks = sorted(set(max(1, int(round(S * j / n_snap))) for j in range(1, n_snap + 1)))
     snaps, last, done, el = [], [0] * len(scenarios), 0, 0.0
@@ -232,21 +242,21 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
 
 def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 50):
     """Solver alone: one batch, every scenario to the end of its heating.
-    Returns ([(u, T)], seconds of set-up + run + read)."""
+    Returns ([(u, T)], {"setup": s, "run": s, "total": s}): set-up = host precompute and
+    upload, run = GPU stepping and the read-back of every field."""
     t0 = time.perf_counter()
     b = tled.Batch(device, stream=stream)
     b.set_options(graph_steps=graph_steps)
     for p, dur in scenarios:
-        h = tled.from_problem(p, device=-1, finalize=False)
-        dt = p.cfl * h.critical_dt()
-        h.close()
-        b.add(p, dt, max(1, int(round(dur / dt))))
+        b.add(p, cfl=p.cfl, t_end=dur)
     b.finalize()
+    b.sync()
+    t1 = time.perf_counter()
     b.run()
     out = [(u.copy(), T.copy()) for u, T in b.read_all()]
-    el = time.perf_counter() - t0
+    t2 = time.perf_counter()
     b.close()
-    return out, el
+    return out, {"setup": t1 - t0, "run": t2 - t1, "total": t2 - t0}
 
 
 @dataclass
@@ -280,6 +290,7 @@ class Ensemble:
         self.t_ref = t_ref
         self.y_std = np.ones(4, np.float32)
         self.calib = 1.0
+        self.last_forward_s = 0.0
 
     def fit(self, data: Dataset, epochs: int, batch: int = 16384, lr: float = 2e-3, log=None):
         self.y_std = data.y.std(0).astype(np.float32) + np.float32(1e-12)
@@ -293,7 +304,11 @@ class Ensemble:
         dev = torch.device("cuda", self.device)
         X = torch.from_numpy(x).to(dev)
         Pm = torch.from_numpy(p).to(dev)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
         ys = torch.stack([m.forward(X, Pm) for m in self.models])      # K x n x 4
+        torch.cuda.synchronize(dev)
+        self.last_forward_s = time.perf_counter() - t0
         return (ys * torch.from_numpy(self.y_std).to(dev)).cpu().numpy()
 
     def predict_many(self, items):
@@ -351,7 +366,9 @@ def train(model: MLP, data: Dataset, epochs: int, batch: int = 16384, lr: float 
 def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream=None):
     """Surrogate-first planning of items [(Problem, duration)]: every scenario is
     predicted by the ensemble; those whose disagreement estimate exceeds
-    threshold_K are run by the solver instead.  Returns results and timings."""
+    threshold_K are run by the solver instead.  Returns results and timings
+    (t_surrogate: input assembly on the host + ensemble inference + read-back;
+    t_surrogate_gpu: the inference calls alone)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -360,7 +377,7 @@ def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream
     t_sur = time.perf_counter() - t0
     est = [ens.disagreement(sp) for _, _, sp in preds]
     reject = [k for k, e in enumerate(est) if e > threshold_K]
-    t_fb, fallback = 0.0, {}
+    t_fb, fallback = {"setup": 0.0, "run": 0.0, "total": 0.0}, {}
     if reject:
         fields, t_fb = solve([items[k] for k in reject], device=device, stream=stream)
         fallback = dict(zip(reject, fields))
@@ -371,4 +388,5 @@ def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream
             results.append(("solver", u, T))
         else:
             results.append(("surrogate", um, Tm))
-    return {"results": results, "t_surrogate": t_sur, "t_fallback": t_fb, "rejected": reject, "estimate": est}
+    return {"results": results, "t_surrogate": t_sur, "t_surrogate_gpu": ens.last_forward_s, "t_fallback": t_fb,
+            "rejected": reject, "estimate": est}

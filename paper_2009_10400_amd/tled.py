@@ -90,10 +90,11 @@ class Info(ctypes.Structure):
     _fields_ = [("n_nodes", _i64), ("n_elems", _i64), ("elem_type", _i32), ("n_prony", _i32),
                 ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
                 ("n_shared_nodes", _i64), ("patch_max_nodes", _i32), ("patch_lds_bytes", _i32),
-                ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d)]
+                ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d), ("patch_wgs_per_cu", _i32),
+                ("reserved", _i32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _P = ctypes.c_void_p
@@ -135,7 +136,9 @@ _SIGS = {
     "tled_batch_add": ([_P, ctypes.c_int, _i64, _dp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(Material), _dp, _dp,
                         _d, _d, _i64, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint8), _d, _d, _i64, _i32,
                         ctypes.POINTER(_i32)], ctypes.c_int),
+    "tled_batch_set_duration": ([_P, _i32, _d, _d], ctypes.c_int),
     "tled_batch_finalize": ([_P], ctypes.c_int),
+    "tled_batch_scenario_steps": ([_P, _i32, _dp, ctypes.POINTER(_i64)], ctypes.c_int),
     "tled_batch_run": ([_P], ctypes.c_int),
     "tled_batch_read": ([_P, _i32, _dp, _dp], ctypes.c_int),
     "tled_batch_read_all": ([_P, _dp, _dp], ctypes.c_int),
@@ -401,7 +404,23 @@ class Batch(Sim):
         if stream is not None:
             self._check(_lib.tled_set_stream(h, _P(int(stream))))
 
-    def add(self, problem, dt: float, n_steps: int, patch_elems: int = 0) -> int:
+    def add(self, problem, dt: float = 0.0, n_steps: int = 0, patch_elems: int = 0, cfl: float = 0.0,
+            t_end: float = 0.0) -> int:
+        """Adds a scenario: either an explicit dt and n_steps, or cfl > 0 and t_end, in which case
+        finalize picks dt = cfl x the scenario's critical step and n_steps = round(t_end / dt)."""
+        k = self._add(problem, dt, n_steps, patch_elems)
+        if cfl > 0.0:
+            self._check(_lib.tled_batch_set_duration(self._h, k, float(cfl), float(t_end)))
+        return k
+
+    def scenario_steps(self, k: int):
+        """(dt, n_steps) of scenario k after finalize."""
+        dt = _d()
+        n = _i64()
+        self._check(_lib.tled_batch_scenario_steps(self._h, int(k), ctypes.byref(dt), ctypes.byref(n)))
+        return dt.value, n.value
+
+    def _add(self, problem, dt: float, n_steps: int, patch_elems: int) -> int:
         X = _f64(problem.X)
         conn = np.ascontiguousarray(problem.conn, dtype=np.int32)
         m = material(problem.params)

@@ -86,3 +86,36 @@ def test_batch_scenarios_against_oracle_and_monitors():
         Vl = o.lumped()["Vl"]
         hot = T >= thr
         assert vol[k] == pytest.approx(Vl[hot].sum(), rel=1e-5, abs=1e-15)
+
+
+def test_batch_fields_independent_of_host_threads_and_duration_api(monkeypatch):
+    """A batch set up on 1 or 4 host threads, with time steps chosen at finalize, runs to the
+    same bits; the chosen steps equal the explicit ones."""
+    from paper_2009_10400_amd import tled
+    sc = W.planning_scenarios(5, seed=13, lo=1500, hi=9000, duration_scale=2e-4)
+    outs = []
+    for threads in ("1", "4"):
+        monkeypatch.setenv("TLED_HOST_THREADS", threads)
+        b = tled.Batch(0)
+        b.set_options(graph_steps=30)
+        for p, dur in sc:
+            b.add(p, cfl=0.8, t_end=dur)
+        b.finalize()
+        steps = [b.scenario_steps(k) for k in range(len(sc))]
+        log(f"  threads {threads}: steps {[n for _, n in steps]}")
+        b.run()
+        outs.append((steps, b.read_all()))
+        b.close()
+    (s1, f1), (s4, f4) = outs
+    assert s1 == s4
+    for (u1, T1), (u4, T4) in zip(f1, f4):
+        assert np.array_equal(u1, u4) and np.array_equal(T1, T4)
+    # explicit dt / n_steps give the same run
+    b = tled.Batch(0)
+    b.set_options(graph_steps=30)
+    for (p, _), (dt, n) in zip(sc, s1):
+        b.add(p, dt, n)
+    b.finalize()
+    b.run()
+    for (u1, T1), (u, T) in zip(f1, b.read_all()):
+        assert np.array_equal(u1, u) and np.array_equal(T1, T)

@@ -75,17 +75,34 @@ def _ref_theta(mlp):
     return theta
 
 
-@pytest.mark.parametrize("n", [1, 300, 1000])
-def test_forward_matches_reference(torch_dev, n):
+@pytest.mark.parametrize("n,layerwise", [(1, False), (300, False), (1000, False), (1000, True)])
+def test_forward_matches_reference(torch_dev, n, layerwise):
     import torch
-    print(f"[forward] n={n}", flush=True)
+    print(f"[forward] n={n} layerwise={layerwise}", flush=True)
     cfg, x, p, t = _small_case(11, n)
-    mlp = _mlp(**cfg, sigma=0.7, seed=3)
+    mlp = _mlp(**cfg, sigma=0.7, seed=3, layerwise=layerwise)
     B = mlp.frequencies().astype(np.float64)
     y = mlp.forward(torch.from_numpy(x).to(torch_dev), torch.from_numpy(p).to(torch_dev)).cpu().numpy()
     yr, _, _ = R.forward(_ref_theta(mlp), x.astype(np.float64), p.astype(np.float64), B, cfg)
     scale = np.abs(yr).max()
     assert np.abs(y - yr).max() <= 2e-2 * scale, (np.abs(y - yr).max(), scale)
+
+
+@pytest.mark.parametrize("width,depth,n_out,n", [(64, 2, 4, 1000), (256, 5, 4, 4097), (128, 3, 20, 77),
+                                                  (256, 1, 1, 1)])
+def test_fused_inference_equals_layerwise(torch_dev, width, depth, n_out, n):
+    """The fused whole-network kernel and the layer-by-layer GEMMs give the same bits."""
+    import torch
+    print(f"[fused] width={width} depth={depth} n_out={n_out} n={n}", flush=True)
+    cfg = dict(n_param=11, n_freq=64, width=width, depth=depth, n_out=n_out)
+    rng = np.random.default_rng(width + n)
+    x = torch.from_numpy(rng.uniform(-2, 2, (n, 3)).astype(np.float32)).to(torch_dev)
+    p = torch.from_numpy(rng.uniform(-1, 1, (n, 11)).astype(np.float32)).to(torch_dev)
+    a = _mlp(**cfg, seed=4)
+    b = _mlp(**cfg, seed=4, layerwise=True)
+    ya, yb = a.forward(x, p).cpu().numpy(), b.forward(x, p).cpu().numpy()
+    assert np.isfinite(ya).all()
+    assert np.array_equal(ya, yb)
 
 
 def test_frequencies_are_gaussian():

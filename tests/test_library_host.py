@@ -178,3 +178,47 @@ def test_batch_host_setup_and_errors():
     with pytest.raises(tled.TledError) as e:
         b.set_time(1e-5, 0.0)
     assert e.value.status == tled.E_STATE
+
+
+def test_batch_duration_picks_fraction_of_critical_step():
+    """tled_batch_set_duration: dt = cfl x the scenario's critical step, n = round(t_end / dt)."""
+    from paper_2009_10400_amd import tled
+    sc = W.planning_scenarios(3, seed=8, lo=1000, hi=4000, duration_scale=1e-3)
+    b = tled.Batch(-1)
+    b.add(sc[0][0], 1e-5, 7)                               # explicit
+    for p, dur in sc[1:]:
+        b.add(p, cfl=0.8, t_end=dur)                       # chosen at finalize
+    with pytest.raises(tled.TledError):
+        b.scenario_steps(0)                                # not finalized yet
+    b.finalize()
+    assert b.scenario_steps(0) == (1e-5, 7)
+    for k, (p, dur) in enumerate(sc[1:], start=1):
+        s = host_sim(p)
+        dt, n = b.scenario_steps(k)
+        assert dt == pytest.approx(0.8 * s.critical_dt(), rel=1e-14)
+        assert n == max(1, round(dur / dt))
+    # dt 0 without a duration, or a cfl outside (0, 1], is refused
+    b2 = tled.Batch(-1)
+    b2.add(sc[0][0], 0.0, 10)
+    with pytest.raises(tled.TledError) as e:
+        b2.finalize()
+    assert e.value.status == tled.E_ARG
+    with pytest.raises(tled.TledError) as e:
+        b2.add(sc[0][0], cfl=1.5, t_end=1.0)
+    assert e.value.status == tled.E_ARG
+
+
+def test_batch_setup_is_independent_of_host_threads(monkeypatch):
+    """The per-scenario precompute runs on a thread pool; results do not depend on its size."""
+    from paper_2009_10400_amd import tled
+    sc = W.planning_scenarios(5, seed=9, lo=1000, hi=6000, duration_scale=1e-3)
+    infos = []
+    for n in ("1", "3"):
+        monkeypatch.setenv("TLED_HOST_THREADS", n)
+        b = tled.Batch(-1)
+        for p, dur in sc:
+            b.add(p, cfl=0.8, t_end=dur)
+        b.finalize()
+        infos.append((b.batch_info(), [b.scenario_steps(k) for k in range(len(sc))]))
+        b.close()
+    assert infos[0] == infos[1]
