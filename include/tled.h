@@ -104,7 +104,7 @@ typedef struct {
                                  precomputed geometry                                          */
     int32_t reorder;          /* 0: auto (on), 1: on, -1: keep the caller's order             */
     int32_t block_size;       /* threads per workgroup of the fused patch kernel: 0 (256),
-                                 256, or 512 (T4 only)                                        */
+                                 256, or 512 (single T4 problems only)                        */
     int32_t patch_elems;      /* elements per patch for the fused variant (0: default)        */
     double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */
 } tled_options;
@@ -222,10 +222,12 @@ tled_status tled_get_state(tled_sim *sim, void *buf);
 tled_status tled_set_state(tled_sim *sim, const void *buf);
 
 /* --- measurement ---------------------------------------------------------
- * Runs n_steps eagerly with a HIP event pair around every launch on the
- * library's stream and returns the mean duration (ms) per launch of each
- * kernel kind: ms[0] element (or fused patch) kernel, ms[1] node (or shared-
- * node) kernel, ms[2] monitor reduction.  Advances the state like tled_step. */
+ * Runs n_steps eagerly on the library's stream with a HIP event pair taken by
+ * the dispatch of every element and node launch (hipExtLaunchKernelGGL; the
+ * monitor reduction by a pair of recorded events) and returns the mean
+ * duration (ms) per launch of each kernel kind: ms[0] element (or fused patch)
+ * kernel, ms[1] node (or shared-node) kernel, ms[2] monitor reduction.
+ * Advances the state like tled_step. */
 tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]);
 
 /* --- batched scenarios (planning sweeps) ----------------------------------

@@ -407,21 +407,28 @@ void single_scenario(tled_sim *s) {
 }
 
 // Enqueue a chunk of k steps (eager, or under stream capture).
+// With ev (4 events per step + 2): the element/patch and node/shared-node
+// launches of step j carry the pairs (4j, 4j+1) and (4j+2, 4j+3), taken by the
+// dispatches themselves; the finish kernel is bracketed by the last two.
 tled_status enqueue_chunk(tled_sim *s, int k, double *ms = nullptr, std::vector<hipEvent_t> *ev = nullptr) {
     const int npe = s->pc.npe;
     const int bs = s->opt.block_size > 0 ? s->opt.block_size : kBlock;
     for (int j = 0; j < k; ++j) {
         const bool mon = (j == k - 1);
-        if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j], s->stream));
-        if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream);
-        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->pa, j, s->stream);
-        if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 1], s->stream));
-        if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream);
-        else launch_shared_nodes(mon, s->pa, j, s->stream);
-        if (ev) HIPCHK(s, hipEventRecord((*ev)[3 * j + 2], s->stream));
+        LaunchTiming t0{}, t1{};
+        if (ev) {
+            t0 = LaunchTiming{(*ev)[4 * j], (*ev)[4 * j + 1]};
+            t1 = LaunchTiming{(*ev)[4 * j + 2], (*ev)[4 * j + 3]};
+        }
+        if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
+        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, s->pa, j, s->stream, ev ? &t0 : nullptr);
+        if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream, ev ? &t1 : nullptr);
+        else launch_shared_nodes(mon, s->is_batch, s->pa, j, s->stream, ev ? &t1 : nullptr);
     }
+    if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k)], s->stream));
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,
                   s->d_mon, s->stream);
+    if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k) + 1], s->stream));
     HIPCHK(s, hipGetLastError());
     (void)ms;
     return TLED_OK;
@@ -837,7 +844,7 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
             if (sim->device >= 0) {
                 const int bs = sim->opt.block_size > 0 ? sim->opt.block_size : kBlock;
                 out->patch_wgs_per_cu =
-                    patch_occupancy(sim->prob.npe, sim->np, sim->variant == 2, bs, probe);
+                    patch_occupancy(sim->prob.npe, sim->np, sim->variant == 2, bs, sim->is_batch, probe);
             }
         }
         out->device_bytes = sim->device_bytes;
@@ -1074,8 +1081,8 @@ tled_status tled_batch_finalize(tled_batch *b) {
     if (b->scen.empty()) return fail(b, TLED_E_STATE, "no scenario added");
     const int v = b->opt.kernel_variant == 0 ? 2 : b->opt.kernel_variant;
     if (v == 1) return fail(b, TLED_E_UNSUPPORTED, "batches run on the fused kernels (variant 2 or 3)");
-    if (b->opt.block_size == 512 && b->scen[0].npe == 8)
-        return fail(b, TLED_E_UNSUPPORTED, "block_size 512 is for T4 meshes only");
+    if (b->opt.block_size == 512)
+        return fail(b, TLED_E_UNSUPPORTED, "batches run with 256-thread workgroups (block_size 0 or 256)");
     std::vector<int> pe(b->scen.size());
     for (size_t k = 0; k < pe.size(); ++k)
         pe[k] = b->scen_pe[k] > 0 ? b->scen_pe[k]
@@ -1225,25 +1232,23 @@ tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]) {
     ms[0] = ms[1] = ms[2] = 0.0;
     const int chunk = sim->opt.graph_steps > 0 ? sim->opt.graph_steps : 100;
     int64_t left = n_steps, chunks = 0;
-    std::vector<hipEvent_t> ev(3 * size_t(chunk) + 2);
+    std::vector<hipEvent_t> ev(4 * size_t(chunk) + 2);
     for (auto &e : ev) HIPCHK(sim, hipEventCreate(&e));
     tled_status st = TLED_OK;
     while (left > 0 && st == TLED_OK) {
         int c = int(std::min<int64_t>(left, chunk));
         st = enqueue_chunk(sim, c, nullptr, &ev);
         if (st != TLED_OK) break;
-        // the finish kernel follows the last node launch; time it with the spare pair
-        HIPCHK(sim, hipEventRecord(ev[3 * chunk + 1], sim->stream));
         HIPCHK(sim, hipStreamSynchronize(sim->stream));
         for (int j = 0; j < c; ++j) {
             float a = 0.f, b = 0.f;
-            HIPCHK(sim, hipEventElapsedTime(&a, ev[3 * j], ev[3 * j + 1]));
-            HIPCHK(sim, hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
+            HIPCHK(sim, hipEventElapsedTime(&a, ev[4 * j], ev[4 * j + 1]));
+            HIPCHK(sim, hipEventElapsedTime(&b, ev[4 * j + 2], ev[4 * j + 3]));
             ms[0] += a;
             ms[1] += b;
         }
         float f = 0.f;
-        HIPCHK(sim, hipEventElapsedTime(&f, ev[3 * (c - 1) + 2], ev[3 * chunk + 1]));
+        HIPCHK(sim, hipEventElapsedTime(&f, ev[4 * size_t(c)], ev[4 * size_t(c) + 1]));
         ms[2] += f;
         ++chunks;
         left -= c;

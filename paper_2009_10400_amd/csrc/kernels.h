@@ -82,12 +82,22 @@ struct PatchArgs {
     const long long *scen_end;  // per scenario: steps to run (the scenario holds afterwards)
 };
 
-void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s);
-void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s);
-void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s);
+// Optional timing of one launch: both events are taken by the dispatch itself.
+struct LaunchTiming {
+    hipEvent_t start, stop;
+};
+
+void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s,
+                    const LaunchTiming *ev = nullptr);
+void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s,
+                 const LaunchTiming *ev = nullptr);
+// batch: per-scenario constants and end steps (256-thread workgroups only).
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
+                  hipStream_t s, const LaunchTiming *ev = nullptr);
 // Resident workgroups per CU of the patch kernel in this configuration (-1 on error).
-int patch_occupancy(int npe, int np, bool geox, int bs, const PatchArgs &a);
-void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s);
+int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a);
+void launch_shared_nodes(bool mon, bool batch, const PatchArgs &a, int j, hipStream_t s,
+                         const LaunchTiming *ev = nullptr);
 // Per-scenario maximum temperature and lumped volume at or above T_abl, over the
 // scenario's interior node range [int_lo, int_hi) and shared range [sh_lo, sh_hi).
 void launch_scenario_monitors(const float4 *nu4, const float *Vl, const long long *ranges /* 4 per scenario */,

@@ -16,6 +16,18 @@
 #include "device_math.h"
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
+
+// Launch with optional timing: with a start/stop event pair the events are taken
+// by the dispatch itself (hipExtLaunchKernelGGL), so no extra packets sit
+// between kernels and the elapsed time is the kernel's own duration.
+#define TLED_LAUNCH(ev, kern, grid, block, lds, stream, ...)                                              \
+    do {                                                                                                  \
+        if (ev) hipExtLaunchKernelGGL(kern, grid, block, lds, stream, (ev)->start, (ev)->stop, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);                             \
+    } while (0)
+
+
 namespace tled {
 
 // Workgroups are dispatched round-robin over the XCDs; map them so that
@@ -498,20 +510,25 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
 // coordinates (float4 each per local node) and the element-slot outputs
 // (float4 per element slot).  GEOX: element geometry rebuilt from the staged
 // coordinates (else read from the precomputed planes).
-template <int NPE, int NP, bool MON, int BS, bool GEOX>
+template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH>
 __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     extern __shared__ float4 lds[];
     __shared__ double shd[BS / 64];
     __shared__ float shf[BS / 64];
     const int pid = xcd_block(blockIdx.x, gridDim.x);
-    const int sc = A.patch_scen[pid];
-    if (*A.step_base + j >= A.scen_end[sc]) {   // this scenario has finished: hold it
-        if (MON && threadIdx.x == 0) {
-            A.part_elem[pid] = 0.0;
-            double *pp = A.part_node + 4 * size_t(pid);
-            pp[0] = 0.0; pp[1] = -INFINITY; pp[2] = INFINITY; pp[3] = 0.0;
+    // BATCH: per-scenario constants and end steps; else the single problem's
+    // constants at index 0 (no scenario lookups, fewer scalar registers live)
+    int sc = 0;
+    if (BATCH) {
+        sc = A.patch_scen[pid];
+        if (*A.step_base + j >= A.scen_end[sc]) {   // this scenario has finished: hold it
+            if (MON && threadIdx.x == 0) {
+                A.part_elem[pid] = 0.0;
+                double *pp = A.part_node + 4 * size_t(pid);
+                pp[0] = 0.0; pp[1] = -INFINITY; pp[2] = INFINITY; pp[3] = 0.0;
+            }
+            return;
         }
-        return;
     }
     const KMat m = A.km[sc];
     const NodeParams p = A.np[sc];
@@ -614,7 +631,7 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     }
 }
 
-template <bool MON>
+template <bool MON, bool BATCH>
 __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j) {
     __shared__ double shd[kBlock / 64];
     __shared__ float shf[kBlock / 64];
@@ -622,9 +639,9 @@ __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j)
     const int s = blk * kBlock + threadIdx.x;
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
     bool nf = false;
-    const int sc = (s < A.n_shared) ? A.shared_scen[s] : 0;
+    const int sc = (BATCH && s < A.n_shared) ? A.shared_scen[s] : 0;
     const long long step = *A.step_base + j;
-    if (s < A.n_shared && step < A.scen_end[sc]) {
+    if (s < A.n_shared && (!BATCH || step < A.scen_end[sc])) {
         const NodeParams p = A.np[sc];
         const float src = (step >= p.n_on && step < p.n_off) ? 1.0f : 0.0f;
         const int a = A.n_interior + s;
@@ -693,123 +710,138 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const double *__restrict
 
 namespace {
 template <int NP>
-void launch_t4_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+void launch_t4_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
     dim3 grid((a.ne + kBlock - 1) / kBlock);
     if (mon)
-        hipLaunchKernelGGL((t4_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
-                           a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (t4_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
+                    a.theta, a.out, a.ne, m, a.status, a.part_elem);
     else
-        hipLaunchKernelGGL((t4_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
-                           a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (t4_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
+                    a.theta, a.out, a.ne, m, a.status, a.part_elem);
 }
 template <int NP>
-void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
     dim3 grid((a.ne + kBlock - 1) / kBlock);
     if (mon)
-        hipLaunchKernelGGL((h8_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
-                           a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (h8_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
+                    a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
     else
-        hipLaunchKernelGGL((h8_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
-                           a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (h8_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1,
+                    a.g2, a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
 }
 
 // occ != nullptr: report the resident workgroups per CU of the instantiation
 // instead of launching it.
-template <int NPE, int NP, int BS, bool GEOX>
-void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s, int *occ) {
+template <int NPE, int NP, int BS, bool GEOX, bool BATCH>
+void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s, int *occ,
+                    const LaunchTiming *ev) {
     if (occ) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX>), BS, lds) != hipSuccess)
+                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX, BATCH>), BS, lds) !=
+            hipSuccess)
             *occ = -1;
         return;
     }
     dim3 grid(a.n_patches);
-    if (mon) hipLaunchKernelGGL((patch_kernel<NPE, NP, true, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
-    else hipLaunchKernelGGL((patch_kernel<NPE, NP, false, BS, GEOX>), grid, dim3(BS), lds, s, a, j);
+    if (mon) TLED_LAUNCH(ev, (patch_kernel<NPE, NP, true, BS, GEOX, BATCH>), grid, dim3(BS), lds, s, a, j);
+    else TLED_LAUNCH(ev, (patch_kernel<NPE, NP, false, BS, GEOX, BATCH>), grid, dim3(BS), lds, s, a, j);
 }
 
+// Batches run with 256-thread workgroups only.
 template <int NPE, int NP>
-void launch_patch_np(bool mon, bool geox, int bs, const PatchArgs &a, int j, size_t lds, hipStream_t s,
-                     int *occ) {
-    if (NPE == 4 && bs == 512) {
-        if (geox) launch_patch_g<NPE, NP, 512, true>(mon, a, j, lds, s, occ);
-        else launch_patch_g<NPE, NP, 512, false>(mon, a, j, lds, s, occ);
+void launch_patch_np(bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j, size_t lds,
+                     hipStream_t s, int *occ, const LaunchTiming *ev) {
+    if (batch) {
+        if (geox) launch_patch_g<NPE, NP, 256, true, true>(mon, a, j, lds, s, occ, ev);
+        else launch_patch_g<NPE, NP, 256, false, true>(mon, a, j, lds, s, occ, ev);
+    } else if (NPE == 4 && bs == 512) {
+        if (geox) launch_patch_g<NPE, NP, 512, true, false>(mon, a, j, lds, s, occ, ev);
+        else launch_patch_g<NPE, NP, 512, false, false>(mon, a, j, lds, s, occ, ev);
     } else {
-        if (geox) launch_patch_g<NPE, NP, 256, true>(mon, a, j, lds, s, occ);
-        else launch_patch_g<NPE, NP, 256, false>(mon, a, j, lds, s, occ);
+        if (geox) launch_patch_g<NPE, NP, 256, true, false>(mon, a, j, lds, s, occ, ev);
+        else launch_patch_g<NPE, NP, 256, false, false>(mon, a, j, lds, s, occ, ev);
     }
 }
 }  // namespace
 
-void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s) {
+void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s,
+                    const LaunchTiming *ev) {
     if (a.ne == 0) return;
     if (npe == 4) {
         switch (np) {
-            case 0: launch_t4_element<0>(mon, a, m, s); break;
-            case 1: launch_t4_element<1>(mon, a, m, s); break;
-            case 2: launch_t4_element<2>(mon, a, m, s); break;
-            case 3: launch_t4_element<3>(mon, a, m, s); break;
-            default: launch_t4_element<4>(mon, a, m, s); break;
+            case 0: launch_t4_element<0>(mon, a, m, s, ev); break;
+            case 1: launch_t4_element<1>(mon, a, m, s, ev); break;
+            case 2: launch_t4_element<2>(mon, a, m, s, ev); break;
+            case 3: launch_t4_element<3>(mon, a, m, s, ev); break;
+            default: launch_t4_element<4>(mon, a, m, s, ev); break;
         }
     } else {
         switch (np) {
-            case 0: launch_h8_element<0>(mon, a, m, s); break;
-            case 1: launch_h8_element<1>(mon, a, m, s); break;
-            case 2: launch_h8_element<2>(mon, a, m, s); break;
-            case 3: launch_h8_element<3>(mon, a, m, s); break;
-            default: launch_h8_element<4>(mon, a, m, s); break;
+            case 0: launch_h8_element<0>(mon, a, m, s, ev); break;
+            case 1: launch_h8_element<1>(mon, a, m, s, ev); break;
+            case 2: launch_h8_element<2>(mon, a, m, s, ev); break;
+            case 3: launch_h8_element<3>(mon, a, m, s, ev); break;
+            default: launch_h8_element<4>(mon, a, m, s, ev); break;
         }
     }
 }
 
-void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s) {
+void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s, const LaunchTiming *ev) {
     dim3 grid((a.nn + kBlock - 1) / kBlock);
-    if (mon) hipLaunchKernelGGL((node_kernel<true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4,
-                                a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
-    else hipLaunchKernelGGL((node_kernel<false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4,
-                            a.nth, a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+    if (mon)
+        TLED_LAUNCH(ev, (node_kernel<true>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4, a.nth,
+                    a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
+    else
+        TLED_LAUNCH(ev, (node_kernel<false>), grid, dim3(kBlock), 0, s, a.rowptr, a.inc, a.out, a.nu4, a.nv4, a.nth,
+                    a.mask, a.Vl, a.nn, p, a.step_base, j, a.status, a.part_node);
 }
 
 namespace {
-void patch_dispatch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s,
-                    int *occ) {
+void patch_dispatch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
+                    hipStream_t s, int *occ, const LaunchTiming *ev) {
     const size_t lds = patch_lds_bytes(npe, geox, a);
     if (npe == 4) {
         switch (np) {
-            case 0: launch_patch_np<4, 0>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 1: launch_patch_np<4, 1>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 2: launch_patch_np<4, 2>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 3: launch_patch_np<4, 3>(mon, geox, bs, a, j, lds, s, occ); break;
-            default: launch_patch_np<4, 4>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 0: launch_patch_np<4, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 1: launch_patch_np<4, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 2: launch_patch_np<4, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 3: launch_patch_np<4, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            default: launch_patch_np<4, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
         }
     } else {
         switch (np) {
-            case 0: launch_patch_np<8, 0>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 1: launch_patch_np<8, 1>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 2: launch_patch_np<8, 2>(mon, geox, bs, a, j, lds, s, occ); break;
-            case 3: launch_patch_np<8, 3>(mon, geox, bs, a, j, lds, s, occ); break;
-            default: launch_patch_np<8, 4>(mon, geox, bs, a, j, lds, s, occ); break;
+            case 0: launch_patch_np<8, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 1: launch_patch_np<8, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 2: launch_patch_np<8, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 3: launch_patch_np<8, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            default: launch_patch_np<8, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
         }
     }
 }
 }  // namespace
 
-void launch_patch(int npe, int np, bool mon, bool geox, int bs, const PatchArgs &a, int j, hipStream_t s) {
-    patch_dispatch(npe, np, mon, geox, bs, a, j, s, nullptr);
+void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
+                  hipStream_t s, const LaunchTiming *ev) {
+    patch_dispatch(npe, np, mon, geox, bs, batch, a, j, s, nullptr, ev);
 }
 
-int patch_occupancy(int npe, int np, bool geox, int bs, const PatchArgs &a) {
+int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a) {
     int occ = 0;
-    patch_dispatch(npe, np, false, geox, bs, a, 0, nullptr, &occ);
+    patch_dispatch(npe, np, false, geox, bs, batch, a, 0, nullptr, &occ, nullptr);
     return occ;
 }
 
-void launch_shared_nodes(bool mon, const PatchArgs &a, int j, hipStream_t s) {
+void launch_shared_nodes(bool mon, bool batch, const PatchArgs &a, int j, hipStream_t s, const LaunchTiming *ev) {
     const int nb = int((a.n_shared + kBlock - 1) / kBlock);
     if (nb == 0) return;
     dim3 grid(nb);
-    if (mon) hipLaunchKernelGGL((shared_node_kernel<true>), grid, dim3(kBlock), 0, s, a, j);
-    else hipLaunchKernelGGL((shared_node_kernel<false>), grid, dim3(kBlock), 0, s, a, j);
+    if (batch) {
+        if (mon) TLED_LAUNCH(ev, (shared_node_kernel<true, true>), grid, dim3(kBlock), 0, s, a, j);
+        else TLED_LAUNCH(ev, (shared_node_kernel<false, true>), grid, dim3(kBlock), 0, s, a, j);
+    } else {
+        if (mon) TLED_LAUNCH(ev, (shared_node_kernel<true, false>), grid, dim3(kBlock), 0, s, a, j);
+        else TLED_LAUNCH(ev, (shared_node_kernel<false, false>), grid, dim3(kBlock), 0, s, a, j);
+    }
 }
 
 // One block per scenario: max T and the lumped volume at or above T_abl (fixed-order reduction).
