@@ -870,6 +870,14 @@ tled_status tled_get_lumped(tled_sim *sim, double *Vl, double *M, double *C, dou
     return TLED_OK;
 }
 
+// Position of Prony component c (0 .. 6 np - 1) of internal element e in the
+// device array: float4 planes of components 4k..4k+3, then a float2 plane.
+static size_t theta_index(int c, int64_t e, int64_t ne, int np) {
+    const int n4 = 6 * np / 4;
+    if (c < 4 * n4) return size_t(c / 4) * 4 * size_t(ne) + 4 * size_t(e) + size_t(c % 4);
+    return 4 * size_t(n4) * size_t(ne) + 2 * size_t(e) + size_t(c - 4 * n4);
+}
+
 tled_status tled_read_state(tled_sim *sim, double *u, double *v, double *T, double *theta, int64_t *step) {
     TRY(need_single(sim));
     const int64_t nn = sim->pc.nn, ne = sim->pc.ne;
@@ -894,7 +902,7 @@ tled_status tled_read_state(tled_sim *sim, double *u, double *v, double *T, doub
     if (theta)
         for (int64_t e = 0; e < ne; ++e) {
             int64_t o = sim->pc.elem_new2old[e];
-            for (int k = 0; k < 6 * np; ++k) theta[6 * np * o + k] = ht[size_t(k) * ne + e];
+            for (int k = 0; k < 6 * np; ++k) theta[6 * np * o + k] = ht[theta_index(k, e, ne, np)];
         }
     if (step) *step = st;
     return TLED_OK;
@@ -929,7 +937,7 @@ tled_status tled_write_state(tled_sim *sim, const double *u, const double *v, co
     if (theta)
         for (int64_t e = 0; e < ne; ++e) {
             int64_t o = sim->pc.elem_new2old[e];
-            for (int k = 0; k < 6 * np; ++k) ht[size_t(k) * ne + e] = float(theta[6 * np * o + k]);
+            for (int k = 0; k < 6 * np; ++k) ht[theta_index(k, e, ne, np)] = float(theta[6 * np * o + k]);
         }
     long long st = step;
     HIPCHK(sim, hipMemcpyAsync(sim->tp.nu4, hu.data(), sizeof(float4) * nn, hipMemcpyHostToDevice, sim->stream));

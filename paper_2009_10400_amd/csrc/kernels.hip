@@ -336,11 +336,27 @@ __device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], con
     r.nonfinite = nf;
 }
 
+// Prony state of element e: the 6 np components in float4 planes (components
+// 4k..4k+3 of all elements, element-major), then one float2 plane when 6 np is
+// not a multiple of 4 (same layout as theta_index on the host).
 __device__ __forceinline__ void load_theta(const float *__restrict__ theta, size_t ne, size_t e, int np, float *th) {
-    for (int k = 0; k < 6 * np; ++k) th[k] = theta[size_t(k) * ne + e];
+    const int n4 = 6 * np / 4;
+    for (int k = 0; k < n4; ++k) {
+        const float4 v = reinterpret_cast<const float4 *>(theta)[size_t(k) * ne + e];
+        th[4 * k] = v.x; th[4 * k + 1] = v.y; th[4 * k + 2] = v.z; th[4 * k + 3] = v.w;
+    }
+    if (6 * np % 4) {
+        const float2 v = reinterpret_cast<const float2 *>(theta + 4 * size_t(n4) * ne)[e];
+        th[4 * n4] = v.x; th[4 * n4 + 1] = v.y;
+    }
 }
 __device__ __forceinline__ void store_theta(float *__restrict__ theta, size_t ne, size_t e, int np, const float *th) {
-    for (int k = 0; k < 6 * np; ++k) theta[size_t(k) * ne + e] = th[k];
+    const int n4 = 6 * np / 4;
+    for (int k = 0; k < n4; ++k)
+        reinterpret_cast<float4 *>(theta)[size_t(k) * ne + e] =
+            make_float4(th[4 * k], th[4 * k + 1], th[4 * k + 2], th[4 * k + 3]);
+    if (6 * np % 4)
+        reinterpret_cast<float2 *>(theta + 4 * size_t(n4) * ne)[e] = make_float2(th[4 * n4], th[4 * n4 + 1]);
 }
 
 // ---------------------------------------------------------------- node update
