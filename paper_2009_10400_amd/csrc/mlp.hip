@@ -233,24 +233,33 @@ __global__ void sum_kernel(int nparts, const float *__restrict__ part, float sca
     if (threadIdx.x == 0) out[0] = sh[0] * scale;
 }
 
-// Column sums of a bfloat16 M x N matrix in chunks of rows: part[c][j].
-constexpr int kColChunk = 512;
-__global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict__ X, float *__restrict__ part) {
+// Column sums of a bfloat16 M x N matrix in chunks of rows: part[c][j]
+// (short chunks: enough workgroups to keep the loads in flight).
+constexpr int kColChunk = 64;
+__global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict__ X, float *__restrict__ part,
+                                      long chunk) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const long r0 = long(blockIdx.y) * kColChunk;
+    const long r0 = long(blockIdx.y) * chunk;
     if (j >= N) return;
     float s = 0.f;
-    const long r1 = std::min(M, r0 + kColChunk);
+    const long r1 = std::min(M, r0 + chunk);
     for (long r = r0; r < r1; ++r) s += bf2f(X[r * N + j]);
     part[size_t(blockIdx.y) * N + j] = s;
 }
 
+// Fixed-order sum of the chunk partials: four interleaved accumulators (chunk
+// c into accumulator c % 4), combined as (a0 + a1) + (a2 + a3).
 __global__ void colsum_final_kernel(int nchunks, int N, const float *__restrict__ part, float *__restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[size_t(c) * N + j];
-    out[j] = s;
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 4 <= nchunks; c += 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] += part[size_t(c + q) * N + j];
+    }
+    for (; c < nchunks; ++c) a[c % 4] += part[size_t(c) * N + j];
+    out[j] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // Adam on the FP32 master parameters; refreshes the bfloat16 copy.
@@ -329,11 +338,20 @@ __global__ __launch_bounds__(kThreads) void fused_forward_kernel(long n, const f
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // weight fragments of the next k step are requested before this step's MFMAs
+        const uint16_t *wrow = Wl + long(nb + (l & 15)) * K + 8 * (l >> 4);
+        bf16x8 bn[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * K);
         for (int k0 = 0; k0 < K; k0 += 32) {
             bf16x8 b[NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                b[j] = *reinterpret_cast<const bf16x8 *>(Wl + long(nb + 16 * j + (l & 15)) * K + k0 + 8 * (l >> 4));
+            for (int j = 0; j < NT; ++j) b[j] = bn[j];
+            if (k0 + 32 < K) {
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * K + k0 + 32);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(16 * i + (l & 15)) * P + k0 + 8 * (l >> 4)]);
@@ -645,13 +663,15 @@ tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
     hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, s->stream, int(nb), s->d_part,
                        1.0f / float(n * no), s->d_loss);
     MCHK(s, hipGetLastError());
-    const unsigned nchunk = unsigned((n + kColChunk - 1) / kColChunk);
+    // row chunks of at least kColChunk, few enough for the grid's y extent
+    const long chunk = std::max<long>(kColChunk, (n + 65534) / 65535);
+    const unsigned nchunk = unsigned((n + chunk - 1) / chunk);
     // output layer
     const Layer &O = s->layers.back();
     MTRY(gemm<EPI_F32>(s, no, W, int(n), s->d_dy, 1, no, s->d_a[D - 1], W, 1, s->d_g + O.w_off, W, 1, nullptr,
                        nullptr));
     hipLaunchKernelGGL(colsum_partial_kernel, dim3((no + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
-                       s->stream, n, no, s->d_dy, s->d_cpart);
+                       s->stream, n, no, s->d_dy, s->d_cpart, chunk);
     hipLaunchKernelGGL(colsum_final_kernel, dim3((no + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
                        int(nchunk), no, s->d_cpart, s->d_g + O.b_off);
     MTRY(gemm<EPI_F32>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, s->d_da, W, 1, nullptr, nullptr));
@@ -663,7 +683,7 @@ tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
         const int in = L.in;
         MTRY(gemm<EPI_F32>(s, W, in, int(n), s->d_dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr));
         hipLaunchKernelGGL(colsum_partial_kernel, dim3((W + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
-                           s->stream, n, W, s->d_dz, s->d_cpart);
+                           s->stream, n, W, s->d_dz, s->d_cpart, chunk);
         hipLaunchKernelGGL(colsum_final_kernel, dim3((W + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
                            int(nchunk), W, s->d_cpart, s->d_g + L.b_off);
         if (l > 0)
