@@ -14,8 +14,9 @@
  *
  * Arithmetic: weights and activations in bfloat16, products accumulated in
  * FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16); FP32 master weights,
- * biases, loss and Adam moments.  Loss: mean over samples and outputs of the
- * squared error.
+ * biases, loss and Adam moments; sine, cosine, exponential and reciprocal from
+ * the hardware transcendental units (errors far below the bfloat16 rounding of
+ * the activations).  Loss: mean over samples and outputs of the squared error.
  *
  * Parameter layout (FP32, host arrays of tled_mlp_param_count floats): for
  * each layer in order, W (rows = outputs, row-major over inputs incl. the

@@ -20,15 +20,30 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;   // LDS rows padded against bank conflicts
 
-// float -> bfloat16 bits, round to nearest even (NaN kept quiet).
-__host__ __device__ inline uint16_t f2bf(float x) {
-    uint32_t u;
-    std::memcpy(&u, &x, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+// float -> bfloat16 bits by the hardware convert (v_cvt_pk_bf16_f32 on gfx950,
+// round to nearest even).
+__device__ inline uint16_t bf16_bits(float x) {
+    const __bf16 h = static_cast<__bf16>(x);
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+}
+
+// Logistic function from the hardware base-2 exponential and reciprocal
+// (v_exp_f32, v_rcp_f32; each within about 1 ulp, far below the bfloat16
+// rounding the activations then take).  Every SiLU of the forward passes and its
+// derivative in the backward pass use this one function.
+__device__ __forceinline__ float sigmoidf_hw(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+
+// sin(2 pi t) or cos(2 pi t) for t in revolutions: reduced to [-1/2, 1/2] (exact
+// for |t| < 2^22), then the hardware sine/cosine, which take revolutions.
+__device__ __forceinline__ float fourier_feature(float t, bool sine) {
+    const float r = t - rintf(t);
+    return sine ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
+}
 
 enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2 };
 // How an operand tile is read from global memory: element by element (any
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
                 } else {
                     const float z = v + bias[n];
                     C[m * scm + n * scn] = z;
-                    Act[size_t(m) * N + n] = f2bf(z / (1.0f + expf(-z)));
+                    Act[size_t(m) * N + n] = bf16_bits(z * sigmoidf_hw(z));
                 }
             }
 }
@@ -181,13 +196,12 @@ __global__ void features_kernel(long n, const float *__restrict__ x, const float
     float v = 0.f;
     if (j < 2 * nf) {
         const int f = j < nf ? j : j - nf;
-        const float a = 6.283185307179586f *
-                        (Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2]);
-        v = j < nf ? sinf(a) : cosf(a);
+        v = fourier_feature(Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2],
+                            j < nf);
     } else if (j < 2 * nf + np) {
         v = p[i * np + (j - 2 * nf)];
     }
-    out[idx] = f2bf(v);
+    out[idx] = bf16_bits(v);
 }
 
 // dZ = dA * d(SiLU)/dz = dA s (1 + z (1 - s)), s = sigmoid(z); bfloat16 out.
@@ -195,8 +209,8 @@ __global__ void silu_back_kernel(long n, const float *__restrict__ dA, const flo
                                  uint16_t *__restrict__ dZ) {
     const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float z = Z[i], s = 1.0f / (1.0f + expf(-z));
-    dZ[i] = f2bf(dA[i] * s * (1.0f + z * (1.0f - s)));
+    const float z = Z[i], s = sigmoidf_hw(z);
+    dZ[i] = bf16_bits(dA[i] * s * (1.0f + z * (1.0f - s)));
 }
 
 // dY = 2 (Y - T) / (n n_out) (bfloat16) and per-block sums of (Y - T)^2.
@@ -208,7 +222,7 @@ __global__ void loss_grad_kernel(long n, int nout, const float *__restrict__ Y, 
     if (i < n * nout) {
         const float d = Y[i] - T[i];
         e2 = d * d;
-        dY[i] = f2bf(2.0f * d / float(n * nout));
+        dY[i] = bf16_bits(2.0f * d / float(n * nout));
     }
     sh[threadIdx.x] = e2;
     __syncthreads();
@@ -274,24 +288,28 @@ __global__ void adam_kernel(long P, float *__restrict__ w, const float *__restri
     v[i] = vi;
     const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
     w[i] = wi;
-    wb[i] = f2bf(wi);
+    wb[i] = bf16_bits(wi);
 }
 
 __global__ void to_bf16_kernel(long n, const float *__restrict__ x, uint16_t *__restrict__ y) {
     const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f2bf(x[i]);
+    if (i < n) y[i] = bf16_bits(x[i]);
 }
 
 // Whole-network inference, 64 samples per workgroup of four wavefronts; the
 // activations never leave LDS.  Features are formed in LDS as in
-// features_kernel; each hidden layer is Z = A W^T + b with A (64 x K) from LDS
-// and W (bfloat16, row-major out x in) streamed from global memory straight into
-// the MFMA B operand (8 consecutive k of one output per lane); wavefront w owns
-// output columns [w W/4, (w+1) W/4).  All waves finish reading A before any
-// writes its bf16(SiLU(Z)) back over it.  The output layer gives wavefront w
-// rows [16w, 16w + 16).  The MFMA sequence per output (k in steps of 32,
-// increasing) and the epilogue arithmetic are those of gemm_kernel, so the
-// result equals the layer-by-layer forward pass bit for bit.
+// features_kernel.  Each hidden layer computes its output transposed,
+// Z^T = W A^T + b, with W (bfloat16, row-major out x in) streamed from global
+// memory straight into the MFMA A operand (8 consecutive k of one unit per lane)
+// and A (64 x K) read from LDS as the B operand; wavefront w owns units
+// [w W/4, (w+1) W/4), and each lane ends with 4 consecutive units of one sample,
+// written back as one 8-byte store of bf16(SiLU(z)).  All waves finish reading A
+// before any writes over it.  The output layer gives wavefront w samples
+// [16w, 16w + 16).  Every output is the same k-ordered sum of the same products
+// as in gemm_kernel, with the same epilogue arithmetic, so the result equals the
+// layer-by-layer forward pass bit for bit (tested).  Registers are capped for
+// three waves per SIMD (152 VGPRs for width 256, no spills): at millions of
+// samples the extra wave hides more of the weight-load latency.
 constexpr int kFusedRows = 64;
 constexpr int kFusedMaxDepth = 8;
 struct NetOffsets {
@@ -299,8 +317,51 @@ struct NetOffsets {
     long b[kFusedMaxDepth + 1];
 };
 
+// Z^T (16 NT units x 64 samples per wavefront) = W A^T with A (64 x K, LDS), K
+// in steps of 32: the weights are the MFMA A operand and the activations the B
+// operand, so each lane ends with 4 consecutive units of one sample.  The
+// weight fragments of step k + 32 are requested before the MFMAs of step k.
+template <int NT>
+__device__ __forceinline__ void fused_k_step(f32x4 (&acc)[4][NT], const uint16_t *act, int P, const uint16_t *wrow,
+                                             int K, int ldw, int k0, bf16x8 (&bn)[NT], int l) {
+    bf16x8 b[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) b[j] = bn[j];
+    if (k0 + 32 < K) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * ldw + k0 + 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(16 * i + (l & 15)) * P + k0 + 8 * (l >> 4)]);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a, acc[i][j], 0, 0, 0);
+    }
+}
+
+// Z^T (16 NT units x 64 samples per wavefront) = W A^T with A (64 x K, LDS), K
+// in steps of 32: the weights are the MFMA A operand and the activations the B
+// operand, so each lane ends with 4 consecutive units of one sample.  The
+// weight fragments of step k + 32 are requested before the MFMAs of step k.
+// KFIX > 0: K = KFIX known at compile time (the loop unrolls fully).
+template <int NT, int KFIX>
+__device__ __forceinline__ void fused_layer_k(f32x4 (&acc)[4][NT], const uint16_t *act, int P, const uint16_t *Wl,
+                                              int K, int nb, int l) {
+    const int ldw = KFIX > 0 ? KFIX : K;
+    const uint16_t *wrow = Wl + long(nb + (l & 15)) * ldw + 8 * (l >> 4);
+    bf16x8 bn[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * ldw);
+    if constexpr (KFIX > 0) {
+#pragma unroll
+        for (int k0 = 0; k0 < KFIX; k0 += 32) fused_k_step<NT>(acc, act, P, wrow, KFIX, KFIX, k0, bn, l);
+    } else {
+        for (int k0 = 0; k0 < K; k0 += 32) fused_k_step<NT>(acc, act, P, wrow, K, K, k0, bn, l);
+    }
+}
+
 template <int W>
-__global__ __launch_bounds__(kThreads) void fused_forward_kernel(long n, const float *__restrict__ x,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(long n, const float *__restrict__ x,
                                                                  const float *__restrict__ p,
                                                                  const float *__restrict__ Bf, int nf, int np,
                                                                  int K0, int depth, int nout,
@@ -318,19 +379,17 @@ __global__ __launch_bounds__(kThreads) void fused_forward_kernel(long n, const f
         if (i < n) {
             if (j < 2 * nf) {
                 const int f = j < nf ? j : j - nf;
-                const float a = 6.283185307179586f *
-                                (Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2]);
-                v = j < nf ? sinf(a) : cosf(a);
+                v = fourier_feature(
+                    Bf[3 * f] * x[3 * i] + Bf[3 * f + 1] * x[3 * i + 1] + Bf[3 * f + 2] * x[3 * i + 2], j < nf);
             } else if (j < 2 * nf + np) {
                 v = p[i * np + (j - 2 * nf)];
             }
         }
-        act[row * P + j] = f2bf(v);
+        act[row * P + j] = bf16_bits(v);
     }
     __syncthreads();
     constexpr int NT = W / 64;                     // 16-column tiles per wavefront
     const int nb = w * (W / 4);
-    int K = K0;
     for (int layer = 0; layer < depth; ++layer) {
         const uint16_t *Wl = wb + off.w[layer];
         f32x4 acc[4][NT];
@@ -338,44 +397,29 @@ __global__ __launch_bounds__(kThreads) void fused_forward_kernel(long n, const f
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // weight fragments of the next k step are requested before this step's MFMAs
-        const uint16_t *wrow = Wl + long(nb + (l & 15)) * K + 8 * (l >> 4);
-        bf16x8 bn[NT];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * K);
-        for (int k0 = 0; k0 < K; k0 += 32) {
-            bf16x8 b[NT];
-#pragma unroll
-            for (int j = 0; j < NT; ++j) b[j] = bn[j];
-            if (k0 + 32 < K) {
-#pragma unroll
-                for (int j = 0; j < NT; ++j)
-                    bn[j] = *reinterpret_cast<const bf16x8 *>(wrow + long(16 * j) * K + k0 + 32);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&act[(16 * i + (l & 15)) * P + k0 + 8 * (l >> 4)]);
-#pragma unroll
-                for (int j = 0; j < NT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
-            }
+        if (layer == 0) {
+            fused_layer_k<NT, 0>(acc, act, P, Wl, K0, nb, l);
+        } else {
+            fused_layer_k<NT, W>(acc, act, P, Wl, W, nb, l);
         }
         __syncthreads();
         const float *bias = wf + off.b[layer];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < NT; ++j) {
+            const int u0 = nb + 16 * j + 4 * (l >> 4);              // 4 consecutive units
+            const float4 bc = *reinterpret_cast<const float4 *>(bias + u0);
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int col = nb + 16 * j + (l & 15);
-                const float bc = bias[col];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * i + 4 * (l >> 4) + r;
-                    const float z = acc[i][j][r] + bc;
-                    act[row * P + col] = f2bf(z / (1.0f + expf(-z)));
-                }
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * i + (l & 15);                  // sample
+                const float z0 = acc[i][j][0] + bc.x, z1 = acc[i][j][1] + bc.y;
+                const float z2 = acc[i][j][2] + bc.z, z3 = acc[i][j][3] + bc.w;
+                uint2 q;
+                q.x = uint32_t(bf16_bits(z0 * sigmoidf_hw(z0))) | (uint32_t(bf16_bits(z1 * sigmoidf_hw(z1))) << 16);
+                q.y = uint32_t(bf16_bits(z2 * sigmoidf_hw(z2))) | (uint32_t(bf16_bits(z3 * sigmoidf_hw(z3))) << 16);
+                *reinterpret_cast<uint2 *>(&act[row * P + u0]) = q;
             }
+        }
         __syncthreads();
-        K = W;
     }
     // output layer: rows [16w, 16w + 16), up to four 16-column tiles
     const uint16_t *Wo = wb + off.w[depth];
