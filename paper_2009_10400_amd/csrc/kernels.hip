@@ -556,9 +556,13 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     float4 *lxyz = lds + A.max_nodes;                      // nloc: reference coordinates (GEOX)
     float4 *lout = lds + (GEOX ? 2 : 1) * A.max_nodes;     // (e1 - e0) * NPE
     const float *gx = GEOX ? A.lX + 3 * size_t(A.lx_begin[pid]) : nullptr;
+    // GEOX: the fourth float of a shared node's staged coordinate carries the
+    // position of its partial (read in the node phase without a global load)
     for (int l = threadIdx.x; l < nloc; l += BS) {
         lnode[l] = (l < nint) ? A.nu4[ib + l] : A.nu4[A.shared_ids[sb + l - nint]];
-        if (GEOX) lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2], 0.f);
+        if (GEOX)
+            lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2],
+                                  __int_as_float(l < nint ? 0 : A.ppos[sb + l - nint]));
     }
     __syncthreads();
     float psi = 0.f;
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             nf |= r.nonfinite;
             if (MON) node_monitor(p, r, A.Vl[a], mo);
         } else {
-            A.partial[A.ppos[sb + l - nint]] = acc;
+            A.partial[GEOX ? __float_as_int(lxyz[l].w) : A.ppos[sb + l - nint]] = acc;
         }
     }
     raise_flags(A.status, nf, inv);
