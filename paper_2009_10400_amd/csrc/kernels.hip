@@ -628,10 +628,21 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             mk = A.mask[a];
         }
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int k1 = lrow[l + 1];
-        for (int k = lrow[l]; k < k1; ++k) {
-            const float4 o = lout[lslot[k]];
-            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+        const int k0 = lrow[l], k1 = lrow[l + 1];
+        // slot indices in groups of eight independent global loads, so their
+        // latency is paid once per group (a T4 node has about five slots in a
+        // patch); sums in slot order
+        for (int k = k0; k < k1; k += 8) {
+            int sl[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sl[q] = (k + q < k1) ? int(lslot[k + q]) : -1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (sl[q] >= 0) {
+                    const float4 o = lout[sl[q]];
+                    acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
+                }
+            }
         }
         if (interior) {
             NodeNew r = node_advance(p, lnode[l], v0, th, mk, acc, src);
