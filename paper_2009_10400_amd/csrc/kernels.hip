@@ -556,13 +556,33 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     float4 *lxyz = lds + A.max_nodes;                      // nloc: reference coordinates (GEOX)
     float4 *lout = lds + (GEOX ? 2 : 1) * A.max_nodes;     // (e1 - e0) * NPE
     const float *gx = GEOX ? A.lX + 3 * size_t(A.lx_begin[pid]) : nullptr;
+    // Stage the local nodes.  The node ids of a thread's first two local nodes
+    // are requested before their data, so the id -> data chain is paid once.
     // GEOX: the fourth float of a shared node's staged coordinate carries the
-    // position of its partial (read in the node phase without a global load)
-    for (int l = threadIdx.x; l < nloc; l += BS) {
-        lnode[l] = (l < nint) ? A.nu4[ib + l] : A.nu4[A.shared_ids[sb + l - nint]];
-        if (GEOX)
-            lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2],
-                                  __int_as_float(l < nint ? 0 : A.ppos[sb + l - nint]));
+    // position of its partial (read in the node phase without a global load).
+    {
+        int nid[2];
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int l = threadIdx.x + it * BS;
+            nid[it] = l < nint ? ib + l : (l < nloc ? A.shared_ids[sb + l - nint] : -1);
+        }
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int l = threadIdx.x + it * BS;
+            if (l < nloc) {
+                lnode[l] = A.nu4[nid[it]];
+                if (GEOX)
+                    lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2],
+                                          __int_as_float(l < nint ? 0 : A.ppos[sb + l - nint]));
+            }
+        }
+        for (int l = threadIdx.x + 2 * BS; l < nloc; l += BS) {
+            lnode[l] = (l < nint) ? A.nu4[ib + l] : A.nu4[A.shared_ids[sb + l - nint]];
+            if (GEOX)
+                lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2],
+                                      __int_as_float(l < nint ? 0 : A.ppos[sb + l - nint]));
+        }
     }
     __syncthreads();
     float psi = 0.f;
