@@ -45,7 +45,7 @@ __device__ __forceinline__ float fourier_feature(float t, bool sine) {
     return sine ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
 }
 
-enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2 };
+enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2, EPI_SILU_BACK = 3 };
 // How an operand tile is read from global memory: element by element (any
 // strides), 16-byte vectors along k (k contiguous), or 16-byte vectors along
 // the tile's rows (rows contiguous).  Chosen on the host from strides and alignment.
@@ -107,7 +107,10 @@ __device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t) 
 // k-tile is read from global memory into registers while the current one is
 // multiplied out of LDS.
 // Epilogues: EPI_F32 C(m,n) = acc; EPI_BIAS_F32 C = acc + bias[n];
-// EPI_BIAS_SILU Z = acc + bias[n] (FP32 into C) and Act[m*N+n] = bf16(Z sigmoid(Z)).
+// EPI_BIAS_SILU Z = acc + bias[n] (FP32 into C) and Act[m*N+n] = bf16(Z sigmoid(Z));
+// EPI_SILU_BACK (backward through a SiLU; `bias` then points at the layer's FP32
+// pre-activations z, row-major M x N): Act[m*N+n] = bf16(acc s (1 + z (1 - s))),
+// s = sigmoid(z).
 // Split-K: workgroup z covers k in [z*kchunk, (z+1)*kchunk) and (EPI_F32 only)
 // writes its partial tile to C + z*M*N (row-major M x N); a reduction follows.
 template <int EPI, int AM, int BMODE>
@@ -167,6 +170,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
                     else C[m * scm + n * scn] = v;
                 } else if (EPI == EPI_BIAS_F32) {
                     C[m * scm + n * scn] = v + bias[n];
+                } else if (EPI == EPI_SILU_BACK) {
+                    const float z = bias[size_t(m) * N + n], sg = sigmoidf_hw(z);
+                    Act[size_t(m) * N + n] = bf16_bits(v * sg * (1.0f + z * (1.0f - sg)));
                 } else {
                     const float z = v + bias[n];
                     C[m * scm + n * scn] = z;
@@ -202,15 +208,6 @@ __global__ void features_kernel(long n, const float *__restrict__ x, const float
         v = p[i * np + (j - 2 * nf)];
     }
     out[idx] = bf16_bits(v);
-}
-
-// dZ = dA * d(SiLU)/dz = dA s (1 + z (1 - s)), s = sigmoid(z); bfloat16 out.
-__global__ void silu_back_kernel(long n, const float *__restrict__ dA, const float *__restrict__ Z,
-                                 uint16_t *__restrict__ dZ) {
-    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float z = Z[i], s = sigmoidf_hw(z);
-    dZ[i] = bf16_bits(dA[i] * s * (1.0f + z * (1.0f - s)));
 }
 
 // dY = 2 (Y - T) / (n n_out) (bfloat16) and per-block sums of (Y - T)^2.
@@ -261,19 +258,22 @@ __global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict_
     part[size_t(blockIdx.y) * N + j] = s;
 }
 
-// Fixed-order sum of the chunk partials: four interleaved accumulators (chunk
-// c into accumulator c % 4), combined as (a0 + a1) + (a2 + a3).
-__global__ void colsum_final_kernel(int nchunks, int N, const float *__restrict__ part, float *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    float a[4] = {0.f, 0.f, 0.f, 0.f};
-    int c = 0;
-    for (; c + 4 <= nchunks; c += 4) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] += part[size_t(c + q) * N + j];
+// Fixed-order sum of the chunk partials: a block covers 64 columns with four
+// threads per column; thread q sums chunks q, q + 4, q + 8, ... in order, and the
+// four sums are combined as (s0 + s1) + (s2 + s3).
+__global__ __launch_bounds__(kThreads) void colsum_final_kernel(int nchunks, int N, const float *__restrict__ part,
+                                                                float *__restrict__ out) {
+    __shared__ float sh[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    float a = 0.f;
+    if (c < N)
+        for (int ch = q; ch < nchunks; ch += 4) a += part[size_t(ch) * N + c];
+    sh[q][threadIdx.x & 63] = a;
+    __syncthreads();
+    if (q == 0 && c < N) {
+        const int j = threadIdx.x & 63;
+        out[c] = (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
     }
-    for (; c < nchunks; ++c) a[c % 4] += part[size_t(c) * N + j];
-    out[j] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // Adam on the FP32 master parameters; refreshes the bfloat16 copy.
@@ -483,8 +483,8 @@ struct tled_mlp {
     uint16_t *d_x0 = nullptr;
     std::vector<float *> d_z;        // per hidden layer, cap x width
     std::vector<uint16_t *> d_a;     // per hidden layer, cap x width
-    float *d_y = nullptr, *d_da = nullptr, *d_part = nullptr, *d_loss = nullptr, *d_cpart = nullptr;
-    uint16_t *d_dy = nullptr, *d_dz = nullptr;
+    float *d_y = nullptr, *d_part = nullptr, *d_loss = nullptr, *d_cpart = nullptr;
+    uint16_t *d_dy = nullptr, *d_dz = nullptr, *d_dz2 = nullptr;   // dZ of two adjacent layers
     std::vector<void *> ws;
     std::string err;
     float *d_split = nullptr;        // split-K partials
@@ -555,8 +555,8 @@ tled_status ensure_workspace(tled_mlp *s, long n) {
     }
     MTRY(walloc(s, &s->d_y, size_t(cap) * no));
     MTRY(walloc(s, &s->d_dy, size_t(cap) * no));
-    MTRY(walloc(s, &s->d_da, size_t(cap) * W));
     MTRY(walloc(s, &s->d_dz, size_t(cap) * W));
+    MTRY(walloc(s, &s->d_dz2, size_t(cap) * W));
     MTRY(walloc(s, &s->d_part, size_t(blocks(cap * no))));
     MTRY(walloc(s, &s->d_loss, 1));
     MTRY(walloc(s, &s->d_cpart, size_t((cap + kColChunk - 1) / kColChunk) * std::max<long>(W, no)));
@@ -716,23 +716,27 @@ tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
                        nullptr));
     hipLaunchKernelGGL(colsum_partial_kernel, dim3((no + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
                        s->stream, n, no, s->d_dy, s->d_cpart, chunk);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((no + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
-                       int(nchunk), no, s->d_cpart, s->d_g + O.b_off);
-    MTRY(gemm<EPI_F32>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, s->d_da, W, 1, nullptr, nullptr));
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((no + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk), no,
+                       s->d_cpart, s->d_g + O.b_off);
+    // dZ of the last hidden layer = (dY W_O) through its SiLU, in the GEMM epilogue
+    uint16_t *dz = s->d_dz, *dz_next = s->d_dz2;
+    MTRY(gemm<EPI_SILU_BACK>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, nullptr, W, 1, dz,
+                             s->d_z[D - 1]));
     for (int l = D - 1; l >= 0; --l) {
         const Layer &L = s->layers[l];
-        hipLaunchKernelGGL(silu_back_kernel, dim3(blocks(n * W)), dim3(kThreads), 0, s->stream, n * W, s->d_da,
-                           s->d_z[l], s->d_dz);
         const uint16_t *ain = l > 0 ? s->d_a[l - 1] : s->d_x0;
         const int in = L.in;
-        MTRY(gemm<EPI_F32>(s, W, in, int(n), s->d_dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr));
+        MTRY(gemm<EPI_F32>(s, W, in, int(n), dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr));
         hipLaunchKernelGGL(colsum_partial_kernel, dim3((W + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
-                           s->stream, n, W, s->d_dz, s->d_cpart, chunk);
-        hipLaunchKernelGGL(colsum_final_kernel, dim3((W + kThreads - 1) / kThreads), dim3(kThreads), 0, s->stream,
-                           int(nchunk), W, s->d_cpart, s->d_g + L.b_off);
-        if (l > 0)
-            MTRY(gemm<EPI_F32>(s, int(n), in, W, s->d_dz, W, 1, s->d_wb + L.w_off, in, 1, s->d_da, in, 1, nullptr,
-                               nullptr));
+                           s->stream, n, W, dz, s->d_cpart, chunk);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((W + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk), W,
+                           s->d_cpart, s->d_g + L.b_off);
+        if (l > 0) {
+            // dZ of layer l - 1 = (dZ_l W_l) through layer l - 1's SiLU
+            MTRY(gemm<EPI_SILU_BACK>(s, int(n), in, W, dz, W, 1, s->d_wb + L.w_off, in, 1, nullptr, in, 1, dz_next,
+                                     s->d_z[l - 1]));
+            std::swap(dz, dz_next);
+        }
     }
     MCHK(s, hipGetLastError());
     if (loss) {
