@@ -18,7 +18,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int BM = 64, BN = 64, BK = 32, BKP = BK + 8;   // LDS rows padded against bank conflicts
+constexpr int BM = 64, BN = 64, BK = 64, BKP = BK + 8;   // LDS rows padded against bank conflicts
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 // float -> bfloat16 bits by the hardware convert (v_cvt_pk_bf16_f32 on gfx950,
@@ -51,17 +51,17 @@ enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2, EPI_SILU_BACK = 3 };
 // the tile's rows (rows contiguous).  Chosen on the host from strides and alignment.
 enum { LD_SCALAR = 0, LD_KVEC = 1, LD_RVEC = 2 };
 
-// One thread's share (8 values) of a 64 x 32 operand tile X(r, k) = X[r*sr + k*sk],
-// rows r0.., k in [k0, k0 + 32), zero outside r < R, k < ke.
+// One thread's share (8 values) of half h (k in [k0 + 32h, k0 + 32h + 32)) of a
+// 64 x 64 operand tile X(r, k) = X[r*sr + k*sk], rows r0.., zero outside r < R, k < ke.
 struct TileRegs {
     uint16_t v[8];
 };
 
 template <int MODE>
 __device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, long sr, long sk, int r0, int R,
-                                 int k0, int ke, int t) {
+                                 int k0, int ke, int t, int h) {
     if (MODE == LD_KVEC) {
-        const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+        const int r = r0 + (t >> 2), k = k0 + 32 * h + (t & 3) * 8;
         if (r < R && k + 8 <= ke) {
             const uint4 w = *reinterpret_cast<const uint4 *>(X + r * sr + k);
             std::memcpy(q.v, &w, 16);
@@ -70,7 +70,7 @@ __device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, lo
             for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + k + i] : uint16_t(0);
         }
     } else if (MODE == LD_RVEC) {
-        const int k = k0 + (t >> 3), r = r0 + (t & 7) * 8;
+        const int k = k0 + 32 * h + (t >> 3), r = r0 + (t & 7) * 8;
         if (k < ke && r + 8 <= R) {
             const uint4 w = *reinterpret_cast<const uint4 *>(X + k * sk + r);
             std::memcpy(q.v, &w, 16);
@@ -79,21 +79,21 @@ __device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, lo
             for (int i = 0; i < 8; ++i) q.v[i] = (k < ke && r + i < R) ? X[k * sk + r + i] : uint16_t(0);
         }
     } else {
-        const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+        const int r = r0 + (t >> 2), k = k0 + 32 * h + (t & 3) * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + (k + i) * sk] : uint16_t(0);
     }
 }
 
-// Stores a thread's share into the LDS tile S[r][k] (row pitch BKP).
+// Stores a thread's share of half h into the LDS tile S[r][k] (row pitch BKP).
 template <int MODE>
-__device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t) {
+__device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t, int h) {
     if (MODE == LD_RVEC) {
-        const int k = t >> 3, r = (t & 7) * 8;
+        const int k = 32 * h + (t >> 3), r = (t & 7) * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) S[r + i][k] = q.v[i];
     } else {
-        const int r = t >> 2, k = (t & 3) * 8;
+        const int r = t >> 2, k = 32 * h + (t & 3) * 8;
         uint4 w;
         std::memcpy(&w, q.v, 16);
         *reinterpret_cast<uint4 *>(&S[r][k]) = w;
@@ -103,9 +103,8 @@ __device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t) 
 // C = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (bfloat16 bits).
 // 64x64 output tile per workgroup of four wavefronts, each wavefront 32x32 as
 // 2x2 MFMA 16x16x32 tiles.  Lane l of a 16x16x32 MFMA supplies A[l%16][8(l/16)..+7]
-// and B[8(l/16)..+7][l%16] and receives D[4(l/16)+r][l%16], r = 0..3.  The next
-// k-tile is read from global memory into registers while the current one is
-// multiplied out of LDS.
+// and B[8(l/16)..+7][l%16] and receives D[4(l/16)+r][l%16], r = 0..3.  k runs in
+// 64-deep LDS tiles (two 32-deep MFMA steps each, in increasing k).
 // Epilogues: EPI_F32 C(m,n) = acc; EPI_BIAS_F32 C = acc + bias[n];
 // EPI_BIAS_SILU Z = acc + bias[n] (FP32 into C) and Act[m*N+n] = bf16(Z sigmoid(Z));
 // EPI_SILU_BACK (backward through a SiLU; `bias` then points at the layer's FP32
@@ -119,8 +118,8 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
                                                         long sbn, float *__restrict__ C, long scm, long scn,
                                                         uint16_t *__restrict__ Act, const float *__restrict__ bias,
                                                         int kchunk) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM][BKP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bt[BN][BKP];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][BKP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[2][BN][BKP];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -131,26 +130,50 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     if (gridDim.z > 1) C += size_t(blockIdx.z) * M * N;
-    TileRegs qa, qb;
-    if (kb < ke) {
-        tile_load<AM>(qa, A, sam, sak, m0, M, kb, ke, t);
-        tile_load<BMODE>(qb, B, sbn, sbk, n0, N, kb, ke, t);
+    const int ntiles = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    TileRegs qa[2], qb[2];
+    // double-buffered 64-deep k tiles: tile t + 1 is read from global memory into
+    // registers while tile t is multiplied out of LDS; one barrier per tile
+    if (ntiles > 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            tile_load<AM>(qa[h], A, sam, sak, m0, M, kb, ke, t, h);
+            tile_load<BMODE>(qb[h], B, sbn, sbk, n0, N, kb, ke, t, h);
+            tile_store<AM>(qa[h], As[0], t, h);
+            tile_store<BMODE>(qb[h], Bt[0], t, h);
+        }
     }
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        tile_store<AM>(qa, As, t);
-        tile_store<BMODE>(qb, Bt, t);
-        __syncthreads();
-        if (k0 + BK < ke) {
-            tile_load<AM>(qa, A, sam, sak, m0, M, k0 + BK, ke, t);
-            tile_load<BMODE>(qb, B, sbn, sbk, n0, N, k0 + BK, ke, t);
+    __syncthreads();
+    for (int tk = 0; tk < ntiles; ++tk) {
+        const int k0 = kb + tk * BK, cur = tk & 1;
+        const bool more = tk + 1 < ntiles;
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                tile_load<AM>(qa[h], A, sam, sak, m0, M, k0 + BK, ke, t, h);
+                tile_load<BMODE>(qb[h], B, sbn, sbk, n0, N, k0 + BK, ke, t, h);
+            }
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + (l & 15)][8 * (l >> 4)]);
+        for (int h = 0; h < 2; ++h) {
+            if (k0 + 32 * h >= ke) break;        // the same 32-deep MFMA steps as a 32-deep loop
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bt[wn + 16 * j + (l & 15)][8 * (l >> 4)]);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const bf16x8 a =
+                    *reinterpret_cast<const bf16x8 *>(&As[cur][wm + 16 * i + (l & 15)][32 * h + 8 * (l >> 4)]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const bf16x8 b =
+                        *reinterpret_cast<const bf16x8 *>(&Bt[cur][wn + 16 * j + (l & 15)][32 * h + 8 * (l >> 4)]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                tile_store<AM>(qa[h], As[cur ^ 1], t, h);
+                tile_store<BMODE>(qb[h], Bt[cur ^ 1], t, h);
             }
         }
         __syncthreads();
