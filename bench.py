@@ -146,8 +146,8 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
     print(json.dumps(out), flush=True)
 
 
-def traffic_from_profiles(kernel_name: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it is current."""
+def traffic_record(workload: str):
+    """The committed rocprofv3 counter summary of the solver kernels, if it is current."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -155,11 +155,35 @@ def traffic_from_profiles(kernel_name: str, workload: str):
         with open(path) as f:
             d = json.load(f)
         from paper_2009_10400_amd.build import source_digest
-        if d.get("source_digest") != source_digest() or d.get("kernel") != kernel_name:
-            return None
-        return float(d["bytes_per_launch"])
+        return d if d.get("source_digest") == source_digest() else None
     except Exception:  # noqa: BLE001
         return None
+
+
+def traffic_from_profiles(kernel_name: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the counter summary, if it is current."""
+    d = traffic_record(workload)
+    if d is None or d.get("kernel") != kernel_name:
+        return None
+    return float(d["bytes_per_launch"])
+
+
+def copy_bandwidth(mib: int = 1024, reps: int = 5):
+    """GB/s of a plain device-to-device copy (read + write bytes / time), HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(problem, dt, steps):
@@ -415,6 +439,19 @@ def main():
             "kernel_ms": kt["element_ms"], "second_kernel_ms": kt["node_ms"],
             "algorithmic_bytes_per_launch": alg_bytes}
     log(f"[bench] kernel times {kt}")
+    # the whole step's HBM traffic (both kernels, counted) against peak and against a plain copy
+    step_hbm = None
+    rec = traffic_record(p.name) if info["kernel_variant"] >= 2 else None
+    if rec is not None:
+        sf, sw = rec["shared_node_kernel_kib"]
+        step_bytes = rec["bytes_per_launch"] + 1024.0 * (sf * rec["fetch_scale"] + sw * rec["write_scale"])
+        gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
+        cbw = copy_bandwidth()
+        step_hbm = {"bytes_counted": step_bytes, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+                    "copy_GBs": cbw, "frac_of_copy": gbs / cbw,
+                    "note": "counted FETCH+WRITE bytes of the patch and shared-node kernels per step / "
+                            "whole-step time; copy = 1 GiB device copy on the same GPU"}
+        log(f"[bench] step HBM {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f} of peak, {gbs / cbw:.3f} of copy {cbw:.0f} GB/s)")
     out = {
         "metric": "coupled element-updates/s (HBM % peak)",
         "value": value, "unit": "element-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -428,6 +465,7 @@ def main():
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
                    "graph_steps": args.graph_steps, "patches": info["n_patches"], "dt": sim.dt},
         "roofline": roof,
+        "step_hbm": step_hbm,
     }
     if not args.no_cpu_baseline and p.npe == 4:
         steps = args.cpu_steps or max(3, int(40e6 / p.ne))

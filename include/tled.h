@@ -135,6 +135,9 @@ typedef struct {
     double  dt, dt_critical;
     int32_t patch_wgs_per_cu; /* fused variant on a device: resident patch workgroups per CU  */
     int32_t reserved;
+    double  dt_thermal;      /* explicit thermal stability bound (Gershgorin, reference
+                                geometry, largest k and smallest c the material reaches);
+                                finalize refuses a dt above it                             */
 } tled_info;
 
 /* --- lifetime ----------------------------------------------------------

@@ -711,6 +711,9 @@ tled_status tled_finalize(tled_sim *sim) {
     if (st != TLED_OK) return st;
     if (sim->prob.dt > sim->pc.dt_cr)
         return fail(sim, TLED_E_ARG, "dt exceeds the critical time step " + std::to_string(sim->pc.dt_cr));
+    if (sim->prob.dt > sim->pc.dt_th)
+        return fail(sim, TLED_E_ARG, "dt exceeds the explicit thermal stability limit " +
+                                         std::to_string(sim->pc.dt_th));
     sim->variant = v;
     if (v >= 2) {
         PatchArgs probe{};
@@ -849,6 +852,7 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
         }
         out->device_bytes = sim->device_bytes;
         out->dt_critical = sim->pc.dt_cr;
+        out->dt_thermal = sim->pc.dt_th;
     }
     return TLED_OK;
 }
@@ -1111,6 +1115,10 @@ tled_status tled_batch_finalize(tled_batch *b) {
         if (b->scen[k].dt > b->ranges[k].dt_cr)
             return fail(b, TLED_E_ARG, "scenario " + std::to_string(k) + ": dt exceeds the critical step " +
                                            std::to_string(b->ranges[k].dt_cr));
+        else if (b->scen[k].dt > b->ranges[k].dt_th)
+            return fail(b, TLED_E_ARG, "scenario " + std::to_string(k) +
+                                           ": dt exceeds the explicit thermal stability limit " +
+                                           std::to_string(b->ranges[k].dt_th));
     PatchArgs probe{};
     probe.max_nodes = b->pc.patches.max_nodes;
     probe.max_elems = b->pc.patches.slot_stride;

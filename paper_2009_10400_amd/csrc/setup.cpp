@@ -500,6 +500,51 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
         if (!p.Tfix.empty()) pc.Tfix[a] = p.Tfix[o];
     }
 
+    // Explicit thermal stability: forward Euler on C dT/dt = -(K + K_b) T + ... is
+    // stable for dt <= 2 / lambda_max(C^-1 (K + K_b)), and by Gershgorin
+    // lambda_max <= max_a (sum_b |K_ab| + K_b,a) / C_a.  K is taken on the reference
+    // geometry with the largest conductivity the material reaches (k, k_m, k(T)),
+    // |K_e,ab| <= V0 k_max |dh_a/dX| |dh_b/dX|; C with the smallest heat capacity (c(T)).
+    {
+        const tled_material &m = p.mat;
+        double kmax = m.k;
+        if (m.cond_mode == 1) kmax = std::max(kmax, m.k_m);
+        if (m.ckT_on && m.k > 0.0) kmax *= std::max(1.0, m.k_hi / m.k);
+        const double cmin = m.ckT_on ? std::min(m.c, m.c_hi) : m.c;
+        std::vector<double> rowsum(nn, 0.0);
+        for (int64_t ei = 0; ei < ne; ++ei) {
+            const ElemGeo &g = geo[eorder[ei]];
+            double gn[8];
+            if (npe == 4) {
+                double r0[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < 3; ++k) {
+                    const double *r = g.geo + 3 * k;
+                    gn[k + 1] = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                    for (int i = 0; i < 3; ++i) r0[i] -= r[i];
+                }
+                gn[0] = std::sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+            } else {
+                for (int a = 0; a < 8; ++a) {
+                    double d2 = 0.0;
+                    for (int j = 0; j < 3; ++j) {
+                        const double dh = (g.geo[3 * j] * kHexSign[a][0] + g.geo[3 * j + 1] * kHexSign[a][1] +
+                                           g.geo[3 * j + 2] * kHexSign[a][2]) / 8.0;
+                        d2 += dh * dh;
+                    }
+                    gn[a] = std::sqrt(d2);
+                }
+            }
+            double sum = 0.0;
+            for (int a = 0; a < npe; ++a) sum += gn[a];
+            for (int a = 0; a < npe; ++a) rowsum[pc.conn[npe * ei + a]] += g.V0 * kmax * gn[a] * sum;
+        }
+        pc.dt_th = std::numeric_limits<double>::infinity();
+        for (int64_t a = 0; a < nn; ++a) {
+            const double den = rowsum[a] + m.wbcb * pc.Vl[a];
+            if (den > 0.0) pc.dt_th = std::min(pc.dt_th, 2.0 * m.rho * cmin * pc.Vl[a] / den);
+        }
+    }
+
     if (opt.build_patches) build_patches(&pc, std::max(8, std::min(opt.patch_elems, 65536 / npe)), p.X);
 
     // node -> element-slot incidence (ascending slot order)
@@ -637,6 +682,7 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
             R.sh_lo = NI + so_; R.sh_hi = NI + so_ + nsh;
             R.patch_lo = int32_t(o.patch); R.patch_hi = int32_t(o.patch + Q.n);
             R.dt_cr = pc.dt_cr;
+            R.dt_th = pc.dt_th;
             R.n_swapped = pc.n_swapped;
             R.node_of.resize(pc.nn);
             for (int64_t a = 0; a < pc.nn; ++a) R.node_of[pc.node_new2old[a]] = map(a);

@@ -79,6 +79,7 @@ struct Precomputed {
     std::vector<int32_t> inc;       // ne * npe values e * npe + s, ascending per node
     int64_t n_swapped = 0;
     double dt_cr = 0.0;
+    double dt_th = 0.0;                      // explicit thermal stability bound (Gershgorin)
     Patches patches;
 };
 
@@ -91,6 +92,7 @@ struct ScenRange {
     std::vector<int64_t> node_of;         // caller node index -> union internal index
     std::vector<int64_t> elem_of;         // caller element index -> union internal index
     double dt_cr = 0.0;
+    double dt_th = 0.0;
     int64_t n_swapped = 0;
 };
 

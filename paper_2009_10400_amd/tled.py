@@ -91,7 +91,7 @@ class Info(ctypes.Structure):
                 ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
                 ("n_shared_nodes", _i64), ("patch_max_nodes", _i32), ("patch_lds_bytes", _i32),
                 ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d), ("patch_wgs_per_cu", _i32),
-                ("reserved", _i32)]
+                ("reserved", _i32), ("dt_thermal", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -222,3 +222,45 @@ def test_batch_setup_is_independent_of_host_threads(monkeypatch):
         infos.append((b.batch_info(), [b.scenario_steps(k) for k in range(len(sc))]))
         b.close()
     assert infos[0] == infos[1]
+
+
+def _tet_gradients(X, conn):
+    """Shape-function gradients (ne x 4 x 3) and volumes of linear tets (numpy, FP64)."""
+    D = np.stack([X[conn[:, k]] - X[conn[:, 0]] for k in (1, 2, 3)], axis=2)   # columns X_k - X_0
+    Di = np.linalg.inv(D)
+    g = np.concatenate([-Di.sum(axis=1, keepdims=True), Di], axis=1)
+    return g, np.abs(np.linalg.det(D)) / 6.0
+
+
+def test_thermal_stability_bound():
+    """dt_thermal = 2 min_a C_a / (sum_b |K_ab| bound + K_b,a) on the reference geometry; it bounds
+    the true largest eigenvalue of C^-1 (K + K_b), and finalize refuses a larger dt."""
+    from paper_2009_10400_amd import tled
+    p = W.cube_t4(n=3, L=0.01)
+    info = host_sim(p).info()
+    m = p.params
+    g, V = _tet_gradients(p.X, p.conn)
+    gn = np.linalg.norm(g, axis=2)                                           # |dh_a/dX|
+    nn = len(p.X)
+    rows = np.zeros(nn)
+    Vl = np.zeros(nn)
+    K = np.zeros((nn, nn))
+    kmax = m["k"] * max(1.0, m["k_hi"] / m["k"]) if m.get("ckT_on") else m["k"]
+    for e, c in enumerate(p.conn):
+        rows[c] += V[e] * kmax * gn[e] * gn[e].sum()
+        Vl[c] += V[e] / 4
+        K[np.ix_(c, c)] += V[e] * kmax * g[e] @ g[e].T
+    cmin = min(m["c"], m["c_hi"]) if m.get("ckT_on") else m["c"]
+    C = m["rho"] * cmin * Vl
+    expect = 2.0 * np.min(C / (rows + m["wbcb"] * Vl))
+    assert info["dt_thermal"] == pytest.approx(expect, rel=1e-12)
+    lam = np.max(np.linalg.eigvals((K + np.diag(m["wbcb"] * Vl)) / C[:, None]).real)
+    assert 2.0 / lam >= info["dt_thermal"] * (1 - 1e-12)          # the bound is conservative
+    assert info["dt_thermal"] > info["dt_critical"]                # mechanics sets the step here
+    # a conductivity high enough to make the thermal bound binding is refused at finalize
+    hot = W.cube_t4(n=3, L=0.01)
+    hot.params = dict(hot.params, k=1e6, k_hi=1e6)
+    s = tled.from_problem(hot, dt=1e-5, device=-1, finalize=False)
+    with pytest.raises(tled.TledError) as e:
+        s.finalize()
+    assert e.value.status == tled.E_ARG and "thermal" in str(e.value)
