@@ -606,10 +606,10 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
     if (nz > 1) {
         const size_t need = size_t(nz) * M * N;
         if (need > s->split_cap) {
+            MCHK(s, hipStreamSynchronize(s->stream));   // earlier launches may still use the old buffer
             if (s->d_split) (void)hipFree(s->d_split);
             s->d_split = nullptr;
             s->split_cap = 0;
-            MCHK(s, hipStreamSynchronize(s->stream));
             void *p = nullptr;
             if (hipMalloc(&p, need * sizeof(float)) != hipSuccess) return mfail(s, TLED_E_OOM, "hipMalloc failed");
             s->d_split = static_cast<float *>(p);

@@ -73,6 +73,17 @@ def _dp(t):
     return _P(t.data_ptr())
 
 
+def _need(t, rows, cols, dtype, name):
+    """Refuse a tensor the kernels would misread (they take plain row-major device pointers)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: a CUDA/HIP device tensor is required")
+    if t.dtype != dtype or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != cols or \
+            (rows is not None and t.shape[0] != rows):
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of shape "
+                         f"({rows if rows is not None else 'n'}, {cols}), got {tuple(t.shape)} {t.dtype}")
+
+
 class MLP:
     """One network on one device (device tensors via torch)."""
 
@@ -136,19 +147,36 @@ class MLP:
         self._check(fn(self._h, *args))
         cur.wait_stream(self._stream)
 
+    def _inputs(self, x, p, y=None):
+        import torch
+        _need(x, None, 3, torch.float32, "coords")
+        n = x.shape[0]
+        if self.cfg["n_param"] > 0:
+            _need(p, n, self.cfg["n_param"], torch.float32, "params")
+        if y is not None:
+            _need(y, n, self.cfg["n_out"], torch.float32, "target")
+        for t in (p, y):
+            if t is not None and t.device != x.device:
+                raise ValueError("all tensors must be on the same device")
+        if x.device.index != self.device:
+            raise ValueError(f"tensors are on {x.device}, the network on device {self.device}")
+
     def forward(self, x, p):
         import torch
+        self._inputs(x, p)
         out = torch.empty((x.shape[0], self.cfg["n_out"]), dtype=torch.float32, device=x.device)
         self._call(_lib.tled_mlp_forward, x.shape[0], _dp(x), _dp(p), _dp(out))
         return out
 
     def train_step(self, x, p, y, lr: float, want_loss: bool = False):
+        self._inputs(x, p, y)
         loss = _f(0.0)
         self._call(_lib.tled_mlp_train_step, x.shape[0], _dp(x), _dp(p), _dp(y), float(lr),
                    ctypes.byref(loss) if want_loss else None)
         return loss.value if want_loss else None
 
     def gradient(self, x, p, y):
+        self._inputs(x, p, y)
         g = np.zeros(self.n_params, np.float32)
         loss = _f(0.0)
         self._call(_lib.tled_mlp_gradient, x.shape[0], _dp(x), _dp(p), _dp(y), g.ctypes.data_as(_fp),
@@ -157,8 +185,12 @@ class MLP:
 
     def gemm(self, A_bits, B_bits, C):
         """C = A B on the matrix cores; A, B int16 tensors of bfloat16 bits, C float32."""
+        import torch
         m, k = A_bits.shape
         n = B_bits.shape[1]
+        _need(A_bits, m, k, torch.int16, "A")
+        _need(B_bits, k, n, torch.int16, "B")
+        _need(C, m, n, torch.float32, "C")
         self._call(_lib.tled_mlp_gemm, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C))
 
     def set_timing(self, on: bool):

@@ -313,6 +313,12 @@ class Sim:
 
     def copy_fields_device(self, u_dst=None, T_dst=None):
         """Write u (nn x 3) and T (nn) as float32 into device tensors (caller numbering)."""
+        import torch
+        n = self.info()["n_nodes"]
+        for t, shape, name in ((u_dst, (n, 3), "u_dst"), (T_dst, (n,), "T_dst")):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+                                  or not t.is_contiguous() or tuple(t.shape) != shape):
+                raise ValueError(f"{name}: expected a contiguous float32 device tensor of shape {shape}")
         up = None if u_dst is None else _P(u_dst.data_ptr())
         tp = None if T_dst is None else _P(T_dst.data_ptr())
         self._check(_lib.tled_copy_fields_device(self._h, up, tp))

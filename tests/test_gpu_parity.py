@@ -215,7 +215,15 @@ def test_device_field_copy_and_torch_allocator():
     s.sync()
     assert np.array_equal(u_t.cpu().numpy(), s.read_u().astype(np.float32))
     assert np.allclose(T_t.cpu().numpy(), s.read_T(), atol=1e-4)
-    assert s.info()["device_bytes"] > 0
+    info = s.info()
+    assert info["device_bytes"] > 0
+    assert 1 <= info["patch_wgs_per_cu"] <= 8
+    assert info["dt_thermal"] > info["dt"]
+    # targets the copy kernel would misread are refused by the binding
+    with pytest.raises(ValueError):
+        s.copy_fields_device(torch.zeros((p.nn, 3), dtype=torch.float64, device="cuda:0"), None)
+    with pytest.raises(ValueError):
+        s.copy_fields_device(None, torch.zeros(p.nn - 1, dtype=torch.float32, device="cuda:0"))
 
 
 @pytest.mark.parametrize("variant", VARIANTS)

@@ -172,3 +172,15 @@ def test_argument_errors(torch_dev):
     with pytest.raises(TledError):
         m.train_step(torch.zeros((4, 3), device=torch_dev), torch.zeros((4, 2), device=torch_dev),
                      torch.zeros((4, 2), device=torch_dev), -1.0)
+    # tensors the kernels would misread are refused by the binding
+    with pytest.raises(ValueError):
+        m.forward(torch.zeros((4, 3), dtype=torch.float64, device=torch_dev), torch.zeros((4, 2), device=torch_dev))
+    with pytest.raises(ValueError):
+        m.forward(torch.zeros((3, 4), device=torch_dev).t(), torch.zeros((4, 2), device=torch_dev))
+    with pytest.raises(ValueError):
+        m.forward(torch.zeros((4, 3), device=torch_dev), torch.zeros((5, 2), device=torch_dev))
+    with pytest.raises(ValueError):
+        m.train_step(torch.zeros((4, 3), device=torch_dev), torch.zeros((4, 2), device=torch_dev),
+                     torch.zeros((4, 3), device=torch_dev), 1e-3)
+    with pytest.raises(ValueError):
+        m.forward(torch.zeros((4, 3)), torch.zeros((4, 2)))
