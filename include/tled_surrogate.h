@@ -75,6 +75,14 @@ tled_status tled_mlp_train_step(tled_mlp *mlp, int64_t n, const float *coords, c
  * array in the parameter layout), without a step; *loss optional. */
 tled_status tled_mlp_gradient(tled_mlp *mlp, int64_t n, const float *coords, const float *params,
                               const float *target, float *grad_host, float *loss);
+/* Ensemble statistics of `members` networks' outputs (device arrays, FP32):
+ * outs is members x n x n_out (member-major, each member's n x n_out block as
+ * tled_mlp_forward writes it); scale (n_out) multiplies the results:
+ * mean[i][o] = scale[o] * mean_k outs[k][i][o], spread[i] = scale[0] *
+ * (max_k - min_k) outs[k][i][0].  Enqueued on hip_stream (NULL: the null
+ * stream); asynchronous.  Returns TLED_E_ARG on bad sizes or null pointers. */
+tled_status tled_mlp_ensemble_stats(int64_t n, int32_t members, int32_t n_out, const float *outs,
+                                    const float *scale, float *mean, float *spread, void *hip_stream);
 /* Plain GEMM on the matrix cores, for tests of the kernel itself:
  * C[m][n] = sum_k A[m][k] B[k][n], A (m x k) and B (k x n) bfloat16 bit
  * patterns (device, row-major), C FP32 (device, row-major). */

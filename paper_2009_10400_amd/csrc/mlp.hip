@@ -480,6 +480,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     }
 }
 
+// Ensemble statistics over K members' outputs (K x n x n_out, member-major):
+// mean[i][o] = scale[o] (sum_k out[k][i][o]) / K and
+// spread[i] = scale[0] (max_k out[k][i][0] - min_k out[k][i][0]); members summed in order.
+__global__ void ensemble_stats_kernel(long n, int K, int nout, const float *__restrict__ outs,
+                                      const float *__restrict__ scale, float *__restrict__ mean,
+                                      float *__restrict__ spread) {
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float invK = 1.0f / float(K);
+    for (int o = 0; o < nout; ++o) {
+        float s = 0.f, lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            const float v = outs[(size_t(k) * n + i) * nout + o];
+            s += v;
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        mean[i * nout + o] = scale[o] * s * invK;
+        if (o == 0) spread[i] = scale[0] * (hi - lo);
+    }
+}
+
 inline unsigned blocks(long n) { return unsigned((n + kThreads - 1) / kThreads); }
 
 struct Layer {
@@ -948,6 +970,17 @@ tled_status tled_mlp_gemm(tled_mlp *s, int32_t m, int32_t n, int32_t k, const ui
     s->gemm_ms = s->fused_ms = s->gemm_flops = s->fused_flops = 0.0;
     MTRY(gemm<EPI_F32>(s, m, n, k, A, k, 1, B, n, 1, C, n, 1, nullptr, nullptr));
     return TLED_OK;
+}
+
+tled_status tled_mlp_ensemble_stats(int64_t n, int32_t members, int32_t n_out, const float *outs,
+                                    const float *scale, float *mean, float *spread, void *hip_stream) {
+    if (n < 0 || members < 1 || n_out < 1 || n_out > 64 || (n > 0 && (!outs || !scale || !mean || !spread)))
+        return TLED_E_ARG;
+    if (n == 0) return TLED_OK;
+    hipLaunchKernelGGL(ensemble_stats_kernel, dim3(blocks(n)), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(hip_stream), long(n), int(members), int(n_out), outs, scale, mean,
+                       spread);
+    return hipGetLastError() == hipSuccess ? TLED_OK : TLED_E_HIP;
 }
 
 tled_status tled_mlp_set_timing(tled_mlp *s, int on) {

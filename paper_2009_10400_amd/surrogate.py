@@ -46,6 +46,7 @@ _SIGS = {
     "tled_mlp_train_step": ([_P, ctypes.c_int64, _P, _P, _P, _f, _fp], ctypes.c_int),
     "tled_mlp_gradient": ([_P, ctypes.c_int64, _P, _P, _P, _fp, _fp], ctypes.c_int),
     "tled_mlp_gemm": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_ensemble_stats": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P], ctypes.c_int),
     "tled_mlp_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "tled_mlp_last_timing": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                              ctypes.c_int),
@@ -161,10 +162,13 @@ class MLP:
         if x.device.index != self.device:
             raise ValueError(f"tensors are on {x.device}, the network on device {self.device}")
 
-    def forward(self, x, p):
+    def forward(self, x, p, out=None):
         import torch
         self._inputs(x, p)
-        out = torch.empty((x.shape[0], self.cfg["n_out"]), dtype=torch.float32, device=x.device)
+        if out is None:
+            out = torch.empty((x.shape[0], self.cfg["n_out"]), dtype=torch.float32, device=x.device)
+        else:
+            _need(out, x.shape[0], self.cfg["n_out"], torch.float32, "out")
         self._call(_lib.tled_mlp_forward, x.shape[0], _dp(x), _dp(p), _dp(out))
         return out
 
@@ -332,27 +336,39 @@ class Ensemble:
         return hist, time.perf_counter() - t0
 
     def _forward_all(self, x, p):
+        """Member outputs into one K x n x 4 device array, then the library's ensemble
+        statistics kernel: (mean of the scaled targets n x 4, spread of target 0, n)."""
         import torch
         dev = torch.device("cuda", self.device)
         X = torch.from_numpy(x).to(dev)
         Pm = torch.from_numpy(p).to(dev)
+        n, K = X.shape[0], len(self.models)
+        outs = torch.empty((K, n, 4), dtype=torch.float32, device=dev)
+        mean = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        spread = torch.empty(n, dtype=torch.float32, device=dev)
+        scale = torch.from_numpy(self.y_std).to(dev)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        ys = torch.stack([m.forward(X, Pm) for m in self.models])      # K x n x 4
+        for k, m in enumerate(self.models):
+            m.forward(X, Pm, out=outs[k])
+        st = _lib.tled_mlp_ensemble_stats(n, K, 4, _dp(outs), _dp(scale), _dp(mean), _dp(spread),
+                                          _P(torch.cuda.current_stream(dev).cuda_stream))
+        if st != 0:
+            raise TledError(st, "tled_mlp_ensemble_stats failed")
         torch.cuda.synchronize(dev)
         self.last_forward_s = time.perf_counter() - t0
-        return (ys * torch.from_numpy(self.y_std).to(dev)).cpu().numpy()
+        return mean.cpu().numpy(), spread.cpu().numpy()
 
     def predict_many(self, items):
         """items [(Problem, duration)] -> [(T mean, u mean, T spread)], one forward call per member."""
         xs, ps = zip(*(scenario_inputs(p, d, self.t_ref) for p, d in items))
-        ys = self._forward_all(np.concatenate(xs), np.concatenate(ps))
+        ym, ys = self._forward_all(np.concatenate(xs), np.concatenate(ps))
         out, o = [], 0
         for (p, d), x in zip(items, xs):
-            y = ys[:, o:o + len(x)]
+            sl = slice(o, o + len(x))
             o += len(x)
-            T, u = unscale(p, d, y)
-            out.append((T.mean(0), u.mean(0), T.max(0) - T.min(0)))
+            T, u = unscale(p, d, ym[sl])
+            out.append((T, u, temperature_scale(p, d) * ys[sl]))
         return out
 
     def calibrate(self, items, fields):

@@ -184,3 +184,27 @@ def test_argument_errors(torch_dev):
                      torch.zeros((4, 3), device=torch_dev), 1e-3)
     with pytest.raises(ValueError):
         m.forward(torch.zeros((4, 3)), torch.zeros((4, 2)))
+
+
+def test_ensemble_statistics_kernel(torch_dev):
+    """Mean over members (scaled) and the member spread of output 0, against numpy."""
+    import ctypes
+    import torch
+    from paper_2009_10400_amd import surrogate as S
+    rng = np.random.default_rng(31)
+    K, n, no = 4, 1003, 4
+    outs = rng.standard_normal((K, n, no)).astype(np.float32)
+    scale = np.array([2.5, 0.5, 1.0, 3.0], np.float32)
+    d_outs = torch.from_numpy(outs).to(torch_dev)
+    d_scale = torch.from_numpy(scale).to(torch_dev)
+    mean = torch.empty((n, no), dtype=torch.float32, device=torch_dev)
+    spread = torch.empty(n, dtype=torch.float32, device=torch_dev)
+    st = S._lib.tled_mlp_ensemble_stats(n, K, no, S._dp(d_outs), S._dp(d_scale), S._dp(mean), S._dp(spread),
+                                        ctypes.c_void_p(torch.cuda.current_stream(torch_dev).cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(mean.cpu().numpy(), scale * outs.astype(np.float64).mean(0), rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(spread.cpu().numpy(), scale[0] * (outs[..., 0].max(0) - outs[..., 0].min(0)),
+                               rtol=1e-6)
+    assert S._lib.tled_mlp_ensemble_stats(n, 0, no, S._dp(d_outs), S._dp(d_scale), S._dp(mean), S._dp(spread),
+                                          None) != 0
