@@ -218,14 +218,27 @@ def temperature_scale(problem, duration: float) -> float:
     return problem.meta["power"] * duration / (m["rho"] * m["c"] * problem.h ** 2 * R_REF)
 
 
-def scenario_inputs(problem, duration: float, t_ref: float):
+def _scenario_params(problem, duration: float, t_ref: float):
     probe = np.asarray(problem.meta["probe"])
-    x = (problem.X - probe) / (XI_SCALE * problem.h)
     prm = np.array([*(probe / 0.05), problem.meta["power"] / 50.0, duration / t_ref,
                     problem.meta["E"] / 4000.0, problem.h / 2e-3,
                     1.0 if problem.meta["kind"] == "ellipsoid" else 0.0])
-    p = np.concatenate([problem.X / 0.05, np.tile(prm, (problem.nn, 1))], axis=1)
-    return x.astype(np.float32), p.astype(np.float32)
+    return probe, prm
+
+
+def fill_inputs(problem, duration: float, t_ref: float, x_out, p_out):
+    """Write one scenario's network inputs into preallocated float32 rows (nn x 3, nn x N_PARAM)."""
+    probe, prm = _scenario_params(problem, duration, t_ref)
+    np.multiply(problem.X - probe, 1.0 / (XI_SCALE * problem.h), out=x_out, casting="same_kind")
+    np.multiply(problem.X, 1.0 / 0.05, out=p_out[:, :3], casting="same_kind")
+    p_out[:, 3:] = prm
+
+
+def scenario_inputs(problem, duration: float, t_ref: float):
+    x = np.empty((problem.nn, 3), np.float32)
+    p = np.empty((problem.nn, N_PARAM), np.float32)
+    fill_inputs(problem, duration, t_ref, x, p)
+    return x, p
 
 
 def scaled_targets(problem, duration: float, u, T):
@@ -361,12 +374,18 @@ class Ensemble:
 
     def predict_many(self, items):
         """items [(Problem, duration)] -> [(T mean, u mean, T spread)], one forward call per member."""
-        xs, ps = zip(*(scenario_inputs(p, d, self.t_ref) for p, d in items))
-        ym, ys = self._forward_all(np.concatenate(xs), np.concatenate(ps))
+        sizes = [p.nn for p, _ in items]
+        X = np.empty((sum(sizes), 3), np.float32)
+        P = np.empty((sum(sizes), N_PARAM), np.float32)
+        o = 0
+        for (p, d), m in zip(items, sizes):
+            fill_inputs(p, d, self.t_ref, X[o:o + m], P[o:o + m])
+            o += m
+        ym, ys = self._forward_all(X, P)
         out, o = [], 0
-        for (p, d), x in zip(items, xs):
-            sl = slice(o, o + len(x))
-            o += len(x)
+        for (p, d), m in zip(items, sizes):
+            sl = slice(o, o + m)
+            o += m
             T, u = unscale(p, d, ym[sl])
             out.append((T, u, temperature_scale(p, d) * ys[sl]))
         return out
