@@ -119,3 +119,37 @@ def test_batch_fields_independent_of_host_threads_and_duration_api(monkeypatch):
     b.run()
     for (u1, T1), (u, T) in zip(f1, b.read_all()):
         assert np.array_equal(u1, u) and np.array_equal(T1, T)
+
+
+def test_h8_batch_equals_single_runs_bitwise():
+    """H8 scenarios of different sizes and materials in one batch: each equal bit for bit to its own
+    run with the same patch size, and held after its step count."""
+    from paper_2009_10400_amd import tled
+    probs = [W.cube_h8(n=n, L=0.02 * n / 6, power=p) for n, p in ((6, 2.0), (9, 5.0), (7, 3.0))]
+    probs[1].params = dict(probs[1].params, mu=1500.0, eta=3000.0)
+    steps = [120, 200, 60]
+    b = tled.Batch(0)
+    b.set_options(graph_steps=40)
+    for p, n in zip(probs, steps):
+        b.add(p, cfl=0.8, t_end=1e9, patch_elems=128)
+    b.finalize()
+    dts = [b.scenario_steps(k)[0] for k in range(len(probs))]
+    # explicit step counts: rebuild with the chosen dt
+    b.close()
+    b = tled.Batch(0)
+    b.set_options(graph_steps=40)
+    for p, dt, n in zip(probs, dts, steps):
+        b.add(p, dt, n, patch_elems=128)
+    b.finalize()
+    b.run()
+    fields = b.read_all()
+    for k, (p, dt, n) in enumerate(zip(probs, dts, steps)):
+        s = tled.from_problem(p, dt=dt, device=0, kernel_variant=2, graph_steps=40, patch_elems=128)
+        s.step(n)
+        assert np.array_equal(fields[k][0], s.read_u()), k
+        assert np.array_equal(fields[k][1], s.read_T()), k
+        assert fields[k][1].max() > p.params["T0"]
+        s.close()
+    b.step(30)
+    for (u0, T0), (u1, T1) in zip(fields, b.read_all()):
+        assert np.array_equal(u0, u1) and np.array_equal(T0, T1)
