@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--patch-elems", type=int, default=0, help="elements per patch (0: library default)")
     ap.add_argument("--block-size", type=int, default=0, help="patch kernel threads per workgroup (0: default)")
+    ap.add_argument("--reorder", type=int, default=0,
+                    help="element order: 0/1 Morton with bisection patches, 2 Morton runs, -1 as generated")
     ap.add_argument("--elems", type=int, default=1_000_000)
     ap.add_argument("--workload", default="ellipsoid_t4", choices=["ellipsoid_t4", "cube_h8"],
                     help="ellipsoid_t4: ~1.0M-tet noisy ellipsoid (default); cube_h8: 64^3 H8 cube")
@@ -406,7 +408,7 @@ def main():
     stream = torch.cuda.Stream(device=0)
     sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, kernel_variant=args.variant,
                             graph_steps=args.graph_steps, patch_elems=args.patch_elems,
-                            block_size=args.block_size)
+                            block_size=args.block_size, reorder=args.reorder)
     info = sim.info()
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
     sim.step(args.warmup)
@@ -463,7 +465,11 @@ def main():
                                 f"0.1 m cube, {p.ne} H8 (64^3, one-point + hourglass) / {p.nn} nodes, "
                                 f"fibre field, mu(T), 1/r^2 point source (10 W)"),
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
-                   "graph_steps": args.graph_steps, "patches": info["n_patches"], "dt": sim.dt},
+                   "graph_steps": args.graph_steps, "patches": info["n_patches"],
+                   "shared_nodes": info["n_shared_nodes"], "patch_lds_bytes": info["patch_lds_bytes"],
+                   "patch_wgs_per_cu": info["patch_wgs_per_cu"],
+                   "patch_order": {-1: "as generated", 2: "Morton runs"}.get(args.reorder, "coordinate bisection"),
+                   "dt": sim.dt},
         "roofline": roof,
         "step_hbm": step_hbm,
     }

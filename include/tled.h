@@ -102,10 +102,16 @@ typedef struct {
                                  geometry; 2: fused patch kernels rebuilding the geometry from
                                  patch-local coordinates; 3: fused patch kernels reading the
                                  precomputed geometry                                          */
-    int32_t reorder;          /* 0: auto (on), 1: on, -1: keep the caller's order             */
+    int32_t reorder;          /* 0: auto (= 1); 1: elements along a Morton curve of their
+                                 centroids, and for the fused variants patches cut by recursive
+                                 coordinate bisection; 2: Morton order, patches are runs of it;
+                                 -1: keep the caller's order (patches are runs of it)          */
     int32_t block_size;       /* threads per workgroup of the fused patch kernel: 0 (256),
                                  256, or 512 (single T4 problems only)                        */
-    int32_t patch_elems;      /* elements per patch for the fused variant (0: default)        */
+    int32_t patch_elems;      /* elements per patch for the fused variant.  0: H8 256; T4 at
+                                 most 504 (1008 with block_size 512), sized so the patch count
+                                 just fills whole rounds of the 1024 (512) workgroups that are
+                                 resident at once on 256 CUs, at least 128                     */
     double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */
 } tled_options;
 
@@ -261,7 +267,10 @@ tled_status tled_batch_create(tled_batch **out, int device);
 void        tled_batch_destroy(tled_batch *b);
 /* Add one scenario (arguments as in the single-problem set-up calls; arrays are
  * copied).  n_fixed nodes fixed_nodes[i] with component mask fixed_mask[i];
- * patch_elems 0 = default.  *index receives the scenario number. */
+ * patch_elems 0 = default (T4 448, H8 256; the single-problem rule for whole
+ * rounds of resident workgroups does not apply to a batch's union of patches).
+ * A scenario's results are bitwise those of the same problem run alone with the
+ * same patch_elems.  *index receives the scenario number. */
 tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const double *X, int64_t n_elems,
                            const int32_t *conn, const tled_material *m, const double *a0, const double *q_elem,
                            double t_on, double t_off, int64_t n_fixed, const int32_t *fixed_nodes,

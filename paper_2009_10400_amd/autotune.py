@@ -15,7 +15,7 @@ import time
 import numpy as np
 
 BUCKETS = ((0, 15_000), (15_000, 50_000), (50_000, 10**9))
-CANDIDATES = (256, 320, 384, 448)
+CANDIDATES = (192, 256, 320, 384, 448, 504)
 
 
 def bucket_of(n_elems: int) -> int:

@@ -76,6 +76,25 @@ struct tled_sim {
 
 namespace {
 
+// Default elements per patch of a single problem.  H8: 256 (on a regular grid,
+// 8x8x4-cell boxes).  T4: the patch kernel is fastest with patches as large as
+// the LDS of four resident 256-thread workgroups per CU allows (about 500
+// elements with bisection patches), but only 256 CUs x 4 = 1024 patches run at
+// once, and a patch count just above a multiple of 1024 leaves a last round
+// that keeps few CUs busy (measured on the 1M-tet ellipsoid: 2087 patches of
+// 480 elements 31.9 us, 2019 patches of 496 elements 29.4 us).  So the count
+// of rounds is the smallest one whose patches fit, and the patches are the
+// smallest (a multiple of 8) that fill those rounds.  512-thread workgroups:
+// two per CU, patches up to 1008 elements.
+int default_patch_elems(int npe, int64_t ne, int block_size) {
+    if (npe != 4) return 256;
+    const int64_t slots = 256 * (block_size == 512 ? 2 : 4), pe_max = block_size == 512 ? 1008 : 504;
+    for (int64_t k = 1;; ++k) {
+        const int64_t pe = ((ne + k * slots - 1) / (k * slots) + 7) / 8 * 8;
+        if (pe <= pe_max) return int(std::max<int64_t>(pe, 128));
+    }
+}
+
 tled_status fail(tled_sim *s, tled_status st, const std::string &msg) {
     if (s) s->err = msg;
     return st;
@@ -571,6 +590,7 @@ tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
     if (!sim || !opt) return TLED_E_ARG;
     if (opt->kernel_variant < 0 || opt->kernel_variant > 3) return fail(sim, TLED_E_ARG, "kernel_variant must be 0..3");
     if (opt->patch_elems < 0 || opt->patch_elems > 4096) return fail(sim, TLED_E_ARG, "patch_elems out of range");
+    if (opt->reorder < -1 || opt->reorder > 2) return fail(sim, TLED_E_ARG, "reorder must be -1..2");
     if (opt->block_size != 0 && opt->block_size != 256 && opt->block_size != 512)
         return fail(sim, TLED_E_UNSUPPORTED, "block_size must be 256 or 512");
     if (sim->finalized && (opt->kernel_variant != sim->opt.kernel_variant || opt->reorder != sim->opt.reorder ||
@@ -701,10 +721,11 @@ tled_status tled_finalize(tled_sim *sim) {
     int v = sim->opt.kernel_variant == 0 ? 2 : sim->opt.kernel_variant;
     SetupOptions so;
     so.reorder = sim->opt.reorder >= 0;
+    so.bisect = sim->opt.reorder != 2;
     so.build_patches = (v >= 2);
-    // Default patch sizes: 448 T4 elements (3 workgroups of 256 threads per CU fit the LDS, and
-    // the ~1M-tet mesh then fills the machine in just under three rounds), 256 H8 elements.
-    so.patch_elems = sim->opt.patch_elems > 0 ? sim->opt.patch_elems : (sim->prob.npe == 4 ? 448 : 256);
+    so.patch_elems = sim->opt.patch_elems > 0
+                         ? sim->opt.patch_elems
+                         : default_patch_elems(sim->prob.npe, sim->prob.ne, sim->opt.block_size);
     if (sim->opt.block_size == 512 && sim->prob.npe == 8)
         return fail(sim, TLED_E_UNSUPPORTED, "block_size 512 is for T4 meshes only");
     tled_status st = precompute(sim->prob, so, &sim->pc, &sim->err);
@@ -1099,7 +1120,7 @@ tled_status tled_batch_finalize(tled_batch *b) {
     for (size_t k = 0; k < pe.size(); ++k)
         pe[k] = b->scen_pe[k] > 0 ? b->scen_pe[k]
                                   : (b->opt.patch_elems > 0 ? b->opt.patch_elems : (b->scen[k].npe == 4 ? 448 : 256));
-    tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, &b->pc, &b->ranges, &b->patch_scen,
+    tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, b->opt.reorder != 2, &b->pc, &b->ranges, &b->patch_scen,
                                       &b->shared_scen, &b->err);
     if (st != TLED_OK) return st;
     for (size_t k = 0; k < b->scen.size(); ++k) {

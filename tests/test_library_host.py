@@ -60,6 +60,35 @@ def host_sim(problem, dt=None, **opts):
     return tled.from_problem(problem, dt=dt if dt is not None else 1e-5, device=-1, **opts)
 
 
+def default_patch_elems(npe, ne):
+    """The documented default: H8 256; T4 the smallest multiple of 8 (at least 128) that
+    fills the fewest whole rounds of 1024 resident workgroups with patches of at most 504."""
+    if npe == 8:
+        return 256
+    k = 1
+    while True:
+        pe = -(-(-(-ne // (1024 * k))) // 8) * 8
+        if pe <= 504:
+            return max(pe, 128)
+        k += 1
+
+
+def test_default_patch_size_fills_whole_rounds():
+    assert default_patch_elems(4, 6000) == 128
+    assert default_patch_elems(4, 1_001_328) == 496          # 2019 patches: two rounds of 1024
+    assert default_patch_elems(4, 2_002_566) == 496          # 4038 patches: four rounds
+    assert default_patch_elems(4, 1024 * 504 + 1) == 256     # one element too many for one round
+    for n in (30000, 500_000):
+        p = W.ellipsoid_t4(n)
+        info = host_sim(p).info()
+        pe = default_patch_elems(4, p.ne)
+        assert info["n_patches"] == -(-p.ne // pe)
+        rounds = -(-info["n_patches"] // 1024)
+        if pe > 128:      # the next smaller size would need another round
+            assert -(-p.ne // (pe - 8)) > rounds * 1024
+        assert info["n_patches"] <= rounds * 1024
+
+
 @pytest.mark.parametrize("name", ["cube_t4", "cube_h8", "ellipsoid"])
 @pytest.mark.parametrize("variant", [1, 2, 3])
 def test_host_precompute_matches_oracle(name, variant):
@@ -77,7 +106,7 @@ def test_host_precompute_matches_oracle(name, variant):
     assert info["kernel_variant"] == variant
     assert info["n_nodes"] == p.nn and info["n_elems"] == p.ne
     if variant >= 2:
-        assert info["n_patches"] == -(-p.ne // (448 if p.npe == 4 else 256))
+        assert info["n_patches"] == -(-p.ne // default_patch_elems(p.npe, p.ne))
         assert 0 < info["n_shared_nodes"] < p.nn
 
 
@@ -264,3 +293,29 @@ def test_thermal_stability_bound():
     with pytest.raises(tled.TledError) as e:
         s.finalize()
     assert e.value.status == tled.E_ARG and "thermal" in str(e.value)
+
+
+def test_bisection_patches_on_a_regular_grid():
+    # 16^3 hexahedra in patches of 256: every cut is a grid plane, so the patches
+    # are 4x8x8 boxes (in some orientation) and the shared nodes are those on the
+    # internal planes -- three planes across one axis, one across each other:
+    # 17^3 - (17 - 3)(17 - 1)(17 - 1)
+    p = W.cube_h8(n=16)
+    for r in (0, 1, 2):
+        info = host_sim(p, reorder=r).info()
+        assert info["n_patches"] == 16
+        assert info["n_shared_nodes"] == 17 ** 3 - 14 * 16 * 16
+
+
+def test_bisection_patches_beat_morton_runs_on_tetrahedra():
+    from paper_2009_10400_amd import tled
+    p = W.ellipsoid_t4(100_000)
+    bis, runs = host_sim(p, reorder=1, patch_elems=448).info(), host_sim(p, reorder=2, patch_elems=448).info()
+    assert bis["n_patches"] == runs["n_patches"]
+    assert bis["n_shared_nodes"] < 0.95 * runs["n_shared_nodes"]
+    assert bis["patch_max_nodes"] < runs["patch_max_nodes"]
+    assert bis["patch_lds_bytes"] < runs["patch_lds_bytes"]
+    assert host_sim(p, patch_elems=448).info() == bis     # the default order, and deterministic
+    with pytest.raises(tled.TledError) as e:
+        host_sim(W.cube_t4(n=2, L=0.01), reorder=3)
+    assert e.value.status == tled.E_ARG
