@@ -139,6 +139,8 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
            "write_scale": write_scale,
            "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
            "algorithmic_bytes_per_launch": alg, "dispatches": nd,
+           "layout": {"kernel_variant": info["kernel_variant"], "n_patches": info["n_patches"],
+                      "n_shared_nodes": info["n_shared_nodes"]},
            "shared_node_kernel_kib": [sf, sw],
            "note": f"scales from a plain {copy_mib} MiB device copy (FETCH_SIZE read {cf[1][0]:.1f} KiB, "
                    f"WRITE_SIZE {cw[1][0]:.1f} KiB)"}
@@ -148,8 +150,9 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
     print(json.dumps(out), flush=True)
 
 
-def traffic_record(workload: str):
-    """The committed rocprofv3 counter summary of the solver kernels, if it is current."""
+def traffic_record(workload: str, info=None):
+    """The committed rocprofv3 counter summary of the solver kernels, if it is current: same
+    solver sources, and (given the run's ``info``) the same patch layout as the counted run."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -157,14 +160,20 @@ def traffic_record(workload: str):
         with open(path) as f:
             d = json.load(f)
         from paper_2009_10400_amd.build import source_digest
-        return d if d.get("source_digest") == source_digest() else None
+        if d.get("source_digest") != source_digest():
+            return None
+        if info is not None:
+            lay = d.get("layout", {})
+            if any(lay.get(k) != info[k] for k in ("kernel_variant", "n_patches", "n_shared_nodes")):
+                return None
+        return d
     except Exception:  # noqa: BLE001
         return None
 
 
-def traffic_from_profiles(kernel_name: str, workload: str):
+def traffic_from_profiles(kernel_name: str, workload: str, info=None):
     """HBM bytes per launch of the dominant kernel from the counter summary, if it is current."""
-    d = traffic_record(workload)
+    d = traffic_record(workload, info)
     if d is None or d.get("kernel") != kernel_name:
         return None
     return float(d["bytes_per_launch"])
@@ -435,7 +444,7 @@ def main():
     else:
         alg_bytes = eb * p.ne + 16.0 * p.npe * p.ne   # plus the nodal outputs it writes
     achieved = alg_bytes / (kt["element_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profiles(kname, p.name)
+    traffic = traffic_from_profiles(kname, p.name, info)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "kernel_ms": kt["element_ms"], "second_kernel_ms": kt["node_ms"],
@@ -443,7 +452,7 @@ def main():
     log(f"[bench] kernel times {kt}")
     # the whole step's HBM traffic (both kernels, counted) against peak and against a plain copy
     step_hbm = None
-    rec = traffic_record(p.name) if info["kernel_variant"] >= 2 else None
+    rec = traffic_record(p.name, info) if info["kernel_variant"] >= 2 else None
     if rec is not None:
         sf, sw = rec["shared_node_kernel_kib"]
         step_bytes = rec["bytes_per_launch"] + 1024.0 * (sf * rec["fetch_scale"] + sw * rec["write_scale"])
