@@ -109,7 +109,7 @@ typedef struct {
     int32_t block_size;       /* threads per workgroup of the fused patch kernel: 0 (256),
                                  256, or 512 (single T4 problems only)                        */
     int32_t patch_elems;      /* elements per patch for the fused variant.  0: H8 256; T4 at
-                                 most 504 (1008 with block_size 512), sized so the patch count
+                                 most 504 (704 with block_size 512), sized so the patch count
                                  just fills whole rounds of the 1024 (512) workgroups that are
                                  resident at once on 256 CUs, at least 128                     */
     double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */

@@ -85,10 +85,10 @@ namespace {
 // 480 elements 31.9 us, 2019 patches of 496 elements 29.4 us).  So the count
 // of rounds is the smallest one whose patches fit, and the patches are the
 // smallest (a multiple of 8) that fill those rounds.  512-thread workgroups:
-// two per CU, patches up to 1008 elements.
+// two per CU, patches up to 704 elements (the 64 KB LDS of one workgroup).
 int default_patch_elems(int npe, int64_t ne, int block_size) {
     if (npe != 4) return 256;
-    const int64_t slots = 256 * (block_size == 512 ? 2 : 4), pe_max = block_size == 512 ? 1008 : 504;
+    const int64_t slots = 256 * (block_size == 512 ? 2 : 4), pe_max = block_size == 512 ? 704 : 504;
     for (int64_t k = 1;; ++k) {
         const int64_t pe = ((ne + k * slots - 1) / (k * slots) + 7) / 8 * 8;
         if (pe <= pe_max) return int(std::max<int64_t>(pe, 128));

@@ -87,6 +87,12 @@ def test_default_patch_size_fills_whole_rounds():
         if pe > 128:      # the next smaller size would need another round
             assert -(-p.ne // (pe - 8)) > rounds * 1024
         assert info["n_patches"] <= rounds * 1024
+    # 512-thread workgroups: two per CU, patches of at most 704 elements (one workgroup's LDS)
+    p = W.ellipsoid_t4(500_000)
+    info = host_sim(p, block_size=512).info()
+    pe = -(-(-(-p.ne // 1024)) // 8) * 8      # one round of 512 would need 984: two rounds
+    assert pe <= 704 and info["n_patches"] == -(-p.ne // pe)
+    assert info["patch_lds_bytes"] <= 65536 - 1024
 
 
 @pytest.mark.parametrize("name", ["cube_t4", "cube_h8", "ellipsoid"])
