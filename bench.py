@@ -107,6 +107,19 @@ def _counter_means(db_path: str, counter: str):
     return {k: (v, n) for k, v, n in rows}
 
 
+def workload_key(name: str, elems: int) -> str:
+    """Name of a measured workload: the T4 ellipsoid at other than 1M elements carries its size."""
+    return name if name != "ellipsoid_t4" or elems == 1_000_000 else f"{name}_{elems}"
+
+
+def problem_for_key(key: str):
+    from paper_2009_10400_amd import workloads as W
+    if key == "cube_h8":
+        return W.cube_h8(64)
+    size = key[len("ellipsoid_t4_"):] if key.startswith("ellipsoid_t4_") else "1000000"
+    return W.ellipsoid_t4(int(size))
+
+
 def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db, copy_mib):
     """HBM traffic of the dominant kernel per launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
     each scaled by what the counter reads for a plain device copy of known size."""
@@ -129,7 +142,7 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
     wk, _ = pick(w, "patch_kernel")
     sf, _ = pick(f, "shared_node_kernel")
     sw, _ = pick(w, "shared_node_kernel")
-    p = W.ellipsoid_t4(1_000_000) if workload == "ellipsoid_t4" else W.cube_h8(64)
+    p = problem_for_key(workload)
     h = tled.from_problem(p, device=-1)
     info = h.info()
     h.close()
@@ -209,6 +222,56 @@ def cpu_baseline(problem, dt, steps):
     el = time.perf_counter() - t0
     return {"value": problem.ne * steps / el, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the full {problem.ne}-tet workload, serial FP64 oracle ({el:.1f} s)"}
+
+
+def host_threads() -> int:
+    """Host cores this process may use (its affinity), capped by OMP_NUM_THREADS when set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(cap))) if cap.isdigit() and int(cap) > 0 else n
+
+
+def cpu_baseline_all_cores(problem, dt, steps, threads):
+    """The same serial oracle on every host core at once: `threads` independent copies of the
+    workload, each advanced `steps` steps by its own thread (the oracle's C calls release the
+    GIL).  Throughput of the whole host, with the oracle's arithmetic unchanged."""
+    import threading
+    import oracle
+    oracle.build()
+    sims, states = [None] * threads, [None] * threads
+
+    def make(i):
+        o = oracle.OracleSim(problem.npe, problem.X, problem.conn, problem.params, a0=problem.a0, q=problem.q,
+                             fix=problem.fix, t_on=problem.t_on, t_off=problem.t_off, dt=dt, gamma=problem.gamma)
+        st = o.initial_state(problem.params["T0"])
+        o.run(st, 1)
+        sims[i], states[i] = o, st
+
+    ths = [threading.Thread(target=make, args=(i,)) for i in range(threads)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    if any(o is None for o in sims):
+        raise RuntimeError("oracle set-up failed")
+    go = threading.Barrier(threads + 1)
+
+    def work(i):
+        go.wait()
+        sims[i].run(states[i], steps)
+
+    ths = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in ths:
+        t.start()
+    go.wait()
+    t0 = time.perf_counter()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    return {"value": threads * problem.ne * steps / el, "unit": "element-updates/s", "cores": threads,
+            "kind": "oracle, one independent copy per core",
+            "sample": f"{threads} copies x {steps} steps of the full {problem.ne}-tet workload, serial FP64 "
+                      f"oracle per thread ({el:.1f} s)"}
 
 
 def sweep(args):
@@ -444,7 +507,8 @@ def main():
     else:
         alg_bytes = eb * p.ne + 16.0 * p.npe * p.ne   # plus the nodal outputs it writes
     achieved = alg_bytes / (kt["element_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profiles(kname, p.name, info)
+    key = workload_key(p.name, args.elems)
+    traffic = traffic_from_profiles(kname, key, info)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
             "kernel_ms": kt["element_ms"], "second_kernel_ms": kt["node_ms"],
@@ -452,7 +516,7 @@ def main():
     log(f"[bench] kernel times {kt}")
     # the whole step's HBM traffic (both kernels, counted) against peak and against a plain copy
     step_hbm = None
-    rec = traffic_record(p.name, info) if info["kernel_variant"] >= 2 else None
+    rec = traffic_record(key, info) if info["kernel_variant"] >= 2 else None
     if rec is not None:
         sf, sw = rec["shared_node_kernel_kib"]
         step_bytes = rec["bytes_per_launch"] + 1024.0 * (sf * rec["fetch_scale"] + sw * rec["write_scale"])
@@ -486,6 +550,10 @@ def main():
         steps = args.cpu_steps or max(3, int(40e6 / p.ne))
         log(f"[bench] CPU baseline: oracle {steps} steps")
         out["cpu_baseline"] = cpu_baseline(p, sim.dt, steps)
+        nt = host_threads()
+        if nt > 1:
+            log(f"[bench] CPU baseline on {nt} host cores")
+            out["cpu_all_cores"] = cpu_baseline_all_cores(p, sim.dt, max(3, steps // 2), nt)
     print(json.dumps(out), flush=True)
 
 
