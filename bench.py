@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--variant", type=int, default=2)
-    ap.add_argument("--graph-steps", type=int, default=50)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="steps per hipGraph chunk (0: library default, 50 for a problem, eager steps for a batch)")
     ap.add_argument("--patch-elems", type=int, default=0, help="elements per patch (0: library default)")
     ap.add_argument("--block-size", type=int, default=0, help="patch kernel threads per workgroup (0: default)")
     ap.add_argument("--reorder", type=int, default=0,
@@ -316,7 +317,8 @@ def sweep(args):
                                f"(log-uniform, {ne_tot} total), probe 1/r^2 source U(20,80) W, E U(2,6) kPa, "
                                f"heating U(30,300) s x {args.duration_scale:g}",
                    "duration_scale": args.duration_scale, "autotune": {str(k): v for k, v in choice.items()},
-                   "graph_steps": args.graph_steps},
+                   "launch": (f"hipGraph chunks of {args.graph_steps}" if args.graph_steps > 0 else
+                              "eager steps, each launching only the scenarios still running")},
         "autotune_report": {str(k): v for k, v in report.items()},
         "ablated_volume_m3": {"min": float(vol.min()), "max": float(vol.max())},
         "T_max_K": {"min": float(tmax.min()), "max": float(tmax.max())},
@@ -538,7 +540,7 @@ def main():
                                 f"0.1 m cube, {p.ne} H8 (64^3, one-point + hourglass) / {p.nn} nodes, "
                                 f"fibre field, mu(T), 1/r^2 point source (10 W)"),
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
-                   "graph_steps": args.graph_steps, "patches": info["n_patches"],
+                   "graph_steps": args.graph_steps or 50, "patches": info["n_patches"],
                    "shared_nodes": info["n_shared_nodes"], "patch_lds_bytes": info["patch_lds_bytes"],
                    "patch_wgs_per_cu": info["patch_wgs_per_cu"],
                    "patch_order": {-1: "as generated", 2: "Morton runs"}.get(args.reorder, "coordinate bisection"),

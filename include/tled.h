@@ -97,7 +97,11 @@ typedef struct {
 typedef struct {
     int32_t graph_steps;      /* steps per chunk: a chunk is one hipGraph replay (default 50;
                                  < 0: eager launches in chunks of 100).  Monitors are reduced
-                                 at the last step of every chunk and of every tled_step call. */
+                                 at the last step of every chunk and of every tled_step call.
+                                 Batches default to eager steps, each of which launches only
+                                 the scenarios still running; a batch's graph launches those
+                                 running at its first step and is captured again when that
+                                 set has changed.                                             */
     int32_t kernel_variant;   /* 0: default (2); 1: two-pass element/node kernels with precomputed
                                  geometry; 2: fused patch kernels rebuilding the geometry from
                                  patch-local coordinates; 3: fused patch kernels reading the

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
+#include <numeric>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -55,6 +57,8 @@ struct tled_sim {
     int *d_new2old = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_k = 0;
+    int graph_np = -1;          // batch: launched patches and shared nodes baked into the graph
+    int64_t graph_ns = -1;
     int64_t step = 0;
     std::vector<float> B;   // per-node velocity coefficient (kept for state writes)
     size_t theta_floats = 0;
@@ -72,6 +76,10 @@ struct tled_sim {
     NodeParams *d_np = nullptr;
     long long *d_ranges = nullptr;
     double *d_scen_mon = nullptr;
+    // batch: union positions (scenarios by descending end step): end step, and
+    // the patch and shared-node counts of the prefix ending at the position
+    std::vector<int64_t> pos_end, pos_shared_hi;
+    std::vector<int32_t> pos_patch_hi;
 };
 
 namespace {
@@ -425,24 +433,52 @@ void single_scenario(tled_sim *s) {
     s->shared_scen.assign(std::max<int64_t>(s->pc.nn - nint, 1), 0);
 }
 
-// Enqueue a chunk of k steps (eager, or under stream capture).
+// Patches and shared nodes to launch at step `step`.  In a batch, the scenarios
+// still running form a prefix of the union (descending end steps), so a step
+// launches that prefix only (at least one workgroup each, so that every launch
+// exists); a single problem launches everything.
+void active_counts(const tled_sim *s, int64_t step, int *n_patches, int64_t *n_shared) {
+    *n_patches = s->pa.n_patches;
+    *n_shared = s->pa.n_shared;
+    if (!s->is_batch || s->pos_end.empty()) return;
+    const auto it = std::partition_point(s->pos_end.begin(), s->pos_end.end(), [&](int64_t e) { return e > step; });
+    const size_t m = size_t(it - s->pos_end.begin());
+    *n_patches = std::max(1, m ? s->pos_patch_hi[m - 1] : 0);
+    *n_shared = std::max<int64_t>(1, m ? s->pos_shared_hi[m - 1] : 0);
+}
+
+// Enqueue a chunk of k steps (eager, or under stream capture) starting at step
+// step0.  Batch: a step that reduces no monitors launches the prefix of
+// scenarios still running at that step (eager) or at step0 (under capture: the
+// prefix at the chunk's first step, which covers every later step of the
+// chunk; scenarios ending inside the chunk exit in the kernels); the last step
+// launches everything, so that every monitor partial is rewritten.
 // With ev (4 events per step + 2): the element/patch and node/shared-node
 // launches of step j carry the pairs (4j, 4j+1) and (4j+2, 4j+3), taken by the
 // dispatches themselves; the finish kernel is bracketed by the last two.
-tled_status enqueue_chunk(tled_sim *s, int k, double *ms = nullptr, std::vector<hipEvent_t> *ev = nullptr) {
+tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, double *ms = nullptr,
+                          std::vector<hipEvent_t> *ev = nullptr) {
     const int npe = s->pc.npe;
     const int bs = s->opt.block_size > 0 ? s->opt.block_size : kBlock;
     for (int j = 0; j < k; ++j) {
         const bool mon = (j == k - 1);
+        PatchArgs pa = s->pa;
+        if (s->is_batch && !mon) {
+            int np;
+            int64_t ns;
+            active_counts(s, captured ? step0 : step0 + j, &np, &ns);
+            pa.n_patches = np;
+            pa.n_shared = int(ns);
+        }
         LaunchTiming t0{}, t1{};
         if (ev) {
             t0 = LaunchTiming{(*ev)[4 * j], (*ev)[4 * j + 1]};
             t1 = LaunchTiming{(*ev)[4 * j + 2], (*ev)[4 * j + 3]};
         }
         if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
-        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, s->pa, j, s->stream, ev ? &t0 : nullptr);
+        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, pa, j, s->stream, ev ? &t0 : nullptr);
         if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream, ev ? &t1 : nullptr);
-        else launch_shared_nodes(mon, s->is_batch, s->pa, j, s->stream, ev ? &t1 : nullptr);
+        else launch_shared_nodes(mon, s->is_batch, pa, j, s->stream, ev ? &t1 : nullptr);
     }
     if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k)], s->stream));
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,
@@ -453,10 +489,10 @@ tled_status enqueue_chunk(tled_sim *s, int k, double *ms = nullptr, std::vector<
     return TLED_OK;
 }
 
-tled_status build_graph(tled_sim *s, int k) {
+tled_status build_graph(tled_sim *s, int k, int64_t step0) {
     hipGraph_t g = nullptr;
     HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    tled_status st = enqueue_chunk(s, k);
+    tled_status st = enqueue_chunk(s, k, step0, true);
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (st != TLED_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -470,6 +506,7 @@ tled_status build_graph(tled_sim *s, int k) {
         return fail(s, TLED_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
     s->graph_k = k;
+    active_counts(s, step0, &s->graph_np, &s->graph_ns);
     return TLED_OK;
 }
 
@@ -598,7 +635,7 @@ tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
         return fail(sim, TLED_E_STATE, "layout options must be set before tled_finalize");
     int old_k = sim->opt.graph_steps;
     sim->opt = *opt;
-    if (sim->opt.graph_steps == 0) sim->opt.graph_steps = 50;
+    if (sim->opt.graph_steps == 0) sim->opt.graph_steps = sim->is_batch ? -1 : 50;
     if (sim->finalized && sim->opt.graph_steps != old_k && sim->graph) {
         (void)hipGraphExecDestroy(sim->graph);
         sim->graph = nullptr;
@@ -766,22 +803,29 @@ tled_status tled_step(tled_sim *sim, int64_t n_steps) {
     TRY(need_device(sim));
     if (n_steps < 0) return fail(sim, TLED_E_ARG, "negative step count");
     const int k = sim->opt.graph_steps;
-    int64_t left = n_steps;
+    int64_t left = n_steps, cur = sim->step;
     if (k > 0) {
         while (left >= k) {
-            if (!sim->graph || sim->graph_k != k) {
+            // a batch's graph launches the prefix of scenarios running at its
+            // first step: captured again when that prefix has changed
+            int np;
+            int64_t ns;
+            active_counts(sim, cur, &np, &ns);
+            if (!sim->graph || sim->graph_k != k || sim->graph_np != np || sim->graph_ns != ns) {
                 if (sim->graph) { (void)hipGraphExecDestroy(sim->graph); sim->graph = nullptr; }
-                TRY(build_graph(sim, k));
+                TRY(build_graph(sim, k, cur));
             }
             HIPCHK(sim, hipGraphLaunch(sim->graph, sim->stream));
             left -= k;
+            cur += k;
         }
     }
     const int chunk = k > 0 ? k : 100;
     while (left > 0) {
         int c = int(std::min<int64_t>(left, chunk));
-        TRY(enqueue_chunk(sim, c));
+        TRY(enqueue_chunk(sim, c, cur, false));
         left -= c;
+        cur += c;
     }
     sim->step += n_steps;
     return TLED_OK;
@@ -1037,6 +1081,7 @@ tled_status tled_set_state(tled_sim *sim, const void *buf) {
 tled_status tled_batch_create(tled_batch **out, int device) {
     TRY(tled_create(out, device));
     (*out)->is_batch = true;
+    (*out)->opt.graph_steps = -1;   // batches: eager steps, each launching exactly the running scenarios
     return TLED_OK;
 }
 
@@ -1120,8 +1165,16 @@ tled_status tled_batch_finalize(tled_batch *b) {
     for (size_t k = 0; k < pe.size(); ++k)
         pe[k] = b->scen_pe[k] > 0 ? b->scen_pe[k]
                                   : (b->opt.patch_elems > 0 ? b->opt.patch_elems : (b->scen[k].npe == 4 ? 448 : 256));
-    tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, b->opt.reorder != 2, &b->pc, &b->ranges, &b->patch_scen,
-                                      &b->shared_scen, &b->err);
+    // end steps as set below, for the union order (scenarios by descending end step)
+    auto end_of = [b](size_t k, double dt_cr) -> int64_t {
+        if (b->scen_cfl[k] > 0.0) {
+            const double dt = b->scen_cfl[k] * dt_cr;
+            return dt > 0.0 ? std::max<int64_t>(1, std::llround(b->scen_tend[k] / dt)) : 0;
+        }
+        return b->scen_steps[k];
+    };
+    tled_status st = precompute_batch(b->scen, pe, b->opt.reorder >= 0, b->opt.reorder != 2, end_of, &b->pc,
+                                      &b->ranges, &b->patch_scen, &b->shared_scen, &b->err);
     if (st != TLED_OK) return st;
     for (size_t k = 0; k < b->scen.size(); ++k) {
         HostProblem &p = b->scen[k];
@@ -1145,6 +1198,23 @@ tled_status tled_batch_finalize(tled_batch *b) {
     probe.max_elems = b->pc.patches.slot_stride;
     if (patch_lds_bytes(b->scen[0].npe, v == 2, probe) > 65536 - 1024)
         return fail(b, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
+    {
+        const size_t S = b->scen.size();
+        std::vector<size_t> pos(S);
+        std::iota(pos.begin(), pos.end(), size_t(0));
+        std::sort(pos.begin(), pos.end(), [&](size_t x, size_t y) { return b->ranges[x].patch_lo < b->ranges[y].patch_lo; });
+        b->pos_end.resize(S);
+        b->pos_patch_hi.resize(S);
+        b->pos_shared_hi.resize(S);
+        for (size_t m = 0; m < S; ++m) {
+            const size_t k = pos[m];
+            b->pos_end[m] = b->scen_steps[k];
+            b->pos_patch_hi[m] = b->ranges[k].patch_hi;
+            b->pos_shared_hi[m] = b->ranges[k].sh_hi - b->pc.patches.n_interior;
+        }
+        // not a prefix order (cannot happen: the union was ordered by these end steps): launch everything
+        if (!std::is_sorted(b->pos_end.begin(), b->pos_end.end(), std::greater<int64_t>())) b->pos_end.clear();
+    }
     b->variant = v;
     b->prob = b->scen[0];
     b->prob.nn = b->pc.nn;
@@ -1268,13 +1338,13 @@ tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]) {
     if (!ms || n_steps <= 0) return fail(sim, TLED_E_ARG, "need n_steps > 0 and an output array");
     ms[0] = ms[1] = ms[2] = 0.0;
     const int chunk = sim->opt.graph_steps > 0 ? sim->opt.graph_steps : 100;
-    int64_t left = n_steps, chunks = 0;
+    int64_t left = n_steps, chunks = 0, cur = sim->step;
     std::vector<hipEvent_t> ev(4 * size_t(chunk) + 2);
     for (auto &e : ev) HIPCHK(sim, hipEventCreate(&e));
     tled_status st = TLED_OK;
     while (left > 0 && st == TLED_OK) {
         int c = int(std::min<int64_t>(left, chunk));
-        st = enqueue_chunk(sim, c, nullptr, &ev);
+        st = enqueue_chunk(sim, c, cur, false, nullptr, &ev);
         if (st != TLED_OK) break;
         HIPCHK(sim, hipStreamSynchronize(sim->stream));
         for (int j = 0; j < c; ++j) {
@@ -1289,6 +1359,7 @@ tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]) {
         ms[2] += f;
         ++chunks;
         left -= c;
+        cur += c;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (st != TLED_OK) return st;

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -617,7 +618,8 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
 }
 
 tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
-                             bool reorder, bool bisect, Precomputed *out, std::vector<ScenRange> *ranges,
+                             bool reorder, bool bisect, const std::function<int64_t(size_t, double)> &end_step,
+                             Precomputed *out, std::vector<ScenRange> *ranges,
                              std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
                              std::string *err) {
     const size_t S = ps.size();
@@ -654,15 +656,25 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
     for (auto &th : pool) th.join();
     for (size_t k = 0; k < S; ++k)
         if (sts[k] != TLED_OK) { *err = "scenario " + std::to_string(k) + ": " + errs[k]; return sts[k]; }
-    // offsets of every scenario in the union (serial prefix sums), then each
-    // scenario fills its own slices of the union arrays (in parallel)
+    // Union order: scenarios by descending end step (stable), so that the
+    // patches and shared nodes of the scenarios still running at any step form
+    // a prefix of the union arrays and a step can launch just that prefix.
+    std::vector<int64_t> ends(S);
+    for (size_t k = 0; k < S; ++k) ends[k] = end_step(k, pcs[k].dt_cr);
+    std::vector<size_t> order(S);
+    std::iota(order.begin(), order.end(), size_t(0));
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return ends[a] > ends[b]; });
+    // offsets of every scenario in the union (serial prefix sums in union
+    // order), then each scenario fills its own slices of the union arrays (in
+    // parallel)
     struct Off {
         int64_t e, i, s, patch, sid, lrow, lx, geo, hgc, khg, a0, lconn, ppos;
     };
     std::vector<Off> off(S + 1);
     {
         Off o{};
-        for (size_t k = 0; k < S; ++k) {
+        for (size_t pos = 0; pos < S; ++pos) {
+            const size_t k = order[pos];
             off[k] = o;
             const Precomputed &pc = pcs[k];
             const Patches &Q = pc.patches;

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <limits>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -113,11 +114,14 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
 
 // Batch of independent scenarios (same element type): each is precomputed with
 // its own patch size, then all are concatenated into one union problem whose
-// patch partition never mixes scenarios.  Node order of the union: all
-// patch-interior nodes scenario by scenario, then all shared nodes scenario by
-// scenario.  patch_scen / shared_scen give the scenario of each patch / shared node.
+// patch partition never mixes scenarios.  Scenarios enter the union in order
+// of descending end_step(k, critical dt of k) (stable); node order of the
+// union: all patch-interior nodes scenario by scenario, then all shared nodes
+// scenario by scenario.  patch_scen / shared_scen give the scenario of each
+// patch / shared node.
 tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vector<int> &patch_elems,
-                             bool reorder, bool bisect, Precomputed *out, std::vector<ScenRange> *ranges,
+                             bool reorder, bool bisect, const std::function<int64_t(size_t, double)> &end_step,
+                             Precomputed *out, std::vector<ScenRange> *ranges,
                              std::vector<int32_t> *patch_scen, std::vector<int32_t> *shared_scen,
                              std::string *err);
 

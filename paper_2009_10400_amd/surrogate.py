@@ -255,7 +255,7 @@ def unscale(problem, duration: float, y):
     return problem.params["T0"] + sT * y[..., 0], su * y[..., 1:]
 
 
-def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, graph_steps: int = 50, log=None):
+def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, graph_steps: int = 0, log=None):
     """Runs scenarios [(Problem, duration)] in one batch, each to the end of its heating,
     and reads every scenario's fields at n_snap evenly spaced batch steps.  A snapshot
     of a scenario at heating time t is the solution of the same scenario with
@@ -289,7 +289,7 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
     return snaps, el
 
 
-def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 50):
+def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 0):
     """Solver alone: one batch, every scenario to the end of its heating.
     Returns ([(u, T)], {"setup": s, "run": s, "total": s}): set-up = host precompute and
     upload, run = GPU stepping and the read-back of every field."""

@@ -25,11 +25,14 @@ def critical_dt(problem):
     return dt
 
 
-def test_batch_equals_single_runs_bitwise_and_holds():
+@pytest.mark.parametrize("graph_steps", [40, -1])
+def test_batch_equals_single_runs_bitwise_and_holds(graph_steps):
+    # scenarios end at different steps, most of them inside a chunk: a step launches only the
+    # scenarios still running (graph chunks: those running at the chunk's first step)
     from paper_2009_10400_amd import tled
     sc, steps = small_batch()
     b = tled.Batch(0)
-    b.set_options(graph_steps=40)
+    b.set_options(graph_steps=graph_steps)
     dts = []
     for (p, _), n in zip(sc, steps):
         dt = 0.8 * critical_dt(p)
