@@ -760,6 +760,7 @@ tled_status tled_finalize(tled_sim *sim) {
     so.reorder = sim->opt.reorder >= 0;
     so.bisect = sim->opt.reorder != 2;
     so.build_patches = (v >= 2);
+    so.threads = host_threads();
     so.patch_elems = sim->opt.patch_elems > 0
                          ? sim->opt.patch_elems
                          : default_patch_elems(sim->prob.npe, sim->prob.ne, sim->opt.block_size);

@@ -172,42 +172,75 @@ tled_status check_inputs(const HostProblem &p, std::string *err) {
 }
 
 // Elements in caller order with repaired orientation; geometry per element.
+// f(lo, hi) over [0, n) cut into `threads` contiguous ranges, one host thread
+// each (the calling thread takes the first).  Callers only write disjoint
+// ranges, so the result does not depend on the thread count.
+template <class F>
+void parallel_ranges(int64_t n, int threads, F f) {
+    const int t = int(std::max<int64_t>(1, std::min<int64_t>(threads, n / 4096)));
+    if (t <= 1) { f(int64_t(0), n); return; }
+    std::vector<std::thread> pool;
+    for (int i = 1; i < t; ++i) pool.emplace_back([&, i] { f(n * i / t, n * (i + 1) / t); });
+    f(int64_t(0), n / t);
+    for (auto &th : pool) th.join();
+}
+
 tled_status element_pass(const HostProblem &p, std::vector<int32_t> *conn, std::vector<ElemGeo> *geo,
-                         int64_t *n_swapped, std::string *err) {
+                         int64_t *n_swapped, std::string *err, int threads = 1) {
     const int npe = p.npe;
     *conn = p.conn;
     geo->resize(p.ne);
-    *n_swapped = 0;
-    for (int64_t e = 0; e < p.ne; ++e) {
-        int32_t *c = conn->data() + npe * e;
-        double Xe[24];
-        for (int a = 0; a < npe; ++a) {
-            if (c[a] < 0 || c[a] >= p.nn) {
-                *err = "connectivity of element " + std::to_string(e) + " out of range";
-                return TLED_E_MESH;
+    // per range: swapped count and the first failing element (the lowest over
+    // all ranges is the one a serial pass would report)
+    struct Res { int64_t swapped = 0, bad = -1; tled_status st = TLED_OK; std::string msg; };
+    std::vector<Res> res(std::max(1, threads));
+    std::atomic<int> slot{0};
+    parallel_ranges(p.ne, threads, [&](int64_t lo, int64_t hi) {
+        Res &r = res[slot++];
+        for (int64_t e = lo; e < hi; ++e) {
+            int32_t *c = conn->data() + npe * e;
+            double Xe[24];
+            bool range_ok = true;
+            for (int a = 0; a < npe; ++a) {
+                if (c[a] < 0 || c[a] >= p.nn) { range_ok = false; break; }
+                std::memcpy(Xe + 3 * a, p.X.data() + 3 * int64_t(c[a]), 3 * sizeof(double));
             }
-            std::memcpy(Xe + 3 * a, p.X.data() + 3 * int64_t(c[a]), 3 * sizeof(double));
-        }
-        double d;
-        if (npe == 4) {
-            d = tet_geometry(Xe, &(*geo)[e]);
-            if (d < 0.0) {
-                std::swap(c[2], c[3]);
-                for (int i = 0; i < 3; ++i) std::swap(Xe[6 + i], Xe[9 + i]);
+            if (!range_ok) {
+                r = Res{r.swapped, e, TLED_E_MESH, "connectivity of element " + std::to_string(e) + " out of range"};
+                return;
+            }
+            double d;
+            if (npe == 4) {
                 d = tet_geometry(Xe, &(*geo)[e]);
-                ++*n_swapped;
-            }
-            if (!(d > 0.0)) {
-                *err = "T4 element " + std::to_string(e) + " has zero volume";
-                return TLED_E_MESH;
-            }
-        } else {
-            d = hex_geometry(Xe, &(*geo)[e]);
-            if (!(d > 0.0)) {
-                *err = "H8 element " + std::to_string(e) + " has det J0 <= 0 (inverted or degenerate)";
-                return TLED_E_MESH;
+                if (d < 0.0) {
+                    std::swap(c[2], c[3]);
+                    for (int i = 0; i < 3; ++i) std::swap(Xe[6 + i], Xe[9 + i]);
+                    d = tet_geometry(Xe, &(*geo)[e]);
+                    ++r.swapped;
+                }
+                if (!(d > 0.0)) {
+                    r = Res{r.swapped, e, TLED_E_MESH, "T4 element " + std::to_string(e) + " has zero volume"};
+                    return;
+                }
+            } else {
+                d = hex_geometry(Xe, &(*geo)[e]);
+                if (!(d > 0.0)) {
+                    r = Res{r.swapped, e, TLED_E_MESH,
+                            "H8 element " + std::to_string(e) + " has det J0 <= 0 (inverted or degenerate)"};
+                    return;
+                }
             }
         }
+    });
+    *n_swapped = 0;
+    const Res *first = nullptr;
+    for (const Res &r : res) {
+        *n_swapped += r.swapped;
+        if (r.bad >= 0 && (!first || r.bad < first->bad)) first = &r;
+    }
+    if (first) {
+        *err = first->msg;
+        return first->st;
     }
     return TLED_OK;
 }
@@ -273,39 +306,53 @@ std::vector<int64_t> morton_order(const HostProblem &p, const std::vector<int32_
 // 8 % fewer patch-local node copies on tetrahedral meshes and bounds the
 // nodes of the largest patch far more tightly (a regular grid of power-of-two
 // size is cut into boxes of the same size either way).
-std::vector<int64_t> bisection_order(const HostProblem &p, const std::vector<int32_t> &conn, int P) {
+std::vector<int64_t> bisection_order(const HostProblem &p, const std::vector<int32_t> &conn, int P, int threads) {
     std::vector<double> cen;
     std::vector<uint64_t> key;
     centroids_and_keys(p, conn, &cen, &key);
-    std::vector<int64_t> order(p.ne);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<std::pair<int64_t, int64_t>> todo{{0, p.ne}};   // depth first: right pushed first
-    while (!todo.empty()) {
-        auto [lo, hi] = todo.back();
-        todo.pop_back();
+    // the partition moves compact records (centroid, key, element) rather than
+    // indices into the centroid array
+    struct Item {
+        double c[3];
+        uint64_t key;
+        int64_t e;
+    };
+    std::vector<Item> it(p.ne);
+    for (int64_t e = 0; e < p.ne; ++e) it[e] = Item{{cen[3 * e], cen[3 * e + 1], cen[3 * e + 2]}, key[e], e};
+    // the two halves of a cut are disjoint ranges: the top cuts hand one half
+    // to another host thread (the result does not depend on the thread count)
+    std::function<void(int64_t, int64_t, int)> split = [&](int64_t lo, int64_t hi, int par) {
         const int64_t M = hi - lo;
-        auto first = order.begin() + lo, last = order.begin() + hi;
+        auto first = it.begin() + lo, last = it.begin() + hi;
         if (M <= P) {
-            std::sort(first, last, [&](int64_t a, int64_t b) { return key[a] != key[b] ? key[a] < key[b] : a < b; });
-            continue;
+            std::sort(first, last, [](const Item &a, const Item &b) { return a.key != b.key ? a.key < b.key : a.e < b.e; });
+            return;
         }
         double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-        for (auto it = first; it != last; ++it)
+        for (auto q = first; q != last; ++q)
             for (int i = 0; i < 3; ++i) {
-                mn[i] = std::min(mn[i], cen[3 * *it + i]);
-                mx[i] = std::max(mx[i], cen[3 * *it + i]);
+                mn[i] = std::min(mn[i], q->c[i]);
+                mx[i] = std::max(mx[i], q->c[i]);
             }
         int ax = 0;   // extents equal to rounding go to the lower axis (regular grids cut alike everywhere)
         for (int i = 1; i < 3; ++i)
             if (mx[i] - mn[i] > (mx[ax] - mn[ax]) * (1.0 + 1e-9)) ax = i;
         const int64_t q = (M + P - 1) / P, left = (q / 2) * int64_t(P);
-        std::nth_element(first, first + left, last, [&](int64_t a, int64_t b) {
-            const double ca = cen[3 * a + ax], cb = cen[3 * b + ax];
-            return ca != cb ? ca < cb : a < b;
+        std::nth_element(first, first + left, last, [ax](const Item &a, const Item &b) {
+            return a.c[ax] != b.c[ax] ? a.c[ax] < b.c[ax] : a.e < b.e;
         });
-        todo.push_back({lo + left, hi});
-        todo.push_back({lo, lo + left});
-    }
+        if (par > 1 && M > 8192) {
+            std::thread th(split, lo, lo + left, par / 2);
+            split(lo + left, hi, par - par / 2);
+            th.join();
+        } else {
+            split(lo, lo + left, 1);
+            split(lo + left, hi, 1);
+        }
+    };
+    split(0, p.ne, std::max(1, threads));
+    std::vector<int64_t> order(p.ne);
+    for (int64_t e = 0; e < p.ne; ++e) order[e] = it[e].e;
     return order;
 }
 
@@ -455,6 +502,12 @@ void build_patches(Precomputed *pc, int patch_elems, const std::vector<double> &
 
 }  // namespace
 
+int host_threads() {
+    int nt = int(std::thread::hardware_concurrency());
+    if (const char *env = std::getenv("TLED_HOST_THREADS")) nt = std::atoi(env);
+    return std::max(1, std::min(nt, 64));
+}
+
 tled_status critical_dt(const HostProblem &p, double *dt_cr, std::string *err) {
     tled_status st = check_inputs(p, err);
     if (st != TLED_OK) return st;
@@ -479,7 +532,7 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
     Precomputed &pc = *out;
     pc = Precomputed();
     pc.npe = npe; pc.nn = p.nn; pc.ne = p.ne;
-    st = element_pass(p, &conn, &geo, &pc.n_swapped, err);
+    st = element_pass(p, &conn, &geo, &pc.n_swapped, err, opt.threads);
     if (st != TLED_OK) return st;
 
     double cd = wave_speed(p.mat);
@@ -489,7 +542,8 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
     // element order (fused variants: patches of pe consecutive elements)
     const int pe = std::max(8, std::min(opt.patch_elems, 65536 / npe));
     std::vector<int64_t> eorder(p.ne);
-    if (opt.reorder) eorder = (opt.build_patches && opt.bisect) ? bisection_order(p, conn, pe) : morton_order(p, conn);
+    if (opt.reorder)
+        eorder = (opt.build_patches && opt.bisect) ? bisection_order(p, conn, pe, opt.threads) : morton_order(p, conn);
     else std::iota(eorder.begin(), eorder.end(), 0);
     pc.elem_new2old = eorder;
     // node order: first touch along the element order (or identity)
@@ -607,7 +661,8 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
 
     if (opt.build_patches) build_patches(&pc, pe, p.X);
 
-    // node -> element-slot incidence (ascending slot order)
+    // node -> element-slot incidence (ascending slot order): the two-pass variant's gather
+    if (opt.build_patches) return TLED_OK;
     pc.rowptr.assign(nn + 1, 0);
     for (int64_t s = 0; s < ne * npe; ++s) pc.rowptr[pc.conn[s] + 1]++;
     for (int64_t a = 0; a < nn; ++a) pc.rowptr[a + 1] += pc.rowptr[a];
@@ -644,12 +699,11 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
             so.bisect = bisect;
             so.build_patches = true;
             so.patch_elems = patch_elems[k];
+            so.threads = std::max(1, host_threads() / int(S));   // threads left over for each scenario
             sts[k] = precompute(ps[k], so, &pcs[k], &errs[k]);
         }
     };
-    int nt = int(std::thread::hardware_concurrency());
-    if (const char *env = std::getenv("TLED_HOST_THREADS")) nt = std::atoi(env);
-    nt = std::max(1, std::min({nt, 64, int(S)}));
+    const int nt = std::max(1, std::min(host_threads(), int(S)));
     std::vector<std::thread> pool;
     for (int t = 1; t < nt; ++t) pool.emplace_back(work);
     work();

@@ -102,7 +102,11 @@ struct SetupOptions {
     bool build_patches = false;
     bool bisect = true;      // with reorder and build_patches: patches by coordinate bisection
     int patch_elems = 512;
+    int threads = 1;         // host threads for the element pass and the bisection
 };
+
+// Host threads for set-up: the hardware concurrency, or TLED_HOST_THREADS, in 1..64.
+int host_threads();
 
 // Element geometry and critical step only (no reordering), for tled_critical_dt.
 // Returns TLED_OK or TLED_E_MESH with a message.

@@ -325,3 +325,27 @@ def test_bisection_patches_beat_morton_runs_on_tetrahedra():
     with pytest.raises(tled.TledError) as e:
         host_sim(W.cube_t4(n=2, L=0.01), reorder=3)
     assert e.value.status == tled.E_ARG
+
+
+def test_single_setup_is_independent_of_host_threads(monkeypatch):
+    """The element pass and the bisection of one problem run on several host threads; the
+    layout and the first reported mesh error do not depend on how many."""
+    from paper_2009_10400_amd import tled
+    p = W.ellipsoid_t4(200_000)
+    bad = p.conn.copy()
+    for e in (150_000, 40_000):                 # two zero-volume elements: the lower one is reported
+        bad[e, 3] = bad[e, 2]
+    out = []
+    for n in ("1", "8"):
+        monkeypatch.setenv("TLED_HOST_THREADS", n)
+        s = host_sim(p)
+        out.append((s.info(), s.lumped()["M"].tobytes()))
+        s = tled.Sim(-1)
+        s.set_mesh(4, p.X, bad)
+        s.set_material(p.params)
+        s.set_time(1e-6, 0.0)
+        with pytest.raises(tled.TledError) as e:
+            s.finalize()
+        out.append(str(e.value))
+    assert out[0] == out[2] and out[1] == out[3]
+    assert "element 40000 " in out[1]
