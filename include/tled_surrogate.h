@@ -83,6 +83,26 @@ tled_status tled_mlp_gradient(tled_mlp *mlp, int64_t n, const float *coords, con
  * stream); asynchronous.  Returns TLED_E_ARG on bad sizes or null pointers. */
 tled_status tled_mlp_ensemble_stats(int64_t n, int32_t members, int32_t n_out, const float *outs,
                                     const float *scale, float *mean, float *spread, void *hip_stream);
+/* Network inputs of n_scen scenarios, whose nodes are the consecutive row ranges
+ * [row_begin[s], row_begin[s+1]) of n_rows = row_begin[n_scen] rows (offsets
+ * nondecreasing, row_begin[0] = 0; every scenario with rows).  For row r of
+ * scenario s, with node coordinates X[r] (m, FP64, n_rows x 3):
+ *   x_out[r] = (X[r] - probe[s]) * xi[s]          (n_rows x 3),
+ *   p_out[r] = (X[r] * p_scale, prm[s][0..n_prm)) (n_rows x (3 + n_prm)),
+ * the products formed in FP64 and rounded once to FP32 (prm is FP32, n_scen x
+ * n_prm).  All arrays on the device; enqueued on hip_stream (NULL: the null
+ * stream), asynchronous.  TLED_E_ARG on bad sizes or null pointers. */
+tled_status tled_mlp_scenario_inputs(int32_t n_scen, int32_t n_prm, int64_t n_rows, const int64_t *row_begin,
+                                     const double *X, const double *probe, const double *xi, double p_scale,
+                                     const float *prm, float *x_out, float *p_out, void *hip_stream);
+/* Physical fields from the ensemble statistics (rows as above, FP32 device
+ * arrays): T_out[r] = T0[s] + sT[s] * mean[r][0], u_out[r][i] = su[s] *
+ * mean[r][1 + i], spread_out[r] = sT[s] * spread[r], each operation rounded
+ * separately (no fused multiply-add).  Asynchronous on hip_stream; TLED_E_ARG
+ * on bad sizes or null pointers. */
+tled_status tled_mlp_scenario_outputs(int32_t n_scen, int64_t n_rows, const int64_t *row_begin, const float *mean,
+                                      const float *spread, const float *T0, const float *sT, const float *su,
+                                      float *T_out, float *u_out, float *spread_out, void *hip_stream);
 /* Plain GEMM on the matrix cores, for tests of the kernel itself:
  * C[m][n] = sum_k A[m][k] B[k][n], A (m x k) and B (k x n) bfloat16 bit
  * patterns (device, row-major), C FP32 (device, row-major). */

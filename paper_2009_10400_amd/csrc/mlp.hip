@@ -502,6 +502,60 @@ __global__ void ensemble_stats_kernel(long n, int K, int nout, const float *__re
     }
 }
 
+// Scenario of row r: the s with row_begin[s] <= r < row_begin[s + 1] (binary
+// search over the n_scen + 1 offsets; rows of empty scenarios never occur).
+__device__ inline int scenario_of(const int64_t *__restrict__ row_begin, int n_scen, int64_t r) {
+    int lo = 0, hi = n_scen - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_begin[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Network inputs of many scenarios in one pass over their nodes: coordinates
+// relative to the scenario's probe in units of its coordinate scale, and the
+// parameter row (coordinates times p_scale, then the scenario's constants).
+// The coordinate arithmetic is FP64, rounded once to FP32.
+__global__ void scenario_inputs_kernel(int n_scen, int n_prm, const int64_t *__restrict__ row_begin,
+                                       const double *__restrict__ X, const double *__restrict__ probe,
+                                       const double *__restrict__ xi, double p_scale, const float *__restrict__ prm,
+                                       float *__restrict__ x_out, float *__restrict__ p_out) {
+#pragma clang fp contract(off)
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= row_begin[n_scen]) return;
+    const int sc = scenario_of(row_begin, n_scen, r);
+    const int w = 3 + n_prm;
+    for (int i = 0; i < 3; ++i) {
+        const double x = X[3 * r + i];
+        const double rel = x - probe[3 * sc + i];
+        x_out[3 * r + i] = float(rel * xi[sc]);
+        p_out[w * r + i] = float(x * p_scale);
+    }
+    for (int k = 0; k < n_prm; ++k) p_out[w * r + 3 + k] = prm[size_t(n_prm) * sc + k];
+}
+
+// Ensemble mean and spread (scaled targets) to physical fields of each row's
+// scenario, in FP32 with one rounding per operation (no fused multiply-add):
+// T = T0 + sT * m0, u = su * m1..3, spread_K = sT * spread.
+__global__ void scenario_outputs_kernel(int n_scen, const int64_t *__restrict__ row_begin,
+                                        const float *__restrict__ mean, const float *__restrict__ spread,
+                                        const float *__restrict__ T0, const float *__restrict__ sT,
+                                        const float *__restrict__ su, float *__restrict__ T_out,
+                                        float *__restrict__ u_out, float *__restrict__ spread_out) {
+    // plain operators under contract(off): hipcc would otherwise form an FMA
+    // (its rounding intrinsics are header functions the pragma does not reach)
+#pragma clang fp contract(off)
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= row_begin[n_scen]) return;
+    const int sc = scenario_of(row_begin, n_scen, r);
+    const float rise = sT[sc] * mean[4 * r];
+    T_out[r] = T0[sc] + rise;
+    for (int i = 0; i < 3; ++i) u_out[3 * r + i] = su[sc] * mean[4 * r + 1 + i];
+    spread_out[r] = sT[sc] * spread[r];
+}
+
 inline unsigned blocks(long n) { return unsigned((n + kThreads - 1) / kThreads); }
 
 struct Layer {
@@ -980,6 +1034,32 @@ tled_status tled_mlp_ensemble_stats(int64_t n, int32_t members, int32_t n_out, c
     hipLaunchKernelGGL(ensemble_stats_kernel, dim3(blocks(n)), dim3(kThreads), 0,
                        static_cast<hipStream_t>(hip_stream), long(n), int(members), int(n_out), outs, scale, mean,
                        spread);
+    return hipGetLastError() == hipSuccess ? TLED_OK : TLED_E_HIP;
+}
+
+tled_status tled_mlp_scenario_inputs(int32_t n_scen, int32_t n_prm, int64_t n_rows, const int64_t *row_begin,
+                                     const double *X, const double *probe, const double *xi, double p_scale,
+                                     const float *prm, float *x_out, float *p_out, void *hip_stream) {
+    if (n_scen < 1 || n_prm < 0 || n_prm > 64 || n_rows < 0 ||
+        (n_rows > 0 && (!row_begin || !X || !probe || !xi || (n_prm > 0 && !prm) || !x_out || !p_out)))
+        return TLED_E_ARG;
+    if (n_rows == 0) return TLED_OK;
+    hipLaunchKernelGGL(scenario_inputs_kernel, dim3(blocks(n_rows)), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(hip_stream), int(n_scen), int(n_prm), row_begin, X, probe, xi,
+                       p_scale, prm, x_out, p_out);
+    return hipGetLastError() == hipSuccess ? TLED_OK : TLED_E_HIP;
+}
+
+tled_status tled_mlp_scenario_outputs(int32_t n_scen, int64_t n_rows, const int64_t *row_begin, const float *mean,
+                                      const float *spread, const float *T0, const float *sT, const float *su,
+                                      float *T_out, float *u_out, float *spread_out, void *hip_stream) {
+    if (n_scen < 1 || n_rows < 0 ||
+        (n_rows > 0 && (!row_begin || !mean || !spread || !T0 || !sT || !su || !T_out || !u_out || !spread_out)))
+        return TLED_E_ARG;
+    if (n_rows == 0) return TLED_OK;
+    hipLaunchKernelGGL(scenario_outputs_kernel, dim3(blocks(n_rows)), dim3(kThreads), 0,
+                       static_cast<hipStream_t>(hip_stream), int(n_scen), row_begin, mean, spread, T0, sT, su, T_out,
+                       u_out, spread_out);
     return hipGetLastError() == hipSuccess ? TLED_OK : TLED_E_HIP;
 }
 

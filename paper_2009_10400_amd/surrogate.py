@@ -47,6 +47,10 @@ _SIGS = {
     "tled_mlp_gradient": ([_P, ctypes.c_int64, _P, _P, _P, _fp, _fp], ctypes.c_int),
     "tled_mlp_gemm": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "tled_mlp_ensemble_stats": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_scenario_inputs": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_double,
+                                  _P, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_scenario_outputs": ([ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+                                  ctypes.c_int),
     "tled_mlp_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "tled_mlp_last_timing": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                              ctypes.c_int),
@@ -348,13 +352,11 @@ class Ensemble:
         hist = [train(m, d, epochs, batch=batch, lr=lr, seed=i, log=log) for i, m in enumerate(self.models)]
         return hist, time.perf_counter() - t0
 
-    def _forward_all(self, x, p):
-        """Member outputs into one K x n x 4 device array, then the library's ensemble
-        statistics kernel: (mean of the scaled targets n x 4, spread of target 0, n)."""
+    def _forward_device(self, X, Pm):
+        """Member outputs (device inputs) into one K x n x 4 device array, then the library's
+        ensemble statistics kernel: device (mean of the scaled targets n x 4, spread of target 0)."""
         import torch
         dev = torch.device("cuda", self.device)
-        X = torch.from_numpy(x).to(dev)
-        Pm = torch.from_numpy(p).to(dev)
         n, K = X.shape[0], len(self.models)
         outs = torch.empty((K, n, 4), dtype=torch.float32, device=dev)
         mean = torch.empty((n, 4), dtype=torch.float32, device=dev)
@@ -370,25 +372,52 @@ class Ensemble:
             raise TledError(st, "tled_mlp_ensemble_stats failed")
         torch.cuda.synchronize(dev)
         self.last_forward_s = time.perf_counter() - t0
-        return mean.cpu().numpy(), spread.cpu().numpy()
+        return mean, spread
 
     def predict_many(self, items):
-        """items [(Problem, duration)] -> [(T mean, u mean, T spread)], one forward call per member."""
-        sizes = [p.nn for p, _ in items]
-        X = np.empty((sum(sizes), 3), np.float32)
-        P = np.empty((sum(sizes), N_PARAM), np.float32)
-        o = 0
-        for (p, d), m in zip(items, sizes):
-            fill_inputs(p, d, self.t_ref, X[o:o + m], P[o:o + m])
-            o += m
-        ym, ys = self._forward_all(X, P)
-        out, o = [], 0
-        for (p, d), m in zip(items, sizes):
-            sl = slice(o, o + m)
-            o += m
-            T, u = unscale(p, d, ym[sl])
-            out.append((T, u, temperature_scale(p, d) * ys[sl]))
-        return out
+        """items [(Problem, duration)] -> [(T mean, u mean, T spread)] (FP32).  The nodes of all
+        scenarios go to the device once (FP64 coordinates and a few constants per scenario); the
+        library assembles the network inputs there (bitwise those of fill_inputs), the members
+        run, and the library turns the ensemble statistics into physical fields (bitwise those of
+        unscale), which come back in one copy."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        S = len(items)
+        sizes = np.array([p.nn for p, _ in items], np.int64)
+        offs = np.zeros(S + 1, np.int64)
+        np.cumsum(sizes, out=offs[1:])
+        n = int(offs[-1])
+        probe = np.empty((S, 3))
+        xi = np.empty(S)
+        prm = np.empty((S, N_PARAM - 3), np.float32)
+        T0 = np.empty(S, np.float32)
+        sT = np.empty(S, np.float32)
+        su = np.empty(S, np.float32)
+        for k, (p, d) in enumerate(items):
+            probe[k], prm[k] = _scenario_params(p, d, self.t_ref)
+            xi[k] = 1.0 / (XI_SCALE * p.h)
+            s_t = temperature_scale(p, d)
+            T0[k], sT[k], su[k] = p.params["T0"], s_t, p.params["alpha"] * s_t * p.h
+        Xd = torch.from_numpy(np.concatenate([np.asarray(p.X, np.float64) for p, _ in items])).to(dev)
+        tab = {name: torch.from_numpy(a).to(dev) for name, a in
+               (("offs", offs), ("probe", probe), ("xi", xi), ("prm", prm), ("T0", T0), ("sT", sT), ("su", su))}
+        x_in = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        p_in = torch.empty((n, N_PARAM), dtype=torch.float32, device=dev)
+        stream = _P(torch.cuda.current_stream(dev).cuda_stream)
+        st = _lib.tled_mlp_scenario_inputs(S, N_PARAM - 3, n, _dp(tab["offs"]), _dp(Xd), _dp(tab["probe"]),
+                                           _dp(tab["xi"]), 1.0 / 0.05, _dp(tab["prm"]), _dp(x_in), _dp(p_in), stream)
+        if st != 0:
+            raise TledError(st, "tled_mlp_scenario_inputs failed")
+        mean, spread = self._forward_device(x_in, p_in)
+        out_d = torch.empty(5 * n, dtype=torch.float32, device=dev)      # T | u | spread
+        st = _lib.tled_mlp_scenario_outputs(S, n, _dp(tab["offs"]), _dp(mean), _dp(spread), _dp(tab["T0"]),
+                                            _dp(tab["sT"]), _dp(tab["su"]), _dp(out_d[:n]), _dp(out_d[n:4 * n]),
+                                            _dp(out_d[4 * n:]), stream)
+        if st != 0:
+            raise TledError(st, "tled_mlp_scenario_outputs failed")
+        host = out_d.cpu().numpy()
+        T, u, sp = host[:n], host[n:4 * n].reshape(n, 3), host[4 * n:]
+        return [(T[a:b], u[a:b], sp[a:b]) for a, b in zip(offs[:-1], offs[1:])]
 
     def calibrate(self, items, fields):
         """Factor c with max|T - T_solver| <= c * max spread on every calibration field."""

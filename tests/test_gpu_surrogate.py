@@ -208,3 +208,41 @@ def test_ensemble_statistics_kernel(torch_dev):
                                rtol=1e-6)
     assert S._lib.tled_mlp_ensemble_stats(n, 0, no, S._dp(d_outs), S._dp(d_scale), S._dp(mean), S._dp(spread),
                                           None) != 0
+
+
+def test_scenario_inputs_and_outputs_match_the_host_path(torch_dev):
+    """predict_many assembles the inputs and unscales the outputs on the device; both are bitwise
+    those of the host functions (fill_inputs, unscale), on scenarios of different sizes."""
+    import torch
+    from paper_2009_10400_amd import surrogate as S, workloads as W
+    items = W.planning_scenarios(5, seed=41, lo=1500, hi=9000, duration_scale=1e-3)
+    ens = S.Ensemble(2, t_ref=0.3)
+    ens.y_std = np.array([0.7, 1.3, 0.9, 1.1], np.float32)
+    got = ens.predict_many(items)
+    for (p, d), (T, u, sp) in zip(items, got):
+        x, prm = S.scenario_inputs(p, d, ens.t_ref)
+        mean, spread = ens._forward_device(torch.from_numpy(x).to(torch_dev), torch.from_numpy(prm).to(torch_dev))
+        mean, spread = mean.cpu().numpy(), spread.cpu().numpy()
+        Tr, ur = S.unscale(p, d, mean)
+        spr = S.temperature_scale(p, d) * spread
+        assert T.dtype == Tr.dtype == np.float32 and T.shape == (p.nn,) and u.shape == (p.nn, 3)
+        assert np.array_equal(T, Tr) and np.array_equal(u, ur) and np.array_equal(sp, spr)
+    # the input kernel alone against fill_inputs, and its argument checks
+    p, d = items[0]
+    x, prm = S.scenario_inputs(p, d, ens.t_ref)
+    probe, pm = S._scenario_params(p, d, ens.t_ref)
+    offs = torch.tensor([0, p.nn], dtype=torch.int64, device=torch_dev)
+    Xd = torch.from_numpy(np.asarray(p.X, np.float64)).to(torch_dev)
+    pr = torch.from_numpy(probe.reshape(1, 3)).to(torch_dev)
+    xi = torch.tensor([1.0 / (S.XI_SCALE * p.h)], dtype=torch.float64, device=torch_dev)
+    pmd = torch.from_numpy(pm.astype(np.float32).reshape(1, -1)).to(torch_dev)
+    xo = torch.empty((p.nn, 3), dtype=torch.float32, device=torch_dev)
+    po = torch.empty((p.nn, S.N_PARAM), dtype=torch.float32, device=torch_dev)
+    assert S._lib.tled_mlp_scenario_inputs(1, S.N_PARAM - 3, p.nn, S._dp(offs), S._dp(Xd), S._dp(pr), S._dp(xi),
+                                           1.0 / 0.05, S._dp(pmd), S._dp(xo), S._dp(po), None) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(xo.cpu().numpy(), x) and np.array_equal(po.cpu().numpy(), prm)
+    assert S._lib.tled_mlp_scenario_inputs(0, S.N_PARAM - 3, p.nn, S._dp(offs), S._dp(Xd), S._dp(pr), S._dp(xi),
+                                           1.0 / 0.05, S._dp(pmd), S._dp(xo), S._dp(po), None) != 0
+    assert S._lib.tled_mlp_scenario_outputs(1, p.nn, None, S._dp(xo), S._dp(xo), S._dp(pmd), S._dp(pmd),
+                                            S._dp(pmd), S._dp(xo), S._dp(xo), S._dp(xo), None) != 0
