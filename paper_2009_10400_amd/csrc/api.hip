@@ -443,8 +443,9 @@ void active_counts(const tled_sim *s, int64_t step, int *n_patches, int64_t *n_s
     if (!s->is_batch || s->pos_end.empty()) return;
     const auto it = std::partition_point(s->pos_end.begin(), s->pos_end.end(), [&](int64_t e) { return e > step; });
     const size_t m = size_t(it - s->pos_end.begin());
-    *n_patches = std::max(1, m ? s->pos_patch_hi[m - 1] : 0);
-    *n_shared = std::max<int64_t>(1, m ? s->pos_shared_hi[m - 1] : 0);
+    // never more than the union holds (a batch may have no shared node at all)
+    *n_patches = std::min(s->pa.n_patches, std::max(1, m ? s->pos_patch_hi[m - 1] : 0));
+    *n_shared = std::min<int64_t>(s->pa.n_shared, std::max<int64_t>(1, m ? s->pos_shared_hi[m - 1] : 0));
 }
 
 // Enqueue a chunk of k steps (eager, or under stream capture) starting at step
@@ -478,7 +479,11 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
         if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
         else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, pa, j, s->stream, ev ? &t0 : nullptr);
         if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream, ev ? &t1 : nullptr);
-        else launch_shared_nodes(mon, s->is_batch, pa, j, s->stream, ev ? &t1 : nullptr);
+        else if (pa.n_shared > 0) launch_shared_nodes(mon, s->is_batch, pa, j, s->stream, ev ? &t1 : nullptr);
+        else if (ev) {   // no shared node, nothing to launch: the timed launch takes zero time
+            HIPCHK(s, hipEventRecord(t1.start, s->stream));
+            HIPCHK(s, hipEventRecord(t1.stop, s->stream));
+        }
     }
     if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k)], s->stream));
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,

@@ -158,3 +158,28 @@ def test_h8_batch_equals_single_runs_bitwise():
     b.step(30)
     for (u0, T0), (u1, T1) in zip(fields, b.read_all()):
         assert np.array_equal(u0, u1) and np.array_equal(T0, T1)
+
+
+def test_batch_without_shared_nodes():
+    """Scenarios that each fit one patch have no shared node: the shared-node launch is skipped
+    (also when timed), and each scenario still equals its own run bit for bit."""
+    from paper_2009_10400_amd import tled
+    probs = [W.cube_t4(n=2, L=0.01), W.cube_t4(n=3, L=0.012)]
+    steps = [30, 55]
+    dts = [0.8 * critical_dt(p) for p in probs]
+    for gs in (-1, 20):
+        b = tled.Batch(0)
+        b.set_options(graph_steps=gs)
+        for p, dt, n in zip(probs, dts, steps):
+            b.add(p, dt, n)
+        b.finalize()
+        assert b.batch_info()["n_shared_nodes"] == 0
+        b.run()
+        for k, (p, dt, n) in enumerate(zip(probs, dts, steps)):
+            ub, Tb = b.read(k)
+            s = tled.from_problem(p, dt=dt, device=0, kernel_variant=2, graph_steps=20, patch_elems=448)
+            s.step(n)
+            assert np.array_equal(ub, s.read_u()) and np.array_equal(Tb, s.read_T()), (gs, k)
+        kt = b.kernel_times(5)
+        assert kt["element_ms"] > 0.0 and kt["node_ms"] >= 0.0
+        b.close()
