@@ -293,12 +293,12 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
     return snaps, el
 
 
-def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 0):
+def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 0, torch_allocator: bool = False):
     """Solver alone: one batch, every scenario to the end of its heating.
     Returns ([(u, T)], {"setup": s, "run": s, "total": s}): set-up = host precompute and
     upload, run = GPU stepping and the read-back of every field."""
     t0 = time.perf_counter()
-    b = tled.Batch(device, stream=stream)
+    b = tled.Batch(device, stream=stream, use_torch_allocator=torch_allocator)
     b.set_options(graph_steps=graph_steps)
     for p, dur in scenarios:
         b.add(p, cfl=p.cfl, t_end=dur)

@@ -205,27 +205,31 @@ class Sim:
         self.device = device
         self._cb = None
         if use_torch_allocator and device >= 0:
-            import sys
-
-            import torch
-            torch.cuda.init()
-            dev = torch.device("cuda", device)
-
-            def _alloc(nbytes, ctx):
-                try:
-                    with torch.cuda.device(dev):
-                        return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
-                except Exception as exc:  # noqa: BLE001 - reported, then NULL (TLED_E_OOM)
-                    print(f"tled: torch allocator failed for {nbytes} bytes: {exc!r}", file=sys.stderr)
-                    return None
-
-            def _free(ptr, ctx):
-                torch.cuda.caching_allocator_delete(int(ptr))
-
-            self._cb = (_ALLOC(_alloc), _FREE(_free))
-            self._check(_lib.tled_set_allocator(h, self._cb[0], self._cb[1], None))
+            self._torch_allocator(device)
         if stream is not None:
             self._check(_lib.tled_set_stream(h, _P(int(stream))))
+
+    def _torch_allocator(self, device: int):
+        """Route the library's device allocations through torch's caching allocator."""
+        import sys
+
+        import torch
+        torch.cuda.init()
+        dev = torch.device("cuda", device)
+
+        def _alloc(nbytes, ctx):
+            try:
+                with torch.cuda.device(dev):
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
+            except Exception as exc:  # noqa: BLE001 - reported, then NULL (TLED_E_OOM)
+                print(f"tled: torch allocator failed for {nbytes} bytes: {exc!r}", file=sys.stderr)
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._cb = (_ALLOC(_alloc), _FREE(_free))
+        self._check(_lib.tled_set_allocator(self._h, self._cb[0], self._cb[1], None))
 
     # ------------------------------------------------------------------ helpers
     def _check(self, st):
@@ -398,7 +402,7 @@ def from_problem(problem, dt=None, device: int = 0, stream=None, finalize: bool 
 class Batch(Sim):
     """Many independent scenarios advanced together by the fused kernels."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, use_torch_allocator: bool = False):
         h = _P()
         st = _lib.tled_batch_create(ctypes.byref(h), int(device))
         if st != OK:
@@ -407,6 +411,8 @@ class Batch(Sim):
         self.device = device
         self._cb = None
         self.sizes = []
+        if use_torch_allocator and device >= 0:
+            self._torch_allocator(device)
         if stream is not None:
             self._check(_lib.tled_set_stream(h, _P(int(stream))))
 

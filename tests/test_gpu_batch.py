@@ -183,3 +183,20 @@ def test_batch_without_shared_nodes():
         kt = b.kernel_times(5)
         assert kt["element_ms"] > 0.0 and kt["node_ms"] >= 0.0
         b.close()
+
+
+def test_batch_through_the_torch_allocator():
+    """A batch whose device memory comes from torch's caching allocator gives the same bits."""
+    from paper_2009_10400_amd import tled
+    sc, steps = small_batch()
+    sc, steps = sc[:3], steps[:3]
+    out = []
+    for ta in (False, True):
+        b = tled.Batch(0, use_torch_allocator=ta)
+        for (p, _), n in zip(sc, steps):
+            b.add(p, 0.8 * critical_dt(p), n)
+        b.finalize()
+        b.run()
+        out.append([f.copy() for pair in b.read_all() for f in pair])
+        b.close()
+    assert all(np.array_equal(a, c) for a, c in zip(*out))
