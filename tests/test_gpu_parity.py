@@ -1,6 +1,6 @@
 """GPU parity: the HIP library (through its C-ABI) against the FP64 oracle.
 
-Bar (north star of the method's port): after 1000 steps, max-abs error of the
+Bar: after 1000 steps, max-abs error of the
 displacement relative to max |u| <= 1e-4 and max-abs error of the temperature
 <= 0.01 K.  The paper's total error indicators e_u, e_T (Section 6.1) are
 printed next to them.

@@ -57,8 +57,8 @@ def test_uniaxial_closed_form(s, eta_factor):
     assert np.abs(off).max() < 1e-9
 
 
-def test_uniaxial_values_survey_table():
-    """Numbers of the closed form at the C1 moduli (mu 1034.4828, kappa 1e4, eta 2 mu)."""
+def test_uniaxial_closed_form_values():
+    """Numbers of the closed form at the cube workload's moduli (mu 1034.4828, kappa 1e4, eta 2 mu)."""
     S, _ = oracle.stress(MAT, np.diag([1.1, 1, 1]), [1, 0, 0], T0)
     assert S[0, 0] == pytest.approx(1372.2166, abs=1e-3)
     assert S[1, 1] == pytest.approx(819.8090, abs=1e-3)
@@ -227,7 +227,7 @@ def test_pennes_0d_closed_form():
 
 
 def test_pennes_no_perfusion_rise():
-    """No perfusion: per-step rise exactly Q dt / (rho c) (C1: 5e7 W/m^3 -> 7.089e-3 K/step at 5.104e-4 s)."""
+    """No perfusion: per-step rise exactly Q dt / (rho c) (the 0.04 m cube: 5e7 W/m^3 -> 7.089e-3 K/step at 5.104e-4 s)."""
     X, conn = _box("h8", 2, 0.01)
     p = dict(MAT, alpha=0.0, alpha_m=0.0, wbcb=0.0)
     dt = 5.104e-4
@@ -255,8 +255,8 @@ def test_prony_step_relaxation(g, tau):
             assert np.allclose(f, ratio * f_el, rtol=1e-10, atol=1e-14 * np.abs(f_el).max())
     if len(g) == 1:
         cd = math.sqrt((MAT["kappa"] + 4 * MAT["mu"] / 3 + 4 * MAT["eta"]) / MAT["rho"])
-        dt_c1 = 0.8 * (0.004 / math.sqrt(2)) / cd       # C1 step, 5.1038e-4 s
-        b = 0.5 / (dt_c1 + 0.5)
+        dt_cube = 0.8 * (0.004 / math.sqrt(2)) / cd       # the 0.04 m cube's step, 5.1038e-4 s
+        b = 0.5 / (dt_cube + 0.5)
         assert b ** 1000 == pytest.approx(0.360506, abs=2e-6)
         assert 1 - 0.5 * (1 - b ** 1000) == pytest.approx(0.680253, abs=2e-6)
         # dt -> 0 limit is the generalised Maxwell relaxation exp(-t / tau)
@@ -405,7 +405,7 @@ def test_mass_invariants(kind, npe):
 
 
 def test_c1_critical_step():
-    """C1 cube: 0.8 * min L_e / c_d = 5.104e-4 s (Kuhn tet L = 3 V / A_max = h / sqrt 2)."""
+    """6000-tet cube (h = 4 mm): 0.8 * min L_e / c_d = 5.104e-4 s (Kuhn tet L = 3 V / A_max = h / sqrt 2)."""
     p = W.cube_t4()
     s = oracle.OracleSim(4, p.X, p.conn, p.params, dt=1e-4)
     cd = math.sqrt((MAT["kappa"] + 4 * MAT["mu"] / 3 + 4 * MAT["eta"]) / MAT["rho"])
