@@ -382,7 +382,7 @@ tled_status upload_all(tled_sim *s) {
         uint16_t *u16;
         TRY(upload(s, &u16, P.lconn)); a.lconn = u16;
         TRY(upload(s, &u16, P.lrow)); a.lrow = u16;
-        TRY(upload(s, &u16, P.lslot)); a.lslot = u16;
+        TRY(upload(s, &u16, P.lpos)); a.lpos = u16;
         a.nu4 = dnu4; a.nv4 = dnv4; a.nth = dnth; a.mask = dmask; a.Vl = dVl; a.theta = dtheta;
         a.g0 = cg0; a.g1 = cg1; a.g2 = cg2; a.hg0 = chg0; a.hg1 = chg1; a.hg2 = chg2; a.khg = ckhg;
         float4 *dpart;

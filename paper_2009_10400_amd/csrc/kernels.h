@@ -57,7 +57,7 @@ struct PatchArgs {
     int ne, n_patches, max_nodes, max_elems, slot_stride;
     int n_interior, n_shared;
     const int *elem_begin, *int_begin, *shared_begin, *shared_ids;
-    const uint16_t *lconn, *lrow, *lslot;
+    const uint16_t *lconn, *lrow, *lpos;
     const int *lrow_begin;
     const int *srow, *ppos;
     const float *lX;            // per-patch local reference coordinates (x, y, z)

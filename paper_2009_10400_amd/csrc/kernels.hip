@@ -524,7 +524,8 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
 
 // One workgroup of BS threads per patch.  LDS: local node state and reference
 // coordinates (float4 each per local node) and the element-slot outputs
-// (float4 per element slot).  GEOX: element geometry rebuilt from the staged
+// (float4 per element slot, grouped by local node: each element writes its
+// slots at their precomputed positions, and each node sums its contiguous run).  GEOX: element geometry rebuilt from the staged
 // coordinates (else read from the precomputed planes).
 template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH>
 __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
@@ -590,9 +591,9 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     for (int e = e0 + threadIdx.x; e < e1; e += BS) {
         float th[6 * NP + 1];
         load_theta(A.theta, A.ne, e, NP, th);
-        const int el = e - e0;
         if (NPE == 4) {
             const ushort4 c = reinterpret_cast<const ushort4 *>(A.lconn)[e];
+            const ushort4 ps = reinterpret_cast<const ushort4 *>(A.lpos)[e];   // independent of c
             float4 u[4] = {lnode[c.x], lnode[c.y], lnode[c.z], lnode[c.w]};
             GeoT4 g;
             if (GEOX) {
@@ -603,14 +604,18 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             }
             ElemResultT4 r;
             t4_compute<NP, MON>(m, u, g, th, r);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) lout[k * A.slot_stride + el] = r.o[k];
+            lout[ps.x] = r.o[0];
+            lout[ps.y] = r.o[1];
+            lout[ps.z] = r.o[2];
+            lout[ps.w] = r.o[3];
             psi += r.psiV;
             nf |= r.nonfinite;
             inv |= r.inverted;
         } else {
             const ushort4 ca = reinterpret_cast<const ushort4 *>(A.lconn)[2 * e];
             const ushort4 cb = reinterpret_cast<const ushort4 *>(A.lconn)[2 * e + 1];
+            const ushort4 pa = reinterpret_cast<const ushort4 *>(A.lpos)[2 * e];
+            const ushort4 pb = reinterpret_cast<const ushort4 *>(A.lpos)[2 * e + 1];
             float4 u[8] = {lnode[ca.x], lnode[ca.y], lnode[ca.z], lnode[ca.w],
                            lnode[cb.x], lnode[cb.y], lnode[cb.z], lnode[cb.w]};
             GeoH8 g;
@@ -623,8 +628,14 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             }
             ElemResultH8 r;
             h8_compute<NP, MON>(m, u, g, th, r);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) lout[k * A.slot_stride + el] = r.o[k];
+            lout[pa.x] = r.o[0];
+            lout[pa.y] = r.o[1];
+            lout[pa.z] = r.o[2];
+            lout[pa.w] = r.o[3];
+            lout[pb.x] = r.o[4];
+            lout[pb.y] = r.o[5];
+            lout[pb.z] = r.o[6];
+            lout[pb.w] = r.o[7];
             psi += r.psiV;
             nf |= r.nonfinite;
             inv |= r.inverted;
@@ -635,7 +646,6 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     // assemble local nodes in a fixed order
     const float src = source_switch(p, A.step_base, j);
     const uint16_t *lrow = A.lrow + A.lrow_begin[pid];
-    const uint16_t *lslot = A.lslot + size_t(e0) * NPE;
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
     for (int l = threadIdx.x; l < nloc; l += BS) {
         const bool interior = l < nint;
@@ -648,21 +658,12 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             mk = A.mask[a];
         }
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        // the node's slots are the contiguous LDS positions k0 .. k1 (element
+        // order): summed in that order, with no global index loads
         const int k0 = lrow[l], k1 = lrow[l + 1];
-        // slot indices in groups of eight independent global loads, so their
-        // latency is paid once per group (a T4 node has about five slots in a
-        // patch); sums in slot order
-        for (int k = k0; k < k1; k += 8) {
-            int sl[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sl[q] = (k + q < k1) ? int(lslot[k + q]) : -1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (sl[q] >= 0) {
-                    const float4 o = lout[sl[q]];
-                    acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
-                }
-            }
+        for (int k = k0; k < k1; ++k) {
+            const float4 o = lout[k];
+            acc.x += o.x; acc.y += o.y; acc.z += o.z; acc.w += o.w;
         }
         if (interior) {
             NodeNew r = node_advance(p, lnode[l], v0, th, mk, acc, src);

@@ -425,8 +425,7 @@ void build_patches(Precomputed *pc, int patch_elems, const std::vector<double> &
     P.lconn.resize(size_t(ne) * npe);
     P.lrow_begin.assign(P.n + 1, 0);
     P.lrow.clear();
-    P.lslot.resize(size_t(ne) * npe);
-    P.lslot_begin.assign(P.n + 1, 0);
+    P.lpos.resize(size_t(ne) * npe);
     P.max_nodes = 0;
     P.max_elems = 0;
     P.slot_stride = int32_t(std::min<int64_t>(patch_elems, ne));
@@ -475,19 +474,17 @@ void build_patches(Precomputed *pc, int patch_elems, const std::vector<double> &
         for (int32_t l = 0; l < nloc; ++l) cnt[l + 1] += cnt[l];
         P.lrow_begin[p] = int32_t(P.lrow.size());
         for (int32_t l = 0; l <= nloc; ++l) P.lrow.push_back(uint16_t(cnt[l]));
-        P.lslot_begin[p] = e0 * npe;
         std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
         for (int32_t e = e0; e < e1; ++e)
             for (int a = 0; a < npe; ++a) {
                 int32_t l = P.lconn[size_t(npe) * e + a];
-                P.lslot[size_t(e0) * npe + fill[l]++] = uint16_t(a * P.slot_stride + (e - e0));
+                P.lpos[size_t(npe) * e + a] = uint16_t(fill[l]++);
             }
         for (int32_t n = ib; n < ie; ++n) local[n] = -1;
         for (int32_t n : touched) local[n] = -1;
     }
     P.shared_begin[P.n] = int32_t(P.shared_ids.size());
     P.lrow_begin[P.n] = int32_t(P.lrow.size());
-    P.lslot_begin[P.n] = int32_t(ne * npe);
     const int64_t nsh = nn - P.n_interior;
     P.lx_begin[P.n] = int32_t(P.lX.size() / 3);
     P.srow.assign(nsh + 1, 0);
@@ -784,11 +781,10 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
     P.shared_begin.resize(T.patch + 1);
     P.lrow_begin.resize(T.patch + 1);
     P.lx_begin.resize(T.patch + 1);
-    P.lslot_begin.resize(T.patch + 1);
     P.shared_ids.resize(T.sid);
     P.lconn.resize(T.lconn);
     P.lrow.resize(T.lrow);
-    P.lslot.resize(size_t(NE) * npe);
+    P.lpos.resize(size_t(NE) * npe);
     P.srow.resize(T.s + 1);
     P.ppos.resize(T.ppos);
     P.lX.resize(size_t(T.lx) * 3);
@@ -835,16 +831,12 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
                 P.shared_begin[g] = sid0 + Q.shared_begin[q];
                 P.lrow_begin[g] = lr0 + Q.lrow_begin[q];
                 P.lx_begin[g] = lx0 + Q.lx_begin[q];
-                P.lslot_begin[g] = int32_t((eo + Q.elem_begin[q]) * npe);
                 (*patch_scen)[g] = int32_t(k);
             }
             for (size_t q = 0; q < Q.shared_ids.size(); ++q) P.shared_ids[sid0 + q] = int32_t(map(Q.shared_ids[q]));
             std::copy(Q.lconn.begin(), Q.lconn.end(), P.lconn.begin() + o.lconn);
             std::copy(Q.lrow.begin(), Q.lrow.end(), P.lrow.begin() + o.lrow);
-            for (size_t q = 0; q < Q.lslot.size(); ++q) {
-                const int a = Q.lslot[q] / Q.slot_stride, el = Q.lslot[q] % Q.slot_stride;
-                P.lslot[size_t(eo) * npe + q] = uint16_t(a * stride + el);
-            }
+            std::copy(Q.lpos.begin(), Q.lpos.end(), P.lpos.begin() + size_t(eo) * npe);   // patch-local
             for (int64_t j = 0; j < nsh; ++j) P.srow[so_ + j] = sid0 + Q.srow[j];
             for (size_t q = 0; q < Q.ppos.size(); ++q) P.ppos[o.ppos + q] = sid0 + Q.ppos[q];
             std::copy(Q.lX.begin(), Q.lX.end(), P.lX.begin() + 3 * o.lx);
@@ -859,7 +851,6 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
     P.shared_begin[T.patch] = int32_t(T.sid);
     P.lrow_begin[T.patch] = int32_t(T.lrow);
     P.lx_begin[T.patch] = int32_t(T.lx);
-    P.lslot_begin[T.patch] = int32_t(NE * npe);
     P.srow[T.s] = int32_t(T.sid);
     if (P.max_elems * npe > 65535 || P.slot_stride * npe > 65535) { *err = "patch too large"; return TLED_E_ARG; }
     U.dt_cr = 0.0;

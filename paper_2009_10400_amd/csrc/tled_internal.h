@@ -42,13 +42,14 @@ struct Patches {
     std::vector<int32_t> shared_begin;     // n + 1 (into shared_ids)
     std::vector<int32_t> shared_ids;       // internal node ids of shared nodes per patch
     std::vector<uint16_t> lconn;           // ne * npe local node indices
-    // local gather lists: for local node l of patch p, its incident element
-    // slots (e_local * npe + s) are lslot[lrow[off+l] .. lrow[off+l+1]).
+    // node-major element outputs: the patch's npe * n_elems element slots are
+    // stored in LDS grouped by local node, local node l owning positions
+    // lrow[off+l] .. lrow[off+l+1] (its slots in element order, then vertex
+    // order); lpos[e * npe + a] is the position of element e's vertex a.
     std::vector<int32_t> lrow_begin;       // n + 1 offsets into lrow (each patch has nloc+1 entries)
-    std::vector<uint16_t> lrow;            // row pointers, local to the patch slot list
-    std::vector<uint16_t> lslot;           // ne * npe entries (slot s * slot_stride + e_local), sorted per local node
-    int32_t slot_stride = 0;               // element stride of the slot-major LDS output array
-    std::vector<int32_t> lslot_begin;      // n + 1 offsets into lslot (= elem_begin * npe)
+    std::vector<uint16_t> lrow;            // row pointers, local to the patch
+    std::vector<uint16_t> lpos;            // ne * npe positions, local to the patch
+    int32_t slot_stride = 0;               // elements of the largest patch (sizes the LDS output array)
     // shared-node assembly: the partial of (patch p, local shared index j) is
     // written to partial slot ppos[shared_begin[p] + j]; slots are sorted by
     // node, then patch, so node n_interior + s sums the contiguous slots
