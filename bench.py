@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--workload", default="ellipsoid_t4", choices=["ellipsoid_t4", "cube_h8"],
                     help="ellipsoid_t4: ~1.0M-tet noisy ellipsoid (default); cube_h8: 64^3 H8 cube")
     ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed regions of --steps steps (the first gives value; all are reported with their median)")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", type=int, default=0, metavar="N",
@@ -497,6 +499,15 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     value = p.ne * args.steps / el
     log(f"[bench] timed {args.steps} steps in {el:.3f}s -> {value:.4g} element-updates/s")
+    reps = [ms_per_step]
+    for _ in range(max(0, args.repeats - 1)):      # the same K steps again, each timed alone
+        t1 = time.perf_counter()
+        sim.step(args.steps)
+        torch.cuda.synchronize()
+        reps.append(1e3 * (time.perf_counter() - t1) / args.steps)
+    sim.sync()
+    med = float(np.median(reps))
+    log(f"[bench] repeats (ms/step): {[round(r, 5) for r in reps]}, median {med:.5f}")
 
     # dominant kernel, timed with HIP events on the library's stream
     kt = sim.kernel_times(args.kernel_steps)
@@ -547,6 +558,7 @@ def main():
                    "dt": sim.dt},
         "roofline": roof,
         "step_hbm": step_hbm,
+        "repeats": {"ms_per_step": reps, "median_ms_per_step": med, "median_value": p.ne / (med * 1e-3)},
     }
     if not args.no_cpu_baseline and p.npe == 4:
         steps = args.cpu_steps or max(3, int(40e6 / p.ne))
