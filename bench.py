@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--reorder", type=int, default=0,
                     help="element order: 0/1 Morton with bisection patches, 2 Morton runs, -1 as generated")
     ap.add_argument("--elems", type=int, default=1_000_000)
-    ap.add_argument("--workload", default="ellipsoid_t4", choices=["ellipsoid_t4", "cube_h8"],
-                    help="ellipsoid_t4: ~1.0M-tet noisy ellipsoid (default); cube_h8: 64^3 H8 cube")
+    ap.add_argument("--workload", default="ellipsoid_t4", choices=["ellipsoid_t4", "cube_h8", "cube_t4"],
+                    help="ellipsoid_t4: ~1.0M-tet noisy ellipsoid (default); cube_h8: 64^3 H8 cube; "
+                         "cube_t4: the 6000-tet parity cube (cache-resident, launch-bound)")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--repeats", type=int, default=5,
                     help="timed regions of --steps steps (the first gives value; all are reported with their median)")
@@ -478,7 +479,8 @@ def main():
     from paper_2009_10400_amd import tled, workloads as W
 
     t = time.time()
-    p = W.ellipsoid_t4(args.elems) if args.workload == "ellipsoid_t4" else W.cube_h8(64)
+    p = {"ellipsoid_t4": lambda: W.ellipsoid_t4(args.elems), "cube_h8": lambda: W.cube_h8(64),
+         "cube_t4": lambda: W.cube_t4()}[args.workload]()
     log(f"[bench] workload ne={p.ne} nn={p.nn} built in {time.time() - t:.1f}s")
     t = time.time()
     stream = torch.cuda.Stream(device=0)
@@ -545,11 +547,13 @@ def main():
         "value": value, "unit": "element-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": (f"noisy ellipsoid 0.2x0.15x0.1 m, {p.ne} T4 / {p.nn} nodes, 2 Prony terms, "
-                                f"shrinkage above 323 K, 20 mm 1/r^4 line source (10 W), random numbering"
-                                if p.npe == 4 else
-                                f"0.1 m cube, {p.ne} H8 (64^3, one-point + hourglass) / {p.nn} nodes, "
-                                f"fibre field, mu(T), 1/r^2 point source (10 W)"),
+        "config": {"workload": {
+                       "ellipsoid_t4": f"noisy ellipsoid 0.2x0.15x0.1 m, {p.ne} T4 / {p.nn} nodes, 2 Prony terms, "
+                                       f"shrinkage above 323 K, 20 mm 1/r^4 line source (10 W), random numbering",
+                       "cube_h8": f"0.1 m cube, {p.ne} H8 (64^3, one-point + hourglass) / {p.nn} nodes, "
+                                  f"fibre field, mu(T), 1/r^2 point source (10 W)",
+                       "cube_t4": f"0.04 m cube, {p.ne} T4 / {p.nn} nodes, 1 Prony term, Gaussian source "
+                                  f"(5e7 W/m^3, sigma 4 mm)"}[args.workload],
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
                    "graph_steps": args.graph_steps or 50, "patches": info["n_patches"],
                    "shared_nodes": info["n_shared_nodes"], "patch_lds_bytes": info["patch_lds_bytes"],
