@@ -349,3 +349,58 @@ def test_single_setup_is_independent_of_host_threads(monkeypatch):
         out.append(str(e.value))
     assert out[0] == out[2] and out[1] == out[3]
     assert "element 40000 " in out[1]
+
+
+def _spread3(q):
+    q = q.astype(np.uint64) & np.uint64(0x1FFFFF)
+    for sh, m in ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF), (8, 0x100F00F00F00F00F),
+                  (4, 0x10C30C30C30C30C3), (2, 0x1249249249249249)):
+        q = (q | (q << np.uint64(sh))) & np.uint64(m)
+    return q
+
+
+def _bisection_patches(X, conn, P):
+    """Recursive coordinate bisection written independently of the library: Morton keys of the
+    element centroids over the bounding cube; a set of M > P elements (q = ceil(M/P) patches) is
+    cut across the longest centroid extent into floor(q/2) P elements and the rest (ties by
+    element number, equal extents to the lower axis); leaves in (key, element) order.  Only sets
+    matter, so full sorts give the same patches as partial ones."""
+    ne, npe = conn.shape
+    c = X[conn[:, 0]].copy()
+    for a in range(1, npe):
+        c += X[conn[:, a]]
+    c /= npe
+    lo, span = X.min(0), max((X.max(0) - X.min(0)).max(), 1e-300)
+    t = np.clip((c - lo) / span * 2097151.0, 0.0, 2097151.0).astype(np.uint64)
+    key = _spread3(t[:, 0]) | (_spread3(t[:, 1]) << np.uint64(1)) | (_spread3(t[:, 2]) << np.uint64(2))
+    order = np.arange(ne)
+    todo = [(0, ne)]
+    while todo:
+        a, b = todo.pop()
+        sub = order[a:b]
+        if b - a <= P:
+            order[a:b] = sub[np.lexsort((sub, key[sub]))]
+            continue
+        ext = c[sub].max(0) - c[sub].min(0)
+        ax = 0
+        for i in (1, 2):
+            if ext[i] > ext[ax] * (1.0 + 1e-9):
+                ax = i
+        order[a:b] = sub[np.lexsort((sub, c[sub, ax]))]
+        left = (-(-(b - a) // P) // 2) * P
+        todo += [(a + left, b), (a, a + left)]
+    pid = np.empty(ne, np.int64)
+    pid[order] = np.arange(ne) // P
+    pairs = np.unique(np.stack([np.repeat(pid, npe), conn.reshape(-1)], 1), axis=0)
+    touched = np.bincount(pairs[:, 1], minlength=len(X))
+    return int((touched > 1).sum()), int(np.bincount(pairs[:, 0]).max())
+
+
+@pytest.mark.parametrize("n, P", [(30_000, 448), (30_000, 128), (100_000, 496)])
+def test_bisection_patches_match_an_independent_implementation(n, P):
+    p = W.ellipsoid_t4(n)
+    n_shared, max_nodes = _bisection_patches(np.asarray(p.X, np.float64), np.asarray(p.conn), P)
+    info = host_sim(p, patch_elems=P).info()
+    assert info["n_patches"] == -(-p.ne // P)
+    assert info["n_shared_nodes"] == n_shared
+    assert info["patch_max_nodes"] == max_nodes
