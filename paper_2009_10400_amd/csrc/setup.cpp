@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 #include "tled_internal.h"
@@ -173,16 +174,42 @@ tled_status check_inputs(const HostProblem &p, std::string *err) {
 
 // Elements in caller order with repaired orientation; geometry per element.
 // f(lo, hi) over [0, n) cut into `threads` contiguous ranges, one host thread
-// each (the calling thread takes the first).  Callers only write disjoint
-// ranges, so the result does not depend on the thread count.
+// each (the calling thread takes the first, and any range whose thread could
+// not be started).  Callers only write disjoint ranges, so the result does not
+// depend on the thread count.
 template <class F>
 void parallel_ranges(int64_t n, int threads, F f) {
     const int t = int(std::max<int64_t>(1, std::min<int64_t>(threads, n / 4096)));
     if (t <= 1) { f(int64_t(0), n); return; }
     std::vector<std::thread> pool;
-    for (int i = 1; i < t; ++i) pool.emplace_back([&, i] { f(n * i / t, n * (i + 1) / t); });
+    int started = 1;
+    for (; started < t; ++started) {
+        try {
+            const int i = started;
+            pool.emplace_back([&, i] { f(n * i / t, n * (i + 1) / t); });
+        } catch (const std::system_error &) {
+            break;
+        }
+    }
+    for (int i = started; i < t; ++i) f(n * i / t, n * (i + 1) / t);
     f(int64_t(0), n / t);
     for (auto &th : pool) th.join();
+}
+
+// Starts up to `extra` host threads running `work` (which takes its items from
+// a shared counter, so the calling thread finishes whatever they do not);
+// stops at the first thread that cannot be started.
+template <class F>
+std::vector<std::thread> start_workers(int extra, F &work) {
+    std::vector<std::thread> pool;
+    for (int t = 0; t < extra; ++t) {
+        try {
+            pool.emplace_back(work);
+        } catch (const std::system_error &) {
+            break;
+        }
+    }
+    return pool;
 }
 
 tled_status element_pass(const HostProblem &p, std::vector<int32_t> *conn, std::vector<ElemGeo> *geo,
@@ -341,8 +368,15 @@ std::vector<int64_t> bisection_order(const HostProblem &p, const std::vector<int
         std::nth_element(first, first + left, last, [ax](const Item &a, const Item &b) {
             return a.c[ax] != b.c[ax] ? a.c[ax] < b.c[ax] : a.e < b.e;
         });
+        std::thread th;
         if (par > 1 && M > 8192) {
-            std::thread th(split, lo, lo + left, par / 2);
+            try {
+                th = std::thread(split, lo, lo + left, par / 2);
+            } catch (const std::system_error &) {
+                // no thread: both halves on this one
+            }
+        }
+        if (th.joinable()) {
             split(lo + left, hi, par - par / 2);
             th.join();
         } else {
@@ -701,8 +735,7 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
         }
     };
     const int nt = std::max(1, std::min(host_threads(), int(S)));
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    std::vector<std::thread> pool = start_workers(nt - 1, work);
     work();
     for (auto &th : pool) th.join();
     for (size_t k = 0; k < S; ++k)
@@ -842,8 +875,7 @@ tled_status precompute_batch(const std::vector<HostProblem> &ps, const std::vect
             std::copy(Q.lX.begin(), Q.lX.end(), P.lX.begin() + 3 * o.lx);
         }
     };
-    pool.clear();
-    for (int t = 1; t < nt; ++t) pool.emplace_back(fill);
+    pool = start_workers(nt - 1, fill);
     fill();
     for (auto &th : pool) th.join();
     P.elem_begin[T.patch] = int32_t(NE);
