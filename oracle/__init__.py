@@ -11,6 +11,7 @@ names of :class:`Material`; missing keys default to zero (flags off).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -76,32 +77,60 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_int64, dp, ctypes.c_int64,
-                                 ctypes.POINTER(ctypes.c_int32), dp, dp, ctypes.POINTER(ctypes.c_uint8), dp,
-                                 ctypes.POINTER(Material), ctypes.c_double, ctypes.c_double,
-                                 ctypes.c_double, ctypes.c_double]
-        L.orc_create.restype = ctypes.c_int
-        L.orc_destroy.argtypes = [P]
-        L.orc_critical_dt.argtypes = [P]
-        L.orc_critical_dt.restype = ctypes.c_double
-        L.orc_n_swapped.argtypes = [P]
-        L.orc_n_swapped.restype = ctypes.c_int64
-        L.orc_lumped.argtypes = [P, dp, dp, dp, dp, dp]
-        L.orc_geometry.argtypes = [P, ctypes.POINTER(ctypes.c_int32), dp, dp]
-        L.orc_run.argtypes = [P, ctypes.c_int64, ctypes.c_int64, dp, dp, dp, dp, dp]
-        L.orc_run.restype = ctypes.c_int
-        L.orc_loads.argtypes = [P, dp, dp, dp, dp]
-        L.orc_loads.restype = ctypes.c_int
-        L.orc_stress.argtypes = [ctypes.POINTER(Material), dp, dp, ctypes.c_double, dp, dp]
-        L.orc_stress.restype = ctypes.c_double
-        L.orc_element.argtypes = [ctypes.POINTER(Material), ctypes.c_int32, dp, dp, dp, dp, dp,
-                                  ctypes.c_double, dp, dp, dp]
-        L.orc_element.restype = ctypes.c_int
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def _load(path: str):
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_int64, dp, ctypes.c_int64,
+                             ctypes.POINTER(ctypes.c_int32), dp, dp, ctypes.POINTER(ctypes.c_uint8), dp,
+                             ctypes.POINTER(Material), ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double]
+    L.orc_create.restype = ctypes.c_int
+    L.orc_destroy.argtypes = [P]
+    L.orc_critical_dt.argtypes = [P]
+    L.orc_critical_dt.restype = ctypes.c_double
+    L.orc_n_swapped.argtypes = [P]
+    L.orc_n_swapped.restype = ctypes.c_int64
+    L.orc_lumped.argtypes = [P, dp, dp, dp, dp, dp]
+    L.orc_geometry.argtypes = [P, ctypes.POINTER(ctypes.c_int32), dp, dp]
+    L.orc_run.argtypes = [P, ctypes.c_int64, ctypes.c_int64, dp, dp, dp, dp, dp]
+    L.orc_run.restype = ctypes.c_int
+    L.orc_loads.argtypes = [P, dp, dp, dp, dp]
+    L.orc_loads.restype = ctypes.c_int
+    L.orc_stress.argtypes = [ctypes.POINTER(Material), dp, dp, ctypes.c_double, dp, dp]
+    L.orc_stress.restype = ctypes.c_double
+    L.orc_element.argtypes = [ctypes.POINTER(Material), ctypes.c_int32, dp, dp, dp, dp, dp,
+                              ctypes.c_double, dp, dp, dp]
+    L.orc_element.restype = ctypes.c_int
+    return L
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every oracle call through another build of the oracle source for the
+    duration of the block (the tests use it to show that the pins catch planted
+    mistakes in a copy of the oracle)."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def build_variant(src_text: str, out_dir: str, name: str) -> str:
+    """Compile oracle source text (e.g. a copy with one planted mistake) into out_dir."""
+    src = os.path.join(out_dir, name + ".c")
+    so = os.path.join(out_dir, name + ".so")
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", so, src, "-lm"])
+    return so
 
 
 def _dp(a):
@@ -158,8 +187,9 @@ class OracleSim:
         q = _f64(q)
         fix = None if fix is None else np.ascontiguousarray(fix, dtype=np.uint8)
         Tfix = _f64(Tfix)
+        self._L = lib()
         h = ctypes.c_void_p()
-        rc = lib().orc_create(ctypes.byref(h), self.npe, self.nn, _dp(self.X), self.ne,
+        rc = self._L.orc_create(ctypes.byref(h), self.npe, self.nn, _dp(self.X), self.ne,
                               self.conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(a0), _dp(q),
                               fix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if fix is not None else None,
                               _dp(Tfix), ctypes.byref(self._m), float(t_on), float(t_off),
@@ -172,27 +202,27 @@ class OracleSim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().orc_destroy(h)
+            self._L.orc_destroy(h)
             self._h = None
 
     @property
     def critical_dt(self) -> float:
-        return lib().orc_critical_dt(self._h)
+        return self._L.orc_critical_dt(self._h)
 
     @property
     def n_swapped(self) -> int:
-        return lib().orc_n_swapped(self._h)
+        return self._L.orc_n_swapped(self._h)
 
     def lumped(self):
         out = {k: np.zeros(self.nn) for k in ("Vl", "M", "Kb", "Qm", "Qr")}
-        lib().orc_lumped(self._h, *(_dp(out[k]) for k in ("Vl", "M", "Kb", "Qm", "Qr")))
+        self._L.orc_lumped(self._h, *(_dp(out[k]) for k in ("Vl", "M", "Kb", "Qm", "Qr")))
         return out
 
     def geometry(self):
         conn = np.zeros((self.ne, self.npe), dtype=np.int32)
         dhdx = np.zeros((self.ne, self.npe, 3))
         V0 = np.zeros(self.ne)
-        lib().orc_geometry(self._h, conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(dhdx), _dp(V0))
+        self._L.orc_geometry(self._h, conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(dhdx), _dp(V0))
         return conn, dhdx, V0
 
     def initial_state(self, T0: float):
@@ -207,7 +237,7 @@ class OracleSim:
         for k in ("u", "u_prev", "T", "theta"):
             state[k] = _f64(state[k])
         mon = np.zeros((nsteps, 6)) if monitors else None
-        rc = lib().orc_run(self._h, int(nsteps), int(state["step"]), _dp(state["u"]), _dp(state["u_prev"]),
+        rc = self._L.orc_run(self._h, int(nsteps), int(state["step"]), _dp(state["u"]), _dp(state["u_prev"]),
                            _dp(state["T"]), _dp(state["theta"]) if state["theta"].size else
                            _dp(np.zeros(1)), _dp(mon))
         if rc != 0:
@@ -219,5 +249,5 @@ class OracleSim:
         """Internal forces (nn x 3) and conduction loads (nn) for a state, without a Prony update."""
         F = np.zeros((self.nn, 3))
         H = np.zeros(self.nn)
-        lib().orc_loads(self._h, _dp(_f64(u)), _dp(_f64(T)), _dp(F), _dp(H))
+        self._L.orc_loads(self._h, _dp(_f64(u)), _dp(_f64(T)), _dp(F), _dp(H))
         return F, H

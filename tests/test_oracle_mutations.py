@@ -1,0 +1,114 @@
+"""The pins catch plausible mistakes in the oracle's laws.
+
+Each case plants one mistake in a copy of the oracle's C source (a flipped sign,
+a wrong end point or ramp width, the wrong modulus scaled, swapped directions,
+a dropped term), compiles the copy with gcc into a temporary directory, routes
+the oracle binding through it, and checks that every pin named for the case now
+fails.  A control build of the unmodified source passes the same pins, so a
+failure is the planted mistake's doing and not the harness's.  Everything runs
+on the CPU; the committed oracle is never modified.
+"""
+import os
+
+import pytest
+
+import oracle
+import test_oracle_law_pins as P
+import test_oracle_pins as Q
+
+MUTATIONS = [
+    # (id, text in tled_oracle.c, planted replacement, pins that must fail)
+    ("muT_drop_sign",
+     "return 1.0 - m->muT_drop * clamp01(", "return 1.0 + m->muT_drop * clamp01(",
+     [lambda: P.test_mu_of_T_uniaxial(340.0, 1.1), P.test_mu_of_T_values]),
+    ("muT_scales_kappa",
+     "eta = m->eta * s, kappa = m->kappa;", "eta = m->eta * s, kappa = m->kappa * s;",
+     [lambda: P.test_mu_of_T_uniaxial(340.0, 1.1), P.test_mu_of_T_with_expansion]),
+    ("muT_eta_unscaled",
+     "eta = m->eta * s, kappa", "eta = m->eta, kappa",
+     [lambda: P.test_mu_of_T_uniaxial(340.0, 1.1)]),
+    ("muT_ramp_width",
+     "clamp01((T - m->muT_lo) / (m->muT_hi - m->muT_lo))",
+     "clamp01(2.0 * (T - m->muT_lo) / (m->muT_hi - m->muT_lo))",
+     [lambda: P.test_mu_of_T_uniaxial(325.0, 0.9), P.test_mu_of_T_values]),
+    ("shrink_sign",
+     "double s = 1.0 + m->shrink_eps * clamp01(", "double s = 1.0 - m->shrink_eps * clamp01(",
+     [lambda: P.test_shrinkage_free_expansion(4, 330.0), lambda: P.test_shrinkage_clamped_heating(340.0, 1559.6815)]),
+    ("shrink_width",
+     "(Te - m->shrink_T) / m->shrink_width", "(Te - m->shrink_T) / (2.0 * m->shrink_width)",
+     [lambda: P.test_shrinkage_free_expansion(8, 325.5), lambda: P.test_shrinkage_clamped_heating(325.5, 739.5914)]),
+    ("shrink_onset",
+     "(Te - m->shrink_T) / m->shrink_width", "(Te - m->shrink_T + 2.0) / m->shrink_width",
+     [lambda: P.test_shrinkage_clamped_heating(325.5, 739.5914), lambda: P.test_shrinkage_free_expansion(4, 325.5)]),
+    ("ti_expansion_swapped_axes",
+     "Fth[i] = li * I3[i] + (lm - li) * A0[i];", "Fth[i] = lm * I3[i] + (li - lm) * A0[i];",
+     [lambda: P.test_ti_expansion_free(4, 0), lambda: P.test_ti_expansion_clamped_heating(10.0)]),
+    ("ti_expansion_fibre_ignored",
+     "double b = (m->expan_mode == 1) ? 1.0 + m->alpha_m * dT : a;", "double b = a;",
+     [lambda: P.test_ti_expansion_free(8, 1), lambda: P.test_ti_expansion_clamped_heating(30.0)]),
+    ("ti_conduction_swapped_k",
+     "D[3 * i + j] += (kmT - kT) *", "D[3 * i + j] += (kT - kmT) *",
+     [lambda: P.test_ti_conduction_patch("t4", 4, (1, 0, 0), "k_m", 1.0),
+      lambda: P.test_ti_conduction_oblique_first_moment("h8", 8, 0.3)]),
+    ("ti_conduction_transposed_fibre",
+     "(a[i] / an) * (a[j] / an);", "(a[i] / an) * (a[(j + 1) % 3] / an);",
+     [lambda: P.test_ti_conduction_oblique_first_moment("t4", 4, 1.1)]),
+    ("ct_reversed",
+     "return m->c + w * (m->c_hi - m->c);", "return m->c_hi + w * (m->c - m->c_hi);",
+     [lambda: P.test_ct_per_step_rise(336.65 + 10), lambda: P.test_ct_per_step_rise(380.0)]),
+    ("ct_evaluated_at_T0",
+     "double Ca = s->m.rho * heat_capacity(&s->m, T[a]) * s->Vl[a];",
+     "double Ca = s->m.rho * heat_capacity(&s->m, s->m.T0) * s->Vl[a];",
+     [lambda: P.test_ct_per_step_rise(350.0)]),
+    ("kt_wrong_normalisation",
+     "return (m->k + w * (m->k_hi - m->k)) / m->k;", "return (m->k + w * (m->k_hi - m->k)) / m->k_hi;",
+     [lambda: P.test_kt_patch(336.65, 1e-5), lambda: P.test_kt_patch(300.0, 1e-10)]),
+    ("metabolic_sign",
+     "+ s->Qm[a] + src * s->Qr[a]", "- s->Qm[a] + src * s->Qr[a]",
+     [lambda: P.test_pennes_0d_metabolic_arterial(309.0), P.test_pennes_metabolic_only_rise]),
+    ("arterial_is_T0",
+     "(T[a] - s->m.T_art)", "(T[a] - s->m.T0)",
+     [lambda: P.test_pennes_0d_metabolic_arterial(309.0)]),
+    # a few of the older pins, for the laws they pin
+    ("pullback_missing_det",
+     "for (int i = 0; i < 9; ++i) S0[i] = detFth * T2[i];", "for (int i = 0; i < 9; ++i) S0[i] = T2[i];",
+     [lambda: Q.test_uniaxial_with_thermal_pullback(40.0), Q.test_clamped_uniform_heating]),
+    ("conduction_sign",
+     "double Tnew = T[a] + dt / Ca * (-Hc[a]", "double Tnew = T[a] + dt / Ca * (Hc[a]",
+     [Q.test_transient_conduction_converges_to_linear_profile]),
+]
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(os.path.join(os.path.dirname(oracle.__file__), "tled_oracle.c")) as f:
+        return f.read()
+
+
+def _outcomes(checks):
+    out = []
+    for chk in checks:
+        try:
+            chk()
+        except AssertionError:
+            out.append(False)
+        else:
+            out.append(True)
+    return out
+
+
+def test_control_build_passes(source, tmp_path):
+    """The unmodified source, built the same way, passes every pin used below."""
+    so = oracle.build_variant(source, str(tmp_path), "control")
+    with oracle.using_library(so):
+        for _, _, _, checks in MUTATIONS:
+            assert all(_outcomes(checks))
+
+
+@pytest.mark.parametrize("name,old,new,checks", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(source, tmp_path, name, old, new, checks):
+    assert source.count(old) == 1, f"mutation site of {name} not found exactly once"
+    so = oracle.build_variant(source.replace(old, new), str(tmp_path), name)
+    with oracle.using_library(so):
+        passed = _outcomes(checks)
+    assert not any(passed), f"{name}: pins that did not catch it: {[i for i, p in enumerate(passed) if p]}"
