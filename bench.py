@@ -305,13 +305,33 @@ def sweep(args):
     t_setup = time.time() - t
     log(f"[sweep] set-up (add + finalize) {t_setup:.1f}s, steps {min(steps)}..{max(steps)}, info={b.batch_info()}")
     torch.cuda.synchronize()
+    # Batch steps are enqueued in chunks of about 20 s each, with a progress line per chunk (a
+    # full-length sweep runs for minutes).  A scenario that goes unstable is reported, not dropped.
     t0 = time.perf_counter()
-    b.run()
-    b.sync()
+    nmax, done, chunk, status = max(steps), 0, 2000, "ok"
+    try:
+        while done < nmax:
+            k = min(chunk, nmax - done)
+            t1 = time.perf_counter()
+            b.step(k)
+            b.sync()
+            done += k
+            dt_chunk = time.perf_counter() - t1
+            log(f"[sweep] {done}/{nmax} batch steps, {time.perf_counter() - t0:.1f}s")
+            chunk = int(max(100, min(4 * chunk, k * 20.0 / max(dt_chunk, 1e-3))))
+    except tled.TledError as e:
+        status = str(e)
+        log(f"[sweep] stopped at batch step {done}: {status}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    updates = sum(p.ne * n for p, n in zip(probs, steps))
-    tmax, vol = b.scenario_monitors(333.15)
+    updates = sum(p.ne * min(n, done) for p, n in zip(probs, steps))
+    tmax, vol, mon_status = b.scenario_monitors(333.15, strict=False)
+    unstable = [k for k in range(len(sc)) if not np.isfinite(tmax[k])]
+    per = [{"k": k, "kind": p.meta["kind"], "n_elems": int(p.ne), "n_nodes": int(p.nn),
+            "dt": b.scenario_steps(k)[0], "steps": int(steps[k]), "heating_s": float(dur),
+            "power_W": float(p.meta["power"]), "E_Pa": float(p.meta["E"]),
+            "T_max_K": float(tmax[k]), "ablated_volume_m3": float(vol[k]), "finite": bool(np.isfinite(tmax[k]))}
+           for k, ((p, dur), _) in enumerate(zip(sc, steps))]
     out = {
         "metric": "scenarios/s (batched planning sweep, solver)", "value": len(sc) / el, "unit": "scenarios/s",
         "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -323,8 +343,10 @@ def sweep(args):
                    "launch": (f"hipGraph chunks of {args.graph_steps}" if args.graph_steps > 0 else
                               "eager steps, each launching only the scenarios still running")},
         "autotune_report": {str(k): v for k, v in report.items()},
-        "ablated_volume_m3": {"min": float(vol.min()), "max": float(vol.max())},
-        "T_max_K": {"min": float(tmax.min()), "max": float(tmax.max())},
+        "status": status, "batch_steps_done": done, "unstable_scenarios": unstable,
+        "ablated_volume_m3": {"min": float(np.nanmin(vol)), "max": float(np.nanmax(vol))},
+        "T_max_K": {"min": float(np.nanmin(tmax)), "max": float(np.nanmax(tmax))},
+        "scenarios": per,
     }
     print(json.dumps(out), flush=True)
 

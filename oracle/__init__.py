@@ -29,7 +29,7 @@ class Material(ctypes.Structure):
     _fields_ = [
         ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
         ("eta", ctypes.c_double), ("alpha", ctypes.c_double), ("alpha_m", ctypes.c_double),
-        ("T0", ctypes.c_double), ("k", ctypes.c_double), ("k_m", ctypes.c_double),
+        ("alpha_n", ctypes.c_double), ("T0", ctypes.c_double), ("k", ctypes.c_double), ("k_m", ctypes.c_double),
         ("c", ctypes.c_double), ("wbcb", ctypes.c_double), ("T_art", ctypes.c_double),
         ("Q_met", ctypes.c_double), ("g", ctypes.c_double * 4), ("tau", ctypes.c_double * 4),
         ("muT_lo", ctypes.c_double), ("muT_hi", ctypes.c_double), ("muT_drop", ctypes.c_double),
@@ -86,7 +86,7 @@ def _load(path: str):
     P = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
     L.orc_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_int64, dp, ctypes.c_int64,
-                             ctypes.POINTER(ctypes.c_int32), dp, dp, ctypes.POINTER(ctypes.c_uint8), dp,
+                             ctypes.POINTER(ctypes.c_int32), dp, dp, dp, dp, ctypes.POINTER(ctypes.c_uint8), dp,
                              ctypes.POINTER(Material), ctypes.c_double, ctypes.c_double,
                              ctypes.c_double, ctypes.c_double]
     L.orc_create.restype = ctypes.c_int
@@ -101,9 +101,9 @@ def _load(path: str):
     L.orc_run.restype = ctypes.c_int
     L.orc_loads.argtypes = [P, dp, dp, dp, dp]
     L.orc_loads.restype = ctypes.c_int
-    L.orc_stress.argtypes = [ctypes.POINTER(Material), dp, dp, ctypes.c_double, dp, dp]
+    L.orc_stress.argtypes = [ctypes.POINTER(Material), dp, dp, dp, ctypes.c_double, dp, dp]
     L.orc_stress.restype = ctypes.c_double
-    L.orc_element.argtypes = [ctypes.POINTER(Material), ctypes.c_int32, dp, dp, dp, dp, dp,
+    L.orc_element.argtypes = [ctypes.POINTER(Material), ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp,
                               ctypes.c_double, dp, dp, dp]
     L.orc_element.restype = ctypes.c_int
     return L
@@ -141,19 +141,23 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def stress(params: dict, F, a0, Te: float):
-    """Total pulled-back stress S0 (3x3) and energy density det(Fth) Psi."""
+def stress(params: dict, F, a0, Te: float, n0=None):
+    """Total pulled-back stress S0 (3x3) and energy density det(Fth) Psi.  n0: the second
+    thermal-expansion axis of the orthotropic mode (expan_mode 2)."""
     m = material(params)
     F = _f64(np.asarray(F).reshape(9))
     a0 = _f64(np.asarray(a0).reshape(3))
+    n0 = None if n0 is None else _f64(np.asarray(n0, dtype=np.float64).reshape(3))
     S = np.zeros(9)
     psi = np.zeros(1)
-    lib().orc_stress(ctypes.byref(m), _dp(F), _dp(a0), float(Te), _dp(S), _dp(psi))
+    lib().orc_stress(ctypes.byref(m), _dp(F), _dp(a0), _dp(n0), float(Te), _dp(S), _dp(psi))
     return S.reshape(3, 3), float(psi[0])
 
 
-def element(params: dict, Xe, ue, Te, a0=(1.0, 0.0, 0.0), theta=None, dt: float = 0.0):
-    """One element: nodal forces (npe x 3), conduction loads (npe), energy; theta updated in place."""
+def element(params: dict, Xe, ue, Te, a0=(1.0, 0.0, 0.0), theta=None, dt: float = 0.0, n0=None, D=None):
+    """One element: nodal forces (npe x 3), conduction loads (npe), energy; theta updated in place.
+    n0: second expansion axis (expan_mode 2); D: conductivity tensor, 3x3 or (xx yy zz xy yz xz)
+    (cond_mode 2)."""
     m = material(params)
     Xe = _f64(Xe)
     npe = Xe.shape[0]
@@ -163,18 +167,30 @@ def element(params: dict, Xe, ue, Te, a0=(1.0, 0.0, 0.0), theta=None, dt: float 
     f = np.zeros((npe, 3))
     h = np.zeros(npe)
     en = np.zeros(1)
-    rc = lib().orc_element(ctypes.byref(m), npe, _dp(Xe), _dp(ue), _dp(Te), _dp(a0),
+    n0 = None if n0 is None else _f64(np.asarray(n0, dtype=np.float64).reshape(3))
+    D = None if D is None else _f64(sym6(D).reshape(6))
+    rc = lib().orc_element(ctypes.byref(m), npe, _dp(Xe), _dp(ue), _dp(Te), _dp(a0), _dp(n0), _dp(D),
                            _dp(theta) if theta is not None else None, float(dt), _dp(f), _dp(h), _dp(en))
     if rc != 0:
         raise ValueError(f"orc_element failed ({rc})")
     return f, h, float(en[0])
 
 
+def sym6(D):
+    """Symmetric tensors as (xx yy zz xy yz xz): accepts (..., 3, 3) or (..., 6)."""
+    D = np.asarray(D, dtype=np.float64)
+    if D.shape[-2:] == (3, 3):
+        return np.stack([D[..., 0, 0], D[..., 1, 1], D[..., 2, 2], D[..., 0, 1], D[..., 1, 2], D[..., 0, 2]], -1)
+    return D
+
+
 class OracleSim:
-    """A problem set up in the oracle: geometry and lumped matrices in FP64."""
+    """A problem set up in the oracle: geometry and lumped matrices in FP64.  n0 (ne x 3): second
+    thermal-expansion axis per element (expan_mode 2); D (ne x 3 x 3 or ne x 6): conductivity
+    tensor per element (cond_mode 2)."""
 
     def __init__(self, npe, X, conn, params: dict, a0=None, q=None, fix=None, Tfix=None,
-                 t_on=0.0, t_off=float("inf"), dt=0.0, gamma=0.0):
+                 t_on=0.0, t_off=float("inf"), dt=0.0, gamma=0.0, n0=None, D=None):
         self.X = _f64(X)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.nn = self.X.shape[0]
@@ -184,13 +200,16 @@ class OracleSim:
         self.n_prony = int(params.get("n_prony", len(params.get("g", []))))
         self._m = material(params)
         a0 = _f64(a0)
+        n0 = _f64(n0)
+        D = None if D is None else _f64(sym6(D))
         q = _f64(q)
         fix = None if fix is None else np.ascontiguousarray(fix, dtype=np.uint8)
         Tfix = _f64(Tfix)
         self._L = lib()
         h = ctypes.c_void_p()
         rc = self._L.orc_create(ctypes.byref(h), self.npe, self.nn, _dp(self.X), self.ne,
-                              self.conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(a0), _dp(q),
+                              self.conn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(a0), _dp(n0),
+                              _dp(D), _dp(q),
                               fix.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if fix is not None else None,
                               _dp(Tfix), ctypes.byref(self._m), float(t_on), float(t_off),
                               float(dt), float(gamma))

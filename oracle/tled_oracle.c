@@ -33,7 +33,11 @@
  *   - critical time step min_e L_e / c_d with c_d = sqrt((kappa + 4mu/3 + 4eta)/rho),
  *     L_e = 3 V0 / A_max (T4) or V0 / A_max (H8);
  *   - T4 elements with negative volume are repaired by swapping their last two
- *     nodes; a degenerate element or an inverted H8 is an error.
+ *     nodes; a degenerate element or an inverted H8 is an error;
+ *   - the orthotropic expansion of Eq. 11 takes m = the fibre a0 and n = the
+ *     per-element second axis made orthonormal to m; a per-element conductivity
+ *     tensor is the D of Eq. 15 as given (not rotated with the tissue), scaled by
+ *     k(T)/k when the conductivity is temperature-dependent.
  *
  * Parity unpinned: the hourglass coefficient and the critical-time-step
  * formula are readings, not the paper's numbers (the hourglass force is pinned
@@ -53,7 +57,8 @@ typedef struct {
     double kappa;        /* bulk modulus, Pa                                    */
     double eta;          /* fibre (anisotropic) coefficient eta_a, Pa           */
     double alpha;        /* thermal expansion coefficient, 1/K (isotropic part) */
-    double alpha_m;      /* expansion along the fibre (expan_mode 1), 1/K       */
+    double alpha_m;      /* expansion along the fibre m = a0 (expan_mode 1, 2), 1/K */
+    double alpha_n;      /* expansion along the second axis n (expan_mode 2), 1/K */
     double T0;           /* stress-free reference temperature, K               */
     double k;            /* thermal conductivity, W/(m K)                      */
     double k_m;          /* conductivity along the fibre (cond_mode 1)          */
@@ -68,8 +73,8 @@ typedef struct {
     double ckT_lo, ckT_hi, c_hi, k_hi;        /* c(T), k(T) linear laws       */
     double hg_coef;      /* hourglass coefficient (H8)                         */
     int32_t n_prony;     /* number of Prony terms, 0..4                        */
-    int32_t expan_mode;  /* 0: F_th = lambda I; 1: transversely isotropic, Eq. 11 */
-    int32_t cond_mode;   /* 0: D = k I; 1: D = k I + (k_m - k) a0 (x) a0         */
+    int32_t expan_mode;  /* 0: F_th = lambda I; 1: transversely isotropic; 2: orthotropic (Eq. 11) */
+    int32_t cond_mode;   /* 0: D = k I; 1: D = k I + (k_m - k) a0 (x) a0; 2: per-element tensor */
     int32_t muT_on;      /* 1: temperature-dependent mu and eta                  */
     int32_t shrink_on;   /* 1: shrinkage factor on the thermal stretch          */
     int32_t ckT_on;      /* 1: temperature-dependent c and k                    */
@@ -81,6 +86,8 @@ typedef struct {
     double *X;        /* nn x 3 reference coordinates                         */
     int32_t *conn;    /* ne x npe (orientation repaired)                      */
     double *a0;       /* ne x 3 unit fibre directions                         */
+    double *n0;       /* ne x 3 second expansion axes (expan_mode 2), or NULL   */
+    double *Dc;       /* ne x 6 conductivity tensors xx yy zz xy yz xz (cond_mode 2), or NULL */
     double *q;        /* ne regional source density, W/m^3                    */
     uint8_t *fix;     /* nn: bit0..2 fixed u_x,u_y,u_z ; bit3 fixed T          */
     double *Tfix;     /* nn prescribed temperatures (where bit3)              */
@@ -149,19 +156,40 @@ static double clamp01(double x) { return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x); }
 /* ---------------------------------------------------------------------- */
 
 /* Thermal stretch ratios, lambda ~= 1 + alpha (T - T0) (Section 3.2, after
- * Eq. 11), optionally times a reversible shrinkage factor. */
-static void thermal_stretch(const orc_material *m, double Te, double *li, double *lm)
+ * Eq. 11), optionally times a reversible shrinkage factor: li across the axes,
+ * lm along m (the fibre), ln along n. */
+static void thermal_stretch(const orc_material *m, double Te, double *li, double *lm, double *ln)
 {
     double dT = Te - m->T0;
     double a = 1.0 + m->alpha * dT;
-    double b = (m->expan_mode == 1) ? 1.0 + m->alpha_m * dT : a;
+    double b = (m->expan_mode == 1 || m->expan_mode == 2) ? 1.0 + m->alpha_m * dT : a;
+    double c = (m->expan_mode == 2) ? 1.0 + m->alpha_n * dT : a;
     if (m->shrink_on) {
         double s = 1.0 + m->shrink_eps * clamp01((Te - m->shrink_T) / m->shrink_width);
         a *= s;
         b *= s;
+        c *= s;
     }
     *li = a;
     *lm = b;
+    *ln = c;
+}
+
+/* Unit axes of Eq. 11: m = a / |a|, and n made orthogonal to m and unit length
+ * (Gram-Schmidt; the paper takes m and n orthonormal).  Returns 0 when n is
+ * (numerically) parallel to m. */
+static int expansion_axes(const double *a_in, const double *n_in, double *mv, double *nv)
+{
+    double an = sqrt(a_in[0] * a_in[0] + a_in[1] * a_in[1] + a_in[2] * a_in[2]);
+    for (int i = 0; i < 3; ++i) mv[i] = a_in[i] / an;
+    if (!n_in) { nv[0] = nv[1] = nv[2] = 0.0; return 1; }
+    double nn0 = sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
+    double d = n_in[0] * mv[0] + n_in[1] * mv[1] + n_in[2] * mv[2];
+    double w[3] = {n_in[0] - d * mv[0], n_in[1] - d * mv[1], n_in[2] - d * mv[2]};
+    double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (!(wn > 1e-6 * nn0)) return 0;
+    for (int i = 0; i < 3; ++i) nv[i] = w[i] / wn;
+    return 1;
 }
 
 /* Scale of mu and eta at temperature T (temperature-dependent mechanics). */
@@ -192,24 +220,29 @@ static double conductivity_scale(const orc_material *m, double T)
  *   Psi = mu/2 (I1bar - 3) + eta/2 (I4bar - 1)^2 + kappa/2 (J - 1)^2,
  * evaluated on the elastic part Fe = F Fth^-1 (Eq. 8), S_i = 2 dPsi/dC_i
  * (Eq. 9), pulled back with det(Fth) Fth^-1 S_i Fth^-T (Eq. 10).
- * Fth = lambda_i I + (lambda_m - lambda_i) a (x) a (Eq. 11, transversely
- * isotropic form; lambda_m = lambda_i gives the isotropic case).
+ * Fth = lambda_i I + (lambda_m - lambda_i) m (x) m + (lambda_n - lambda_i) n (x) n
+ * (Eq. 11) with m the unit fibre a and n the second axis (n_in, made orthonormal
+ * to m; may be NULL outside the orthotropic mode).  The transversely isotropic
+ * form has lambda_n = lambda_i and the isotropic one lambda_m = lambda_n = lambda_i.
  * psi returns det(Fth) Psi, the strain energy per unit reference volume.
  * Returns J of the elastic part.
  */
-double orc_stress(const orc_material *m, const double *F, const double *a_in,
+double orc_stress(const orc_material *m, const double *F, const double *a_in, const double *n_in,
                   double Te, double *S0, double *psi)
 {
-    double an = sqrt(a_in[0] * a_in[0] + a_in[1] * a_in[1] + a_in[2] * a_in[2]);
-    double a[3] = {a_in[0] / an, a_in[1] / an, a_in[2] / an};
-    double A0[9], I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double a[3], nv[3];
+    expansion_axes(a_in, m->expan_mode == 2 ? n_in : NULL, a, nv);
+    double A0[9], N0[9], I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) A0[3 * i + j] = a[i] * a[j];
+        for (int j = 0; j < 3; ++j) {
+            A0[3 * i + j] = a[i] * a[j];
+            N0[3 * i + j] = nv[i] * nv[j];
+        }
 
-    double li, lm;
-    thermal_stretch(m, Te, &li, &lm);
+    double li, lm, ln;
+    thermal_stretch(m, Te, &li, &lm, &ln);
     double Fth[9], Fth_inv[9], Fth_invT[9];
-    for (int i = 0; i < 9; ++i) Fth[i] = li * I3[i] + (lm - li) * A0[i];
+    for (int i = 0; i < 9; ++i) Fth[i] = li * I3[i] + (lm - li) * A0[i] + (ln - li) * N0[i];
     inv3(Fth, Fth_inv);
     transpose3(Fth_inv, Fth_invT);
     double detFth = det3(Fth);
@@ -373,6 +406,7 @@ typedef struct {
 static void element_compute(const orc_material *m, int npe, const double *dhdx, double V0,
                             const double *gam, double khg,
                             const double *ue, const double *Te_nodes, const double *a,
+                            const double *nax, const double *Dc,
                             double *theta, double dt, double *f, double *h, elem_info *info)
 {
     /* Eq. 17: F = u_e^T (L h) + I, i.e. F_ij = delta_ij + sum_a u_a,i dh_a/dX_j */
@@ -386,7 +420,7 @@ static void element_compute(const orc_material *m, int npe, const double *dhdx, 
     Te /= (double)npe;
 
     double S0[9], psi;
-    orc_stress(m, F, a, Te, S0, &psi);
+    orc_stress(m, F, a, nax, Te, S0, &psi);
 
     /* Prony recursion on the total stress (after Eq. 27):
      * theta_i <- dt phi_i/(dt + tau_i) S + tau_i/(dt + tau_i) theta_i ; S~ = S - sum theta_i */
@@ -426,7 +460,8 @@ static void element_compute(const orc_material *m, int npe, const double *dhdx, 
     }
 
     /* Eq. 16 (Eqs. 18-19 with one point):
-     * K_e = V0 det(F) (L h F^-1) D (L h F^-1)^T, f_ther = K_e T_e */
+     * K_e = V0 det(F) (L h F^-1) D (L h F^-1)^T, f_ther = K_e T_e, with D the
+     * element conductivity tensor of Eq. 15 (times k(T)/k when temperature-dependent) */
     double Finv[9];
     inv3(F, Finv);
     double J = det3(F);
@@ -439,6 +474,11 @@ static void element_compute(const orc_material *m, int npe, const double *dhdx, 
             D[3 * i + j] = (i == j) ? kT : 0.0;
             if (m->cond_mode == 1) D[3 * i + j] += (kmT - kT) * (a[i] / an) * (a[j] / an);
         }
+    if (m->cond_mode == 2) {
+        static const int comp[9] = {0, 3, 5, 3, 1, 4, 5, 4, 2}; /* (xx yy zz xy yz xz) */
+        double ks = conductivity_scale(m, Te);
+        for (int i = 0; i < 9; ++i) D[i] = ks * Dc[comp[i]];
+    }
     double BF[8][3];
     for (int ai = 0; ai < npe; ++ai)
         for (int j = 0; j < 3; ++j) {
@@ -467,9 +507,14 @@ static void element_compute(const orc_material *m, int npe, const double *dhdx, 
  * Xe npe x 3, ue npe x 3, Te npe, theta n_prony x 6 (in/out), outputs f npe x 3, h npe.
  * Returns 0, or ORC_E_MESH for a degenerate element. */
 int orc_element(const orc_material *m, int32_t npe, const double *Xe, const double *ue,
-                const double *Te, const double *a0, double *theta, double dt,
-                double *f, double *h, double *energy)
+                const double *Te, const double *a0, const double *n0, const double *Dc,
+                double *theta, double dt, double *f, double *h, double *energy)
 {
+    if (m->expan_mode == 2) {
+        double mv[3], nv[3];
+        if (!n0 || !expansion_axes(a0, n0, mv, nv)) return ORC_E_ARG;
+    }
+    if (m->cond_mode == 2 && !Dc) return ORC_E_ARG;
     double dhdx[24], V0 = 0.0, gam[32];
     double d;
     if (npe == 4) d = t4_geometry(Xe, dhdx, &V0);
@@ -484,7 +529,7 @@ int orc_element(const orc_material *m, int32_t npe, const double *Xe, const doub
     }
     double th0[24] = {0};
     elem_info info;
-    element_compute(m, npe, dhdx, V0, npe == 8 ? gam : NULL, khg, ue, Te, a0,
+    element_compute(m, npe, dhdx, V0, npe == 8 ? gam : NULL, khg, ue, Te, a0, n0, Dc,
                     theta ? theta : th0, dt, f, h, &info);
     if (energy) *energy = info.psi;
     return ORC_OK;
@@ -496,20 +541,22 @@ int orc_element(const orc_material *m, int32_t npe, const double *Xe, const doub
 void orc_destroy(orc_sim *s)
 {
     if (!s) return;
-    free(s->X); free(s->conn); free(s->a0); free(s->q); free(s->fix); free(s->Tfix);
+    free(s->X); free(s->conn); free(s->a0); free(s->n0); free(s->Dc); free(s->q); free(s->fix); free(s->Tfix);
     free(s->dhdx); free(s->V0); free(s->gam); free(s->khg);
     free(s->Vl); free(s->M); free(s->Kb); free(s->Qm); free(s->Qr);
     free(s);
 }
 
 int orc_create(orc_sim **out, int32_t npe, int64_t nn, const double *X, int64_t ne,
-               const int32_t *conn, const double *a0, const double *q, const uint8_t *fix,
+               const int32_t *conn, const double *a0, const double *n0, const double *Dc,
+               const double *q, const uint8_t *fix,
                const double *Tfix, const orc_material *m, double t_on, double t_off,
                double dt, double gamma)
 {
     *out = NULL;
     if ((npe != 4 && npe != 8) || nn <= 0 || ne <= 0 || !X || !conn || !m) return ORC_E_ARG;
     if (m->n_prony < 0 || m->n_prony > 4) return ORC_E_ARG;
+    if ((m->expan_mode == 2 && !n0) || (m->cond_mode == 2 && !Dc)) return ORC_E_ARG;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     if (!s) return ORC_E_OOM;
     s->npe = npe; s->nn = nn; s->ne = ne; s->m = *m;
@@ -539,6 +586,20 @@ int orc_create(orc_sim **out, int32_t npe, int64_t nn, const double *X, int64_t 
     for (int64_t e = 0; e < ne; ++e) {
         if (a0) { s->a0[3 * e] = a0[3 * e]; s->a0[3 * e + 1] = a0[3 * e + 1]; s->a0[3 * e + 2] = a0[3 * e + 2]; }
         else { s->a0[3 * e] = 1.0; s->a0[3 * e + 1] = 0.0; s->a0[3 * e + 2] = 0.0; }
+    }
+    if (m->expan_mode == 2) {
+        s->n0 = malloc(sizeof(double) * 3 * ne);
+        if (!s->n0) { orc_destroy(s); return ORC_E_OOM; }
+        memcpy(s->n0, n0, sizeof(double) * 3 * ne);
+        for (int64_t e = 0; e < ne; ++e) {
+            double mv[3], nv[3];
+            if (!expansion_axes(s->a0 + 3 * e, s->n0 + 3 * e, mv, nv)) { orc_destroy(s); return ORC_E_ARG; }
+        }
+    }
+    if (m->cond_mode == 2) {
+        s->Dc = malloc(sizeof(double) * 6 * ne);
+        if (!s->Dc) { orc_destroy(s); return ORC_E_OOM; }
+        memcpy(s->Dc, Dc, sizeof(double) * 6 * ne);
     }
     if (q) memcpy(s->q, q, sizeof(double) * ne);
     if (fix) memcpy(s->fix, fix, nn);
@@ -629,6 +690,7 @@ static void element_loop(const orc_sim *s, const double *u, const double *T, dou
         elem_info info;
         element_compute(&s->m, npe, s->dhdx + (int64_t)3 * npe * e, s->V0[e],
                         npe == 8 ? s->gam + 32 * e : NULL, s->khg[e], ue, Te, s->a0 + 3 * e,
+                        s->n0 ? s->n0 + 3 * e : NULL, s->Dc ? s->Dc + 6 * e : NULL,
                         theta + (int64_t)6 * s->m.n_prony * e, s->dt, f, h, &info);
         for (int a = 0; a < npe; ++a) {
             for (int i = 0; i < 3; ++i) Fint[3 * (int64_t)c[a] + i] += f[3 * a + i];

@@ -475,12 +475,20 @@ class Batch(Sim):
             o += s
         return out
 
-    def scenario_monitors(self, ablation_T: float = 333.15):
+    def scenario_monitors(self, ablation_T: float = 333.15, strict: bool = True):
+        """Per-scenario maximum temperature and volume at or above ablation_T.  With strict=False a
+        device-raised instability does not raise: (T_max, volume, status) is returned, and the
+        scenarios that went unstable show a non-finite T_max."""
         S = len(self.sizes)
         tmax = np.zeros(S)
         vol = np.zeros(S)
-        self._check(_lib.tled_batch_monitors(self._h, float(ablation_T), _ptr(tmax), _ptr(vol)))
-        return tmax, vol
+        st = _lib.tled_batch_monitors(self._h, float(ablation_T), _ptr(tmax), _ptr(vol))
+        if strict:
+            self._check(st)
+            return tmax, vol
+        if st not in (OK, E_UNSTABLE):
+            self._check(st)
+        return tmax, vol, st
 
     def batch_info(self) -> dict:
         i = BatchInfo()

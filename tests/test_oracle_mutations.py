@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import test_oracle_law_pins as P
+import test_oracle_ortho_pins as R
 import test_oracle_pins as Q
 
 MUTATIONS = [
@@ -41,10 +42,11 @@ MUTATIONS = [
      "(Te - m->shrink_T) / m->shrink_width", "(Te - m->shrink_T + 2.0) / m->shrink_width",
      [lambda: P.test_shrinkage_clamped_heating(325.5, 739.5914), lambda: P.test_shrinkage_free_expansion(4, 325.5)]),
     ("ti_expansion_swapped_axes",
-     "Fth[i] = li * I3[i] + (lm - li) * A0[i];", "Fth[i] = lm * I3[i] + (li - lm) * A0[i];",
+     "Fth[i] = li * I3[i] + (lm - li) * A0[i] + (ln - li) * N0[i];",
+     "Fth[i] = lm * I3[i] + (li - lm) * A0[i] + (ln - li) * N0[i];",
      [lambda: P.test_ti_expansion_free(4, 0), lambda: P.test_ti_expansion_clamped_heating(10.0)]),
     ("ti_expansion_fibre_ignored",
-     "double b = (m->expan_mode == 1) ? 1.0 + m->alpha_m * dT : a;", "double b = a;",
+     "double b = (m->expan_mode == 1 || m->expan_mode == 2) ? 1.0 + m->alpha_m * dT : a;", "double b = a;",
      [lambda: P.test_ti_expansion_free(8, 1), lambda: P.test_ti_expansion_clamped_heating(30.0)]),
     ("ti_conduction_swapped_k",
      "D[3 * i + j] += (kmT - kT) *", "D[3 * i + j] += (kT - kmT) *",
@@ -69,6 +71,26 @@ MUTATIONS = [
     ("arterial_is_T0",
      "(T[a] - s->m.T_art)", "(T[a] - s->m.T0)",
      [lambda: P.test_pennes_0d_metabolic_arterial(309.0)]),
+    ("ortho_n_ratio_from_alpha_m",
+     "double c = (m->expan_mode == 2) ? 1.0 + m->alpha_n * dT : a;",
+     "double c = (m->expan_mode == 2) ? 1.0 + m->alpha_m * dT : a;",
+     [lambda: R.test_ortho_expansion_free(4, 0), R.test_ortho_clamped_heating_values]),
+    ("ortho_n_not_orthogonalised",
+     "double w[3] = {n_in[0] - d * mv[0], n_in[1] - d * mv[1], n_in[2] - d * mv[2]};",
+     "double w[3] = {n_in[0], n_in[1], n_in[2]};",
+     [lambda: R.test_ortho_expansion_free(8, 1)]),
+    ("ortho_n_term_dropped",
+     "+ (lm - li) * A0[i] + (ln - li) * N0[i];", "+ (lm - li) * A0[i];",
+     [lambda: R.test_ortho_expansion_free(4, 2), R.test_ortho_clamped_heating_values,
+      lambda: R.test_ortho_clamped_volumetric(0)]),
+    ("tensor_xy_xz_swapped",
+     "static const int comp[9] = {0, 3, 5, 3, 1, 4, 5, 4, 2};",
+     "static const int comp[9] = {0, 5, 3, 5, 1, 4, 3, 4, 2};",
+     [lambda: R.test_tensor_conduction_first_moment("t4", 4, 0, 1.3),
+      lambda: R.test_tensor_conduction_rigid_rotation("h8", 8)]),
+    ("tensor_kT_unscaled",
+     "double ks = conductivity_scale(m, Te);", "double ks = 1.0;",
+     [lambda: R.test_tensor_conduction_kT(336.65), lambda: R.test_tensor_conduction_kT(370.0)]),
     # a few of the older pins, for the laws they pin
     ("pullback_missing_det",
      "for (int i = 0; i < 9; ++i) S0[i] = detFth * T2[i];", "for (int i = 0; i < 9; ++i) S0[i] = T2[i];",
