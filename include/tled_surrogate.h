@@ -108,6 +108,19 @@ tled_status tled_mlp_scenario_outputs(int32_t n_scen, int64_t n_rows, const int6
  * patterns (device, row-major), C FP32 (device, row-major). */
 tled_status tled_mlp_gemm(tled_mlp *mlp, int32_t m, int32_t n, int32_t k, const uint16_t *A, const uint16_t *B,
                           float *C);
+/* tled_mlp_gemm for callers that cannot allocate (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid allocation): no device or host
+ * memory is allocated per call.  Its split-K partials live in a static device
+ * array of 512 x 64 x 64 floats (8 MiB) that every GPU the library runs on holds
+ * until the process ends; the array's address on a device is resolved when a
+ * handle is created on it.  TLED_E_ARG when a product's split-K partials would
+ * exceed the array (the split rule keeps them within it), TLED_E_STATE if the
+ * address was not resolved.  All calls on one GPU share the array and each
+ * leaves it holding its partials: calls that overlap on one GPU (several
+ * streams or threads) race.  Timing (tled_mlp_set_timing) does not apply.
+ * Same kernels and the same bits as tled_mlp_gemm. */
+tled_status tled_mlp_gemm_static(tled_mlp *mlp, int32_t m, int32_t n, int32_t k, const uint16_t *A,
+                                 const uint16_t *B, float *C);
 /* Measurement: with timing on, every GEMM and fused-inference launch is
  * bracketed by HIP events on the handle's stream (and waited for);
  * tled_mlp_last_timing returns, since timing was switched on, the summed GEMM

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -565,8 +566,35 @@ struct Layer {
 
 }  // namespace
 
+// Split-K partials of tled_mlp_gemm_static: a static device array (each GPU the
+// library runs on holds its own copy for the life of the process).  Host code
+// never passes `scratch` itself (on the host it names a stand-in, not a device
+// address): its per-device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, when a handle is created there.  With
+// the split rule of gemm() (nz x output tiles <= 512, 64 x 64 tiles) the
+// partials never exceed 512 x 4096 floats, which is this array's size.
+constexpr size_t kStaticSplitFloats = size_t(512) * 64 * 64;
+static __device__ __align__(256) float scratch[kStaticSplitFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<float *> g_scratch_addr;   // device ordinal -> address of `scratch` on that device
+
+// Call with `device` current.
+tled_status resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (size_t(device) >= g_scratch_addr.size()) g_scratch_addr.resize(size_t(device) + 1, nullptr);
+    if (g_scratch_addr[device]) return TLED_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TLED_E_HIP;
+    g_scratch_addr[device] = static_cast<float *>(p);
+    return TLED_OK;
+}
+}  // namespace
+
 struct tled_mlp {
     int device = 0;
+    float *d_static_split = nullptr;   // this device's `scratch` (resolved at creation)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     tled_mlp_config cfg{};
@@ -671,15 +699,26 @@ int load_mode(const uint16_t *X, long sr, long sk) {
     return LD_SCALAR;
 }
 
+// split_ext: split-K partials in a caller-held buffer of split_ext_cap floats
+// (nothing is allocated and no timing events are created); else the handle's
+// buffer, grown on demand.
 template <int EPI>
 tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, long sak, const uint16_t *B,
-                 long sbk, long sbn, float *C, long scm, long scn, uint16_t *Act, const float *bias) {
+                 long sbk, long sbn, float *C, long scm, long scn, uint16_t *Act, const float *bias,
+                 float *split_ext = nullptr, size_t split_ext_cap = 0) {
     const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     int nz = 1;
     if (EPI == EPI_F32 && tiles < 256 && K >= 4 * BK) nz = int(std::min<long>(64, std::max<long>(1, 512 / tiles)));
     int kchunk = ((K + nz - 1) / nz + BK - 1) / BK * BK;
     nz = (K + kchunk - 1) / kchunk;
-    if (nz > 1) {
+    float *split = s->d_split;
+    if (nz > 1 && split_ext) {
+        const size_t need = size_t(nz) * M * N;
+        if (need > split_ext_cap)
+            return mfail(s, TLED_E_ARG, "split-K partials of " + std::to_string(need) + " floats exceed the " +
+                                            std::to_string(split_ext_cap) + " of the static scratch array");
+        split = split_ext;
+    } else if (nz > 1) {
         const size_t need = size_t(nz) * M * N;
         if (need > s->split_cap) {
             MCHK(s, hipStreamSynchronize(s->stream));   // earlier launches may still use the old buffer
@@ -691,16 +730,18 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
             s->d_split = static_cast<float *>(p);
             s->split_cap = need;
         }
+        split = s->d_split;
     }
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz);
     const int am = load_mode(A, sam, sak), bmode = load_mode(B, sbn, sbk);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s->timing) {
+    const bool timed = s->timing && !split_ext;
+    if (timed) {
         MCHK(s, hipEventCreate(&e0));
         MCHK(s, hipEventCreate(&e1));
         MCHK(s, hipEventRecord(e0, s->stream));
     }
-    float *Cout = nz > 1 ? s->d_split : C;
+    float *Cout = nz > 1 ? split : C;
 #define TLED_GEMM_LAUNCH(AMODE, BMODE_)                                                                       \
     hipLaunchKernelGGL((gemm_kernel<EPI, AMODE, BMODE_>), grid, dim3(kThreads), 0, s->stream, M, N, K, A, sam, sak, \
                        B, sbk, sbn, Cout, scm, scn, Act, bias, kchunk)
@@ -712,9 +753,9 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
 #undef TLED_GEMM_LAUNCH
     if (nz > 1)
         hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks(long(M) * N)), dim3(kThreads), 0, s->stream, nz, M, N,
-                           s->d_split, C, scm, scn);
+                           split, C, scm, scn);
     MCHK(s, hipGetLastError());
-    if (s->timing) {
+    if (timed) {
         MCHK(s, hipEventRecord(e1, s->stream));
         MCHK(s, hipEventSynchronize(e1));
         float ms = 0.f;
@@ -860,9 +901,14 @@ tled_status tled_mlp_create(tled_mlp **out, int device, const tled_mlp_config *c
     int nd = 0;
     if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return TLED_E_HIP;
     if (hipSetDevice(device) != hipSuccess) return TLED_E_HIP;
+    if (resolve_scratch(device) != TLED_OK) return TLED_E_HIP;
     tled_mlp *s = new (std::nothrow) tled_mlp();
     if (!s) return TLED_E_OOM;
     s->device = device;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        s->d_static_split = g_scratch_addr[device];
+    }
     s->cfg = *cfg;
     s->K0 = ((2 * cfg->n_freq + cfg->n_param + 31) / 32) * 32;
     long off = 0;
@@ -1024,6 +1070,15 @@ tled_status tled_mlp_gemm(tled_mlp *s, int32_t m, int32_t n, int32_t k, const ui
     s->gemm_ms = s->fused_ms = s->gemm_flops = s->fused_flops = 0.0;
     MTRY(gemm<EPI_F32>(s, m, n, k, A, k, 1, B, n, 1, C, n, 1, nullptr, nullptr));
     return TLED_OK;
+}
+
+tled_status tled_mlp_gemm_static(tled_mlp *s, int32_t m, int32_t n, int32_t k, const uint16_t *A,
+                                 const uint16_t *B, float *C) {
+    if (!s || m <= 0 || n <= 0 || k <= 0 || !A || !B || !C) return TLED_E_ARG;
+    if (!s->d_static_split) return mfail(s, TLED_E_STATE, "static scratch not resolved for this device");
+    MCHK(s, hipSetDevice(s->device));
+    return gemm<EPI_F32>(s, m, n, k, A, k, 1, B, n, 1, C, n, 1, nullptr, nullptr, s->d_static_split,
+                         kStaticSplitFloats);
 }
 
 tled_status tled_mlp_ensemble_stats(int64_t n, int32_t members, int32_t n_out, const float *outs,

@@ -46,6 +46,7 @@ _SIGS = {
     "tled_mlp_train_step": ([_P, ctypes.c_int64, _P, _P, _P, _f, _fp], ctypes.c_int),
     "tled_mlp_gradient": ([_P, ctypes.c_int64, _P, _P, _P, _fp, _fp], ctypes.c_int),
     "tled_mlp_gemm": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "tled_mlp_gemm_static": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P], ctypes.c_int),
     "tled_mlp_ensemble_stats": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P], ctypes.c_int),
     "tled_mlp_scenario_inputs": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_double,
                                   _P, _P, _P, _P], ctypes.c_int),
@@ -200,6 +201,17 @@ class MLP:
         _need(B_bits, k, n, torch.int16, "B")
         _need(C, m, n, torch.float32, "C")
         self._call(_lib.tled_mlp_gemm, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C))
+
+    def gemm_static(self, A_bits, B_bits, C):
+        """gemm() through the allocation-free entry point (split-K partials in the library's static
+        device scratch array)."""
+        import torch
+        m, k = A_bits.shape
+        n = B_bits.shape[1]
+        _need(A_bits, m, k, torch.int16, "A")
+        _need(B_bits, k, n, torch.int16, "B")
+        _need(C, m, n, torch.float32, "C")
+        self._call(_lib.tled_mlp_gemm_static, m, n, k, _dp(A_bits), _dp(B_bits), _dp(C))
 
     def set_timing(self, on: bool):
         self._check(_lib.tled_mlp_set_timing(self._h, int(on)))
