@@ -57,7 +57,7 @@ def parse():
                          "cube_t4: the 6000-tet parity cube (cache-resident, launch-bound)")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--repeats", type=int, default=5,
-                    help="timed regions of --steps steps (the first gives value; all are reported with their median)")
+                    help="timed regions of --steps steps each; value is their median, all are reported")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps for the CPU baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", type=int, default=0, metavar="N",
@@ -65,10 +65,23 @@ def parse():
     ap.add_argument("--duration-scale", type=float, default=1e-3,
                     help="sweep heating durations are U(30, 300) s times this factor")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", default="auto", choices=["auto"] + ["prefix-eager", "prefix-graph-50",
+                                                                        "queue-graph-100", "queue-graph-400"],
+                    help="batch launch schedule of the sweep (auto: chosen by the autotuner)")
     ap.add_argument("--surrogate", type=int, default=0, metavar="N_TRAIN",
                     help="instead of the headline run: train the surrogate ensemble on N_TRAIN planning runs and "
                          "compare scenarios/s of surrogate-with-fallback against the solver (one JSON line)")
     ap.add_argument("--holdout", type=int, default=200)
+    ap.add_argument("--data-dir", default="",
+                    help="surrogate training data: with --shard, where to write it; else, if it holds shards "
+                         "of the N_TRAIN training runs, train on them instead of solving the runs here")
+    ap.add_argument("--shard", default="", metavar="K/N",
+                    help="with --surrogate N_TRAIN: only solve the K-th of N slices of the training runs and "
+                         "store a node subsample of their snapshots in --data-dir (training data made in "
+                         "separate runs)")
+    ap.add_argument("--shard-nodes", type=int, default=2048, help="nodes stored per snapshot field")
+    ap.add_argument("--surrogate-schedule", type=int, default=0, choices=[0, 1],
+                    help="batch schedule of the surrogate's solver runs (1: work queue in graph chunks of 100)")
     ap.add_argument("--calib", type=int, default=100, help="solver runs held back to calibrate the disagreement")
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--members", type=int, default=4)
@@ -87,16 +100,18 @@ def parse():
 
 
 def copy_calibration(mib: int):
-    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE give the counter scale."""
+    """The library's plain streaming copy kernel at a known size: its FETCH_SIZE / WRITE_SIZE give
+    the counter scale."""
     import torch
+    from paper_2009_10400_amd import tled
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     for _ in range(5):
-        dst.copy_(src)
+        tled.stream_copy(dst, src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5, "kernel": "stream_copy_kernel"}), flush=True)
 
 
 def _counter_means(db_path: str, counter: str):
@@ -197,21 +212,40 @@ def traffic_from_profiles(kernel_name: str, workload: str, info=None):
 
 
 def copy_bandwidth(mib: int = 1024, reps: int = 5):
-    """GB/s of a plain device-to-device copy (read + write bytes / time), HIP events."""
+    """GB/s of the library's plain streaming copy kernel (read + write bytes / time), HIP events
+    recorded on the stream the copies run on."""
     import torch
+    from paper_2009_10400_amd import tled
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
+    st = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(st):
+        tled.stream_copy(dst, src, st.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            tled.stream_copy(dst, src, st.cuda_stream)
+        e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(dst, src))
     del src, dst
+    if not ok:
+        raise RuntimeError("stream copy produced wrong data")
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(problem, dt, steps):
@@ -225,7 +259,8 @@ def cpu_baseline(problem, dt, steps):
     o.run(st, steps)
     el = time.perf_counter() - t0
     return {"value": problem.ne * steps / el, "unit": "element-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the full {problem.ne}-tet workload, serial FP64 oracle ({el:.1f} s)"}
+            "sample": f"{steps} steps of the full {problem.ne}-tet workload, serial FP64 oracle ({el:.1f} s)",
+            "cpu_model": cpu_model(), "host_cores_available": host_threads()}
 
 
 def host_threads() -> int:
@@ -290,14 +325,23 @@ def sweep(args):
     ne_tot = sum(p.ne for p in probs)
     log(f"[sweep] {len(sc)} scenarios, {ne_tot} elements, built in {time.time() - t:.1f}s")
     stream = torch.cuda.Stream(device=0)
-    choice, report = {}, {}
+    choice, report, sched_report = {}, {}, None
     if not args.no_autotune:
         t = time.time()
         choice, report = autotune.tune(probs, stream=stream.cuda_stream, log=log)
         log(f"[sweep] autotune {time.time() - t:.1f}s -> {choice}")
+    if args.schedule == "auto":
+        t = time.time()
+        sched, sched_opts, sched_report = autotune.tune_schedule(probs, [d for _, d in sc], choice,
+                                                                 stream=stream.cuda_stream, log=log)
+        log(f"[sweep] schedule autotune {time.time() - t:.1f}s -> {sched}")
+    else:
+        sched, sched_opts = args.schedule, dict(autotune.SCHEDULES[args.schedule])
+    if args.graph_steps:
+        sched_opts["graph_steps"] = args.graph_steps
     t = time.time()
     b = tled.Batch(0, stream=stream.cuda_stream)
-    b.set_options(graph_steps=args.graph_steps)
+    b.set_options(**sched_opts)
     for p, dur in sc:
         b.add(p, cfl=p.cfl, t_end=dur, patch_elems=choice.get(autotune.bucket_of(p.ne), 0))
     b.finalize()
@@ -340,9 +384,13 @@ def sweep(args):
                                f"(log-uniform, {ne_tot} total), probe 1/r^2 source U(20,80) W, E U(2,6) kPa, "
                                f"heating U(30,300) s x {args.duration_scale:g}",
                    "duration_scale": args.duration_scale, "autotune": {str(k): v for k, v in choice.items()},
-                   "launch": (f"hipGraph chunks of {args.graph_steps}" if args.graph_steps > 0 else
-                              "eager steps, each launching only the scenarios still running")},
-        "autotune_report": {str(k): v for k, v in report.items()},
+                   "schedule": sched, "schedule_options": sched_opts,
+                   "launch": ({0: "each step launches the patches of the scenarios still running, counted on the host",
+                               1: "work queue: resident workgroups pull the step's patches; running scenarios "
+                                  "counted on the device"}[sched_opts.get("batch_schedule", 0)] +
+                              (f"; hipGraph chunks of {sched_opts['graph_steps']} steps"
+                               if sched_opts.get("graph_steps", 0) > 0 else "; eager steps"))},
+        "autotune_report": {str(k): v for k, v in report.items()}, "schedule_autotune": sched_report,
         "status": status, "batch_steps_done": done, "unstable_scenarios": unstable,
         "ablated_volume_m3": {"min": float(np.nanmin(vol)), "max": float(np.nanmax(vol))},
         "T_max_K": {"min": float(np.nanmin(tmax)), "max": float(np.nanmax(tmax))},
@@ -366,18 +414,39 @@ def surrogate_bench(args):
     t_ref = 300.0 * ds
     t = time.time()
     train_sc = W.planning_scenarios(args.surrogate, seed=5, duration_scale=ds)
-    calib_sc = W.planning_scenarios(args.calib, seed=9, duration_scale=ds)
-    test_sc = W.planning_scenarios(args.holdout, seed=7, duration_scale=ds)
+    if not args.shard:
+        calib_sc = W.planning_scenarios(args.calib, seed=9, duration_scale=ds)
+        test_sc = W.planning_scenarios(args.holdout, seed=7, duration_scale=ds)
     log(f"[surrogate] scenarios built in {time.time() - t:.1f}s")
     stream = torch.cuda.Stream(device=0)
     st = stream.cuda_stream
 
     t = time.time()
-    snaps, t_solve_train = S.solve_snapshots(train_sc, n_snap=args.snapshots, stream=st, log=log)
-    data = S.make_dataset(train_sc, snaps, t_ref)
-    log(f"[surrogate] training data: {len(snaps)} fields, {len(data.x)} samples in {time.time() - t:.1f}s "
-        f"(solver {t_solve_train:.2f}s)")
-    del snaps
+    if args.shard:
+        k, n = (int(v) for v in args.shard.split("/"))
+        lo, hi = len(train_sc) * k // n, len(train_sc) * (k + 1) // n
+        snaps, t_solve = S.solve_snapshots(train_sc[lo:hi], n_snap=args.snapshots, stream=st, log=log,
+                                           batch_schedule=args.surrogate_schedule,
+                                           graph_steps=100 if args.surrogate_schedule else 0)
+        os.makedirs(args.data_dir, exist_ok=True)
+        path = os.path.join(args.data_dir, f"shard_{k:02d}_of_{n:02d}.npz")
+        S.write_shard(path, train_sc, lo, snaps, per_field=args.shard_nodes)
+        print(json.dumps({"shard": args.shard, "runs": hi - lo, "fields": len(snaps), "solver_seconds": t_solve,
+                          "seconds": time.time() - t, "path": path, "bytes": os.path.getsize(path),
+                          "duration_scale": ds}), flush=True)
+        return
+    shards = sorted(f for f in (os.listdir(args.data_dir) if args.data_dir else []) if f.startswith("shard_"))
+    if shards:
+        data = S.dataset_from_shards([os.path.join(args.data_dir, f) for f in shards], train_sc, t_ref)
+        t_solve_train = None
+        log(f"[surrogate] training data from {len(shards)} shards: {int(data.field.max()) + 1} fields, "
+            f"{len(data.x)} samples in {time.time() - t:.1f}s")
+    else:
+        snaps, t_solve_train = S.solve_snapshots(train_sc, n_snap=args.snapshots, stream=st, log=log)
+        data = S.make_dataset(train_sc, snaps, t_ref)
+        log(f"[surrogate] training data: {len(snaps)} fields, {len(data.x)} samples in {time.time() - t:.1f}s "
+            f"(solver {t_solve_train:.2f}s)")
+        del snaps
     net = dict(n_freq=64, width=256, depth=5, n_out=4, sigma=args.sigma)
     ens = S.Ensemble(args.members, t_ref=t_ref, stream=st, **net)
     hist, t_train = ens.fit(data, args.epochs, batch=args.train_batch, lr=args.lr, log=log)
@@ -407,14 +476,15 @@ def surrogate_bench(args):
     m0.close()
     del data, X, P, Y
 
-    cal = S.solve(calib_sc, stream=st)[0]
+    sched = dict(batch_schedule=args.surrogate_schedule, graph_steps=100 if args.surrogate_schedule else 0)
+    cal = S.solve(calib_sc, stream=st, log=log, **sched)[0]
     c = ens.calibrate(calib_sc, cal)
     log(f"[surrogate] calibration factor {c:.3g} from {len(calib_sc)} runs")
 
     # solver alone on the test set
     torch.cuda.synchronize()
-    ref, t_solver = S.solve(test_sc, stream=st)
-    rep = S.plan(ens, test_sc, threshold_K=args.threshold, stream=st)
+    ref, t_solver = S.solve(test_sc, stream=st, log=log, **sched)
+    rep = S.plan(ens, test_sc, threshold_K=args.threshold, stream=st, log=log, **sched)
     t_fb = rep["t_fallback"]
     t_plan = rep["t_surrogate"] + t_fb["total"]
     t_plan_gpu = rep["t_surrogate_gpu"] + t_fb["run"]
@@ -513,25 +583,24 @@ def main():
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
     sim.step(args.warmup)
     sim.sync()
+    # capture the hipGraphs the timed step(K) calls replay (set-up only: nothing runs)
+    sim.prepare(args.steps)
     torch.cuda.synchronize()
     log("[bench] warmup done")
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    sim.sync()
-    ms_per_step = 1e3 * el / args.steps
-    value = p.ne * args.steps / el
-    log(f"[bench] timed {args.steps} steps in {el:.3f}s -> {value:.4g} element-updates/s")
-    reps = [ms_per_step]
-    for _ in range(max(0, args.repeats - 1)):      # the same K steps again, each timed alone
+    # --repeats timed regions of exactly K steps each, every one bracketed by device
+    # synchronisation; the line reports their median (all of them under "repeats")
+    reps = []
+    for _ in range(max(1, args.repeats)):
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         sim.step(args.steps)
         torch.cuda.synchronize()
         reps.append(1e3 * (time.perf_counter() - t1) / args.steps)
     sim.sync()
-    med = float(np.median(reps))
-    log(f"[bench] repeats (ms/step): {[round(r, 5) for r in reps]}, median {med:.5f}")
+    ms_per_step = float(np.median(reps))
+    value = p.ne / (ms_per_step * 1e-3)
+    log(f"[bench] {len(reps)} timed regions of {args.steps} steps (ms/step): {[round(r, 5) for r in reps]}, "
+        f"median {ms_per_step:.5f} -> {value:.4g} element-updates/s")
 
     # dominant kernel, timed with HIP events on the library's stream
     kt = sim.kernel_times(args.kernel_steps)
@@ -578,16 +647,19 @@ def main():
                                   f"(5e7 W/m^3, sigma 4 mm)"}[args.workload],
                    "n_elems": p.ne, "n_nodes": p.nn, "kernel_variant": info["kernel_variant"],
                    "graph_steps": args.graph_steps or 50, "patches": info["n_patches"],
-                   "shared_nodes": info["n_shared_nodes"], "patch_lds_bytes": info["patch_lds_bytes"],
+                   "shared_nodes": info["n_shared_nodes"],
+                   "shared_node_fraction": info["n_shared_nodes"] / max(1, info["n_nodes"]),
+                   "patch_lds_bytes": info["patch_lds_bytes"],
                    "patch_wgs_per_cu": info["patch_wgs_per_cu"],
                    "patch_order": {-1: "as generated", 2: "Morton runs"}.get(args.reorder, "coordinate bisection"),
                    "dt": sim.dt},
         "roofline": roof,
         "step_hbm": step_hbm,
-        "repeats": {"ms_per_step": reps, "median_ms_per_step": med, "median_value": p.ne / (med * 1e-3)},
+        "repeats": {"ms_per_step": reps, "median_ms_per_step": ms_per_step,
+                    "note": "value and ms_per_step are the median of these timed regions of K steps each"},
     }
     if not args.no_cpu_baseline and p.npe == 4:
-        steps = args.cpu_steps or max(3, int(40e6 / p.ne))
+        steps = args.cpu_steps or max(3, int(100e6 / p.ne))
         log(f"[bench] CPU baseline: oracle {steps} steps")
         out["cpu_baseline"] = cpu_baseline(p, sim.dt, steps)
         nt = host_threads()

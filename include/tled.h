@@ -71,7 +71,8 @@ typedef struct {
     double kappa;        /* bulk modulus, Pa                                           */
     double eta;          /* fibre coefficient eta_a, Pa (0: isotropic neo-Hookean)    */
     double alpha;        /* thermal expansion coefficient, 1/K                         */
-    double alpha_m;      /* expansion along the fibre when expan_mode = 1              */
+    double alpha_m;      /* expansion along the fibre m = a0 when expan_mode = 1 or 2  */
+    double alpha_n;      /* expansion along the second axis n when expan_mode = 2      */
     double T0;           /* stress-free reference and initial temperature, K          */
     double k;            /* thermal conductivity, W/(m K)                              */
     double k_m;          /* conductivity along the fibre when cond_mode = 1            */
@@ -86,8 +87,12 @@ typedef struct {
     double ckT_lo, ckT_hi, c_hi, k_hi;         /* c(T), k(T) linear from (lo: c, k) to (hi: c_hi, k_hi) */
     double hg_coef;      /* H8 hourglass coefficient (stiffness hg_coef (kappa + 4 mu/3) V0 sum|dh/dX|^2 / 8) */
     int32_t n_prony;     /* 0..4                                                       */
-    int32_t expan_mode;  /* 0: F_th = lambda I; 1: lambda I + (lambda_m - lambda) a0 a0 (Eq. 11) */
-    int32_t cond_mode;   /* 0: D = k I; 1: D = k I + (k_m - k) a0 a0                    */
+    int32_t expan_mode;  /* Eq. 11.  0: F_th = lambda I; 1: lambda I + (lambda_m - lambda) m m
+                            (transversely isotropic, m = a0); 2: orthotropic,
+                            lambda I + (lambda_m - lambda) m m + (lambda_n - lambda) n n, with n
+                            from tled_set_expansion_axes                                  */
+    int32_t cond_mode;   /* Eqs. 15-16.  0: D = k I; 1: D = k I + (k_m - k) a0 a0; 2: per-element
+                            tensor from tled_set_conductivity (times k(T)/k with ckT_on)  */
     int32_t muT_on;      /* 1: temperature-dependent mu and eta                        */
     int32_t shrink_on;   /* 1: shrinkage factor on lambda                             */
     int32_t ckT_on;      /* 1: temperature-dependent c (per node) and k (per element)  */
@@ -117,6 +122,16 @@ typedef struct {
                                  just fills whole rounds of the 1024 (512) workgroups that are
                                  resident at once on 256 CUs, at least 128                     */
     double  ablation_T;       /* threshold of the ablated-volume monitor, K (0: 333.15 K)     */
+    int32_t batch_schedule;   /* batches only, set before finalize.  0: each step launches the
+                                 patches of the scenarios still running, counted on the host
+                                 (eager steps, or hipGraph chunks captured again whenever that
+                                 set changes); 1: work queue: the patch kernel runs with the
+                                 workgroups that are resident at once, which pull the step's
+                                 patches from per-XCD device counters, and the running
+                                 scenarios are counted on the device from the step counter, so
+                                 one captured chunk of graph_steps steps (default 100) serves
+                                 the whole batch                                             */
+    int32_t reserved;
 } tled_options;
 
 typedef struct {
@@ -179,10 +194,29 @@ tled_status tled_set_material(tled_sim *sim, const tled_material *m);
 /* Fibre directions a0, n_elems x 3, normalised inside (Table 5: unit vector a0).
  * Default: (1, 0, 0) for every element. */
 tled_status tled_set_fibres(tled_sim *sim, const double *a0);
-/* Fixed displacement components: node[i] with mask[i] bits 0..2 = x, y, z.
- * Fixed components stay at zero displacement.  Repeated calls accumulate. */
+/* Second axis n of the orthotropic thermal expansion (Eq. 11, expan_mode 2),
+ * n_elems x 3.  Made orthonormal to the element's fibre m = a0 inside (its
+ * component along m is removed, then it is normalised); tled_finalize fails
+ * with TLED_E_ARG when expan_mode is 2 and no axes were given, or when an n is
+ * parallel to its m.  NULL clears.  Single problems only (a batch refuses
+ * expan_mode 2 with TLED_E_UNSUPPORTED). */
+tled_status tled_set_expansion_axes(tled_sim *sim, const double *n0);
+/* Element conductivity tensors D of Eq. 15 (cond_mode 2), n_elems x 6 in the
+ * order xx yy zz xy yz xz, W/(m K).  Used as given (fixed in space), pulled
+ * back with the total deformation as J F^-1 D F^-T (Eq. 16), and scaled by
+ * k(T)/k when ckT_on is set.  tled_finalize fails with TLED_E_ARG when
+ * cond_mode is 2 and no tensors were given.  NULL clears.  Single problems
+ * only (a batch refuses cond_mode 2 with TLED_E_UNSUPPORTED). */
+tled_status tled_set_conductivity(tled_sim *sim, const double *D);
+/* Fixed displacement components (the essential boundary condition of
+ * Section 6.1's verification model, whose right face is held in position): node[i] with
+ * mask[i] bits 0..2 = x, y, z.  Fixed components stay at zero displacement.
+ * Repeated calls accumulate. */
 tled_status tled_set_fixed_dofs(tled_sim *sim, int64_t n, const int32_t *node, const uint8_t *mask);
-/* Fixed temperatures (Dirichlet): node[i] held at T[i] (K). */
+/* Fixed temperatures: node[i] held at T[i] (K), the essential boundary
+ * condition of the Pennes equation (Eq. 1).  The paper's own cases use none:
+ * their exterior is adiabatic (Section 6.1, Table 5), which is what every
+ * boundary without a fixed temperature gets here. */
 tled_status tled_set_fixed_temperature(tled_sim *sim, int64_t n, const int32_t *node, const double *T);
 /* Regional heat source Q_r (Eq. 1) per element, W/m^3, lumped to nodes with the
  * reference volume V0/npe; active while t_on <= step*dt < t_off. */
@@ -191,8 +225,10 @@ tled_status tled_set_heat_source(tled_sim *sim, const double *q_elem, double t_o
  * D = gamma M (Eq. 21).  tled_finalize fails with TLED_E_ARG if dt exceeds
  * the critical step. */
 tled_status tled_set_time(tled_sim *sim, double dt, double damping_gamma);
-/* Critical time step min_e L_e / c_d, c_d = sqrt((kappa + 4 mu/3 + 4 eta)/rho),
- * L_e = 3 V0 / A_max (T4) or V0 / A_max (H8).  Needs mesh and material. */
+/* Critical time step of the explicit central difference (the stability limit
+ * that Section 7 discusses for the time step): min_e L_e / c_d, with
+ * c_d = sqrt((kappa + 4 mu/3 + 4 eta)/rho) and L_e = 3 V0 / A_max (T4) or
+ * V0 / A_max (H8).  Needs mesh and material. */
 tled_status tled_critical_dt(tled_sim *sim, double *dt_cr);
 
 /* Precompute (FP64 on the host: dh/dX, V0, lumped M, C, K_b, Q), reorder,
@@ -200,9 +236,24 @@ tled_status tled_critical_dt(tled_sim *sim, double *dt_cr);
  * u = v = 0, T = T0 (fixed-T nodes at their value), Prony state 0. */
 tled_status tled_finalize(tled_sim *sim);
 
-/* --- stepping ----------------------------------------------------------- */
+/* --- stepping -----------------------------------------------------------
+ * tled_step advances n_steps time steps of Section 4's loop (element physics,
+ * assembly, Eq. 20 and Eq. 27 node updates), asynchronously on the library's
+ * stream, in hipGraph chunks (tled_options.graph_steps).  Monitors are
+ * reduced at the last step of every chunk. */
 tled_status tled_step(tled_sim *sim, int64_t n_steps);
-/* Wait for the stream and report device-raised errors. */
+/* Captures and instantiates, without running anything, the hipGraphs that a
+ * following tled_step(sim, n_steps) replays: the chunk of graph_steps steps and
+ * a shorter last chunk.  A last chunk shorter than graph_steps is otherwise
+ * enqueued as eager launches unless a graph of its length is already cached
+ * (up to 8 graphs are kept per handle, least recently used first out).  For a
+ * batch only the graphs at the current step are captured (its graphs depend
+ * on the scenarios still running).  Set-up work for callers that time or
+ * repeat tled_step calls of one length. */
+tled_status tled_prepare_steps(tled_sim *sim, int64_t n_steps);
+/* Wait for the stream and report device-raised errors (non-finite values or
+ * det F <= 0, which the explicit scheme of Section 4 produces when dt is too
+ * large or an element inverts). */
 tled_status tled_sync(tled_sim *sim);
 
 /* --- outputs (synchronous; caller numbering) ----------------------------- */
@@ -300,6 +351,14 @@ tled_status tled_batch_read_all(tled_batch *b, double *u, double *T);
  * above ablation_T (e.g. 333.15 K, the 60 C isotherm). */
 tled_status tled_batch_monitors(tled_batch *b, double ablation_T, double *T_max, double *ablated_volume);
 tled_status tled_batch_get_info(tled_batch *b, tled_batch_info *out);
+
+/* --- measurement ---------------------------------------------------------
+ * Plain streaming copy of `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned device memory of GPU `device`) on `hip_stream` (NULL: the default
+ * stream): the reference bandwidth that the solver's HBM throughput is quoted
+ * against, and a kernel of known traffic for calibrating hardware counters.
+ * Asynchronous; TLED_E_ARG for a bad size or alignment. */
+tled_status tled_stream_copy(int device, void *dst, const void *src, size_t bytes, void *hip_stream);
 
 const char *tled_status_string(tled_status s);
 const char *tled_last_error(const tled_sim *sim);

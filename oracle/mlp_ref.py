@@ -65,3 +65,24 @@ def loss_and_grad(theta, x, p, target, B, cfg):
             s = 1.0 / (1.0 + np.exp(-z))
             dz = da * s * (1.0 + z * (1.0 - s))
     return loss, g
+
+
+def grad_magnitude(theta, x, p, target, B, cfg):
+    """Per-parameter magnitude of the gradient's terms, sum_n |dz_ni| |a_nj| for weights and
+    sum_n |dz_ni| for biases (FP64): the scale against which a low-precision evaluation of the
+    same sums is judged element by element."""
+    lay, K0, P = layout(**cfg)
+    y, zs, acts = forward(theta, x, p, B, cfg)
+    n, no = target.shape
+    dz = 2.0 * (y - target) / (n * no)
+    m = np.zeros(P)
+    for l in range(len(lay) - 1, -1, -1):
+        ws, wsh, bs = lay[l]
+        m[ws] = (np.abs(dz).T @ np.abs(acts[l])).ravel()
+        m[bs] = np.abs(dz).sum(0)
+        if l > 0:
+            da = dz @ theta[ws].reshape(wsh)
+            z = zs[l - 1]
+            s = 1.0 / (1.0 + np.exp(-z))
+            dz = da * s * (1.0 + z * (1.0 - s))
+    return m

@@ -11,13 +11,20 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(CSRC, "libtled.so")
-SOURCES = ["setup.cpp", "kernels.hip", "api.hip", "mlp.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "api.hip", "mlp.hip", "copy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-pthread", "-Wno-unused-command-line-argument"]
+
+
+# The solver kernels fuse a multiply and an add only inside one source expression
+# (-ffp-contract=on), never across statements: every instantiation of a kernel
+# (single problem, batch, work queue) then rounds the same way, which keeps a
+# batch's scenarios equal bit for bit to their single runs.
+SOURCE_FLAGS = {"kernels.hip": ["-ffp-contract=on"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -27,7 +34,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++"]
-        cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + HIP_FLAGS + SOURCE_FLAGS.get(src, []) + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
@@ -47,12 +54,14 @@ SOLVER_SOURCES = ("device_math.h", "kernels.h", "kernels.hip", "setup.cpp", "tle
 
 
 def source_digest(names=SOLVER_SOURCES) -> str:
-    """Hash of library sources (ties counter measurements to the kernels that produced them)."""
+    """Hash of library sources and of the flags they are compiled with (ties counter
+    measurements to the kernels that produced them)."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(names):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + f.read())
+        h.update(repr((HIP_FLAGS, SOURCE_FLAGS.get(name, []))).encode())
     return h.hexdigest()[:16]
 
 

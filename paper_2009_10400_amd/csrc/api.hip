@@ -55,10 +55,17 @@ struct tled_sim {
     double *d_part_elem = nullptr, *d_part_node = nullptr;
     int n_elem_parts = 0, n_node_parts = 0;
     int *d_new2old = nullptr;
-    hipGraphExec_t graph = nullptr;
-    int graph_k = 0;
-    int graph_np = -1;          // batch: launched patches and shared nodes baked into the graph
-    int64_t graph_ns = -1;
+    // instantiated hipGraphs of step chunks, keyed by chunk length and (batch)
+    // the launched patch and shared-node counts baked into them; least
+    // recently used first out
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        int k, np;
+        int64_t ns;
+        uint64_t used;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     int64_t step = 0;
     std::vector<float> B;   // per-node velocity coefficient (kept for state writes)
     size_t theta_floats = 0;
@@ -80,6 +87,9 @@ struct tled_sim {
     // the patch and shared-node counts of the prefix ending at the position
     std::vector<int64_t> pos_end, pos_shared_hi;
     std::vector<int32_t> pos_patch_hi;
+    // work-queue schedule: grids of the patch and shared-node kernels
+    bool queue = false;
+    int q_grid = 0, q_sgrid = 0;
 };
 
 namespace {
@@ -131,11 +141,13 @@ void *dev_alloc(tled_sim *s, size_t bytes) {
     return p;
 }
 
+void drop_graphs(tled_sim *s) {
+    for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+}
+
 void free_device(tled_sim *s) {
-    if (s->graph) {
-        (void)hipGraphExecDestroy(s->graph);
-        s->graph = nullptr;
-    }
+    drop_graphs(s);
     for (auto &b : s->bufs) {
         if (s->release) s->release(b.p, s->actx);
         else (void)hipFree(b.p);
@@ -194,13 +206,14 @@ long long first_step_at(double t, double dt) {
 KMat make_kmat(const tled_material &m, double dt) {
     KMat k{};
     k.mu = float(m.mu); k.kappa = float(m.kappa); k.eta = float(m.eta);
-    k.alpha = float(m.alpha); k.alpha_m = float(m.alpha_m); k.T0 = float(m.T0);
+    k.alpha = float(m.alpha); k.alpha_m = float(m.alpha_m); k.alpha_n = float(m.alpha_n);
     k.k = float(m.k); k.k_m = float(m.k_m);
-    k.muT_lo = float(m.muT_lo); k.muT_inv = m.muT_on ? float(1.0 / (m.muT_hi - m.muT_lo)) : 0.f;
+    // ramp starts as offsets from T0, formed in FP64 (the kernels work on dT = T - T0)
+    k.muT_off = float(m.T0 - m.muT_lo); k.muT_inv = m.muT_on ? float(1.0 / (m.muT_hi - m.muT_lo)) : 0.f;
     k.muT_drop = float(m.muT_drop);
-    k.sh_T = float(m.shrink_T); k.sh_inv = m.shrink_on ? float(1.0 / m.shrink_width) : 0.f;
+    k.sh_off = float(m.T0 - m.shrink_T); k.sh_inv = m.shrink_on ? float(1.0 / m.shrink_width) : 0.f;
     k.sh_eps = float(m.shrink_eps);
-    k.ck_lo = float(m.ckT_lo); k.ck_inv = m.ckT_on ? float(1.0 / (m.ckT_hi - m.ckT_lo)) : 0.f;
+    k.ck_off = float(m.T0 - m.ckT_lo); k.ck_inv = m.ckT_on ? float(1.0 / (m.ckT_hi - m.ckT_lo)) : 0.f;
     k.c_lo = float(m.c); k.c_hi = float(m.c_hi); k.kr_hi = m.k > 0 ? float(m.k_hi / m.k) : 1.f;
     for (int i = 0; i < 4; ++i) {
         if (i < m.n_prony) {
@@ -224,7 +237,7 @@ NodeParams make_nparams(const HostProblem &pr, const KMat &k, double abl_T) {
     p.T0 = float(m.T0);
     p.rho = float(m.rho);
     p.abl_T = float(abl_T);
-    p.ck_lo = k.ck_lo; p.ck_inv = k.ck_inv; p.c_lo = k.c_lo; p.c_hi = k.c_hi;
+    p.ck_off = k.ck_off; p.ck_inv = k.ck_inv; p.c_lo = k.c_lo; p.c_hi = k.c_hi;
     p.ckT_on = m.ckT_on;
     p.n_on = first_step_at(pr.t_on, dt);
     p.n_off = first_step_at(pr.t_off, dt);
@@ -274,6 +287,22 @@ tled_status upload_all(tled_sim *s) {
             h1[e] = make_float4(float(h[4]), float(h[5]), float(h[6]), float(h[7]));
             h2[e] = make_float4(float(h[8]), float(h[9]), float(h[10]), float(h[11]));
             khg[e] = float(pc.khg[e]);
+        }
+    }
+    // anisotropy plane (orthotropic expansion axis, conductivity tensor): two
+    // float4 per element, only when a mode reads it
+    std::vector<float4> aniso;
+    const tled_material &m0 = s->scen[0].mat;
+    if (m0.expan_mode == 2 || m0.cond_mode == 2) {
+        aniso.assign(2 * size_t(ne), make_float4(0.f, 0.f, 0.f, 0.f));
+        for (int64_t e = 0; e < ne; ++e) {
+            float nx = 0.f, ny = 0.f;
+            if (m0.expan_mode == 2) oct_encode(&pc.n0[3 * e], &nx, &ny);
+            float d[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (m0.cond_mode == 2)
+                for (int i = 0; i < 6; ++i) d[i] = float(pc.Dc[6 * e + i]);
+            aniso[2 * e] = make_float4(nx, ny, d[0], d[1]);
+            aniso[2 * e + 1] = make_float4(d[2], d[3], d[4], d[5]);
         }
     }
     // node arrays (each node with the constants of its scenario)
@@ -337,6 +366,11 @@ tled_status upload_all(tled_sim *s) {
     TRY(zeros(s, &s->d_mon, 1));
 
     t.g0 = cg0; t.g1 = cg1; t.g2 = cg2; t.hg0 = chg0; t.hg1 = chg1; t.hg2 = chg2; t.khg = ckhg;
+    if (!aniso.empty()) {
+        float4 *dan;
+        TRY(upload(s, &dan, aniso));
+        t.aniso = dan;
+    }
     t.nu4 = dnu4; t.nv4 = dnv4; t.nth = dnth; t.mask = dmask; t.Vl = dVl; t.theta = dtheta;
     t.step_base = s->d_step;
     t.status = s->d_status;
@@ -385,6 +419,7 @@ tled_status upload_all(tled_sim *s) {
         TRY(upload(s, &u16, P.lpos)); a.lpos = u16;
         a.nu4 = dnu4; a.nv4 = dnv4; a.nth = dnth; a.mask = dmask; a.Vl = dVl; a.theta = dtheta;
         a.g0 = cg0; a.g1 = cg1; a.g2 = cg2; a.hg0 = chg0; a.hg1 = chg1; a.hg2 = chg2; a.khg = ckhg;
+        a.aniso = t.aniso;
         float4 *dpart;
         TRY(zeros(s, &dpart, std::max<size_t>(P.shared_ids.size(), 1)));
         a.partial = dpart;
@@ -392,6 +427,17 @@ tled_status upload_all(tled_sim *s) {
         a.status = s->d_status;
         s->n_elem_parts = P.n;
         s->n_node_parts = P.n + int((a.n_shared + kBlock - 1) / kBlock);
+        if (s->queue) {
+            // as many patch workgroups as are resident at once (never more than the patches);
+            // the shared-node kernel's fixed grid strides over the nodes
+            int cus = 0;
+            HIPCHK(s, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device));
+            const int occ = patch_queue_occupancy(npe, s->np, s->variant == 2, a);
+            if (occ <= 0) return fail(s, TLED_E_HIP, "work-queue patch kernel does not fit on a CU");
+            s->q_grid = std::max(1, std::min(a.n_patches, occ * cus));
+            s->q_sgrid = int(std::max<int64_t>(1, std::min<int64_t>((a.n_shared + kBlock - 1) / kBlock, 8 * cus)));
+            s->n_node_parts = P.n + s->q_sgrid;
+        }
         TRY(zeros(s, &s->d_part_elem, s->n_elem_parts));
         TRY(zeros(s, &s->d_part_node, size_t(4) * s->n_node_parts));
         a.part_elem = s->d_part_elem;
@@ -414,6 +460,22 @@ tled_status upload_all(tled_sim *s) {
         TRY(upload(s, &dl, end)); a.scen_end = dl;
         TRY(upload(s, &s->d_ranges, rng));
         TRY(zeros(s, &s->d_scen_mon, 2 * S));
+        if (s->queue) {
+            int *dq;
+            TRY(zeros(s, &dq, kNumXcd));
+            a.queue = dq;
+            std::vector<long long> pe(s->pos_end.begin(), s->pos_end.end()), ps(s->pos_shared_hi.begin(),
+                                                                                s->pos_shared_hi.end());
+            long long *dpe, *dps;
+            TRY(upload(s, &dpe, pe));
+            TRY(upload(s, &dps, ps));
+            TRY(upload(s, &d, s->pos_patch_hi));
+            a.pos_end = dpe; a.pos_shared_hi = dps; a.pos_patch_hi = d;
+            a.n_pos = int(pe.size());
+            long long *dqc;
+            TRY(zeros(s, &dqc, 4));
+            a.qcount = dqc;
+        }
     }
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return TLED_OK;
@@ -440,12 +502,27 @@ void single_scenario(tled_sim *s) {
 void active_counts(const tled_sim *s, int64_t step, int *n_patches, int64_t *n_shared) {
     *n_patches = s->pa.n_patches;
     *n_shared = s->pa.n_shared;
-    if (!s->is_batch || s->pos_end.empty()) return;
+    if (!s->is_batch || s->queue || s->pos_end.empty()) return;   // the work queue counts on the device
     const auto it = std::partition_point(s->pos_end.begin(), s->pos_end.end(), [&](int64_t e) { return e > step; });
     const size_t m = size_t(it - s->pos_end.begin());
     // never more than the union holds (a batch may have no shared node at all)
     *n_patches = std::min(s->pa.n_patches, std::max(1, m ? s->pos_patch_hi[m - 1] : 0));
     *n_shared = std::min<int64_t>(s->pa.n_shared, std::max<int64_t>(1, m ? s->pos_shared_hi[m - 1] : 0));
+}
+
+// Work-queue schedule: the running scenarios' patch and shared-node counts of
+// step `step`, written into that step's parity slot (the kernels keep the slots
+// current from then on).  Asynchronous on the library's stream; `h` must stay
+// alive until the stream has passed the copy.
+tled_status set_queue_counts(tled_sim *s, int64_t step, long long h[2]) {
+    if (!s->queue) return TLED_OK;
+    const auto it = std::partition_point(s->pos_end.begin(), s->pos_end.end(), [&](int64_t e) { return e > step; });
+    const size_t m = size_t(it - s->pos_end.begin());
+    h[0] = m ? s->pos_patch_hi[m - 1] : 0;
+    h[1] = m ? s->pos_shared_hi[m - 1] : 0;
+    HIPCHK(s, hipMemcpyAsync(s->pa.qcount + 2 * (step & 1), h, 2 * sizeof(long long), hipMemcpyHostToDevice,
+                             s->stream));
+    return TLED_OK;
 }
 
 // Enqueue a chunk of k steps (eager, or under stream capture) starting at step
@@ -476,6 +553,11 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
             t0 = LaunchTiming{(*ev)[4 * j], (*ev)[4 * j + 1]};
             t1 = LaunchTiming{(*ev)[4 * j + 2], (*ev)[4 * j + 3]};
         }
+        if (s->queue) {
+            launch_patch_queue(npe, s->np, mon, s->variant == 2, s->pa, j, s->q_grid, s->stream, ev ? &t0 : nullptr);
+            launch_shared_nodes_queue(mon, s->pa, j, s->q_sgrid, s->stream, ev ? &t1 : nullptr);
+            continue;
+        }
         if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
         else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, pa, j, s->stream, ev ? &t0 : nullptr);
         if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream, ev ? &t1 : nullptr);
@@ -494,7 +576,22 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
     return TLED_OK;
 }
 
-tled_status build_graph(tled_sim *s, int k, int64_t step0) {
+constexpr size_t kMaxGraphs = 8;
+
+// The cached graph of a k-step chunk starting at step0, or null.
+hipGraphExec_t find_graph(tled_sim *s, int k, int64_t step0) {
+    int np;
+    int64_t ns;
+    active_counts(s, step0, &np, &ns);
+    for (auto &g : s->graphs)
+        if (g.k == k && g.np == np && g.ns == ns) {
+            g.used = ++s->graph_clock;
+            return g.exec;
+        }
+    return nullptr;
+}
+
+tled_status build_graph(tled_sim *s, int k, int64_t step0, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
     HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     tled_status st = enqueue_chunk(s, k, step0, true);
@@ -504,15 +601,34 @@ tled_status build_graph(tled_sim *s, int k, int64_t step0) {
         return st;
     }
     if (e != hipSuccess) return fail(s, TLED_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(s, TLED_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    // move the graph's launch data to the device now, not at its first launch
+    e = hipGraphUpload(exec, s->stream);
     if (e != hipSuccess) {
-        s->graph = nullptr;
-        return fail(s, TLED_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        (void)hipGraphExecDestroy(exec);
+        return fail(s, TLED_E_HIP, std::string("hipGraphUpload: ") + hipGetErrorString(e));
     }
-    s->graph_k = k;
-    active_counts(s, step0, &s->graph_np, &s->graph_ns);
+    if (s->graphs.size() >= kMaxGraphs) {
+        auto lru = std::min_element(s->graphs.begin(), s->graphs.end(),
+                                    [](const tled_sim::GraphEntry &a, const tled_sim::GraphEntry &b) {
+                                        return a.used < b.used;
+                                    });
+        (void)hipGraphExecDestroy(lru->exec);
+        s->graphs.erase(lru);
+    }
+    tled_sim::GraphEntry ge{exec, k, 0, 0, ++s->graph_clock};
+    active_counts(s, step0, &ge.np, &ge.ns);
+    s->graphs.push_back(ge);
+    *out = exec;
     return TLED_OK;
+}
+
+tled_status get_graph(tled_sim *s, int k, int64_t step0, hipGraphExec_t *out) {
+    *out = find_graph(s, k, step0);
+    return *out ? TLED_OK : build_graph(s, k, step0, out);
 }
 
 tled_status check_status(tled_sim *s) {
@@ -635,16 +751,16 @@ tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
     if (opt->reorder < -1 || opt->reorder > 2) return fail(sim, TLED_E_ARG, "reorder must be -1..2");
     if (opt->block_size != 0 && opt->block_size != 256 && opt->block_size != 512)
         return fail(sim, TLED_E_UNSUPPORTED, "block_size must be 256 or 512");
+    if (opt->batch_schedule < 0 || opt->batch_schedule > 1) return fail(sim, TLED_E_ARG, "batch_schedule must be 0 or 1");
+    if (opt->batch_schedule == 1 && !sim->is_batch)
+        return fail(sim, TLED_E_ARG, "batch_schedule 1 (work queue) is for batch handles");
     if (sim->finalized && (opt->kernel_variant != sim->opt.kernel_variant || opt->reorder != sim->opt.reorder ||
-                           opt->patch_elems != sim->opt.patch_elems))
+                           opt->patch_elems != sim->opt.patch_elems || opt->batch_schedule != sim->opt.batch_schedule))
         return fail(sim, TLED_E_STATE, "layout options must be set before tled_finalize");
-    int old_k = sim->opt.graph_steps;
     sim->opt = *opt;
-    if (sim->opt.graph_steps == 0) sim->opt.graph_steps = sim->is_batch ? -1 : 50;
-    if (sim->finalized && sim->opt.graph_steps != old_k && sim->graph) {
-        (void)hipGraphExecDestroy(sim->graph);
-        sim->graph = nullptr;
-    }
+    if (sim->opt.graph_steps == 0) sim->opt.graph_steps = !sim->is_batch ? 50 : (sim->opt.batch_schedule == 1 ? 100 : -1);
+    // captured graphs hold the kernel constants by value: capture again
+    if (sim->finalized) drop_graphs(sim);
     if (sim->finalized) {
         build_kernel_constants(sim);
         if (sim->device >= 0 && sim->d_km) {
@@ -674,6 +790,8 @@ tled_status tled_set_mesh(tled_sim *sim, int elem_type, int64_t n_nodes, const d
         if (!std::isfinite(p.X[i])) return fail(sim, TLED_E_ARG, "non-finite coordinate");
     p.conn.assign(conn, conn + elem_type * n_elems);
     p.a0.clear();
+    p.n0.clear();
+    p.Dc.clear();
     p.q.clear();
     p.fix.assign(n_nodes, 0);
     p.Tfix.assign(n_nodes, 0.0);
@@ -694,6 +812,24 @@ tled_status tled_set_fibres(tled_sim *sim, const double *a0) {
     if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
     if (!a0) { sim->prob.a0.clear(); return TLED_OK; }
     sim->prob.a0.assign(a0, a0 + 3 * sim->prob.ne);
+    return TLED_OK;
+}
+
+tled_status tled_set_expansion_axes(tled_sim *sim, const double *n0) {
+    TRY(need_single_setup(sim));
+    if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
+    if (!n0) { sim->prob.n0.clear(); return TLED_OK; }
+    sim->prob.n0.assign(n0, n0 + 3 * sim->prob.ne);
+    for (double v : sim->prob.n0)
+        if (!std::isfinite(v)) { sim->prob.n0.clear(); return fail(sim, TLED_E_ARG, "non-finite expansion axis"); }
+    return TLED_OK;
+}
+
+tled_status tled_set_conductivity(tled_sim *sim, const double *D) {
+    TRY(need_single_setup(sim));
+    if (!sim->prob.have_mesh) return fail(sim, TLED_E_STATE, "set the mesh first");
+    if (!D) { sim->prob.Dc.clear(); return TLED_OK; }
+    sim->prob.Dc.assign(D, D + 6 * sim->prob.ne);
     return TLED_OK;
 }
 
@@ -771,6 +907,9 @@ tled_status tled_finalize(tled_sim *sim) {
                          : default_patch_elems(sim->prob.npe, sim->prob.ne, sim->opt.block_size);
     if (sim->opt.block_size == 512 && sim->prob.npe == 8)
         return fail(sim, TLED_E_UNSUPPORTED, "block_size 512 is for T4 meshes only");
+    if (sim->opt.block_size == 512 && (sim->prob.mat.expan_mode == 2 || sim->prob.mat.cond_mode == 2))
+        return fail(sim, TLED_E_UNSUPPORTED,
+                    "block_size 512 is not available with orthotropic expansion or tensor conduction");
     tled_status st = precompute(sim->prob, so, &sim->pc, &sim->err);
     if (st != TLED_OK) return st;
     if (sim->prob.dt > sim->pc.dt_cr)
@@ -814,16 +953,20 @@ tled_status tled_step(tled_sim *sim, int64_t n_steps) {
         while (left >= k) {
             // a batch's graph launches the prefix of scenarios running at its
             // first step: captured again when that prefix has changed
-            int np;
-            int64_t ns;
-            active_counts(sim, cur, &np, &ns);
-            if (!sim->graph || sim->graph_k != k || sim->graph_np != np || sim->graph_ns != ns) {
-                if (sim->graph) { (void)hipGraphExecDestroy(sim->graph); sim->graph = nullptr; }
-                TRY(build_graph(sim, k, cur));
-            }
-            HIPCHK(sim, hipGraphLaunch(sim->graph, sim->stream));
+            hipGraphExec_t g;
+            TRY(get_graph(sim, k, cur, &g));
+            HIPCHK(sim, hipGraphLaunch(g, sim->stream));
             left -= k;
             cur += k;
+        }
+        // a shorter last chunk replays a graph of its length when one is cached
+        // (tled_prepare_steps captures it), else it is enqueued eagerly
+        if (left > 0) {
+            if (hipGraphExec_t g = find_graph(sim, int(left), cur)) {
+                HIPCHK(sim, hipGraphLaunch(g, sim->stream));
+                cur += left;
+                left = 0;
+            }
         }
     }
     const int chunk = k > 0 ? k : 100;
@@ -834,6 +977,22 @@ tled_status tled_step(tled_sim *sim, int64_t n_steps) {
         cur += c;
     }
     sim->step += n_steps;
+    return TLED_OK;
+}
+
+tled_status tled_prepare_steps(tled_sim *sim, int64_t n_steps) {
+    TRY(need_device(sim));
+    if (n_steps < 0) return fail(sim, TLED_E_ARG, "negative step count");
+    const int k = sim->opt.graph_steps;
+    if (k <= 0 || n_steps == 0) return TLED_OK;
+    hipGraphExec_t g;
+    const int64_t full = n_steps / k, rest = n_steps % k;
+    int64_t cur = sim->step;
+    if (full > 0) TRY(get_graph(sim, k, cur, &g));
+    if (rest > 0) {
+        // a batch's prefix may differ at the last chunk: capture at the step it starts
+        TRY(get_graph(sim, int(rest), cur + full * k, &g));
+    }
     return TLED_OK;
 }
 
@@ -1077,6 +1236,8 @@ tled_status tled_set_state(tled_sim *sim, const void *buf) {
                                    hipMemcpyHostToDevice, sim->stream));
     HIPCHK(sim, hipMemcpyAsync(sim->d_step, &st, sizeof(st), hipMemcpyHostToDevice, sim->stream));
     HIPCHK(sim, hipMemcpyAsync(sim->d_status, &status, sizeof(status), hipMemcpyHostToDevice, sim->stream));
+    long long qc[2];
+    TRY(set_queue_counts(sim, st, qc));
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
     sim->step = st;
     return TLED_OK;
@@ -1111,6 +1272,8 @@ tled_status tled_batch_add(tled_batch *b, int elem_type, int64_t n_nodes, const 
     if (!b->scen.empty() && b->scen[0].npe != elem_type) return fail(b, TLED_E_ARG, "a batch needs one element type");
     if (!b->scen.empty() && b->scen[0].mat.n_prony != m->n_prony)
         return fail(b, TLED_E_ARG, "a batch needs one Prony term count");
+    if (m->expan_mode == 2 || m->cond_mode == 2)
+        return fail(b, TLED_E_UNSUPPORTED, "orthotropic expansion and tensor conduction are single-problem options");
     HostProblem p;
     p.npe = elem_type; p.nn = n_nodes; p.ne = n_elems;
     p.X.assign(X, X + 3 * n_nodes);
@@ -1221,6 +1384,9 @@ tled_status tled_batch_finalize(tled_batch *b) {
         // not a prefix order (cannot happen: the union was ordered by these end steps): launch everything
         if (!std::is_sorted(b->pos_end.begin(), b->pos_end.end(), std::greater<int64_t>())) b->pos_end.clear();
     }
+    b->queue = b->opt.batch_schedule == 1;
+    if (b->queue && (b->pos_end.empty() || v != 2 && v != 3))
+        return fail(b, TLED_E_STATE, "the work-queue schedule needs the fused kernels and end-step ordered scenarios");
     b->variant = v;
     b->prob = b->scen[0];
     b->prob.nn = b->pc.nn;
@@ -1233,6 +1399,13 @@ tled_status tled_batch_finalize(tled_batch *b) {
             b->own_stream = true;
         }
         st = upload_all(b);
+        if (st != TLED_OK) {
+            free_device(b);
+            return st;
+        }
+        long long qc[2];
+        st = set_queue_counts(b, 0, qc);
+        if (st == TLED_OK && hipStreamSynchronize(b->stream) != hipSuccess) st = fail(b, TLED_E_HIP, "stream sync");
         if (st != TLED_OK) {
             free_device(b);
             return st;

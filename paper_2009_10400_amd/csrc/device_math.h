@@ -17,12 +17,15 @@ namespace tled {
 // Kernel-side material constants (single precision, derived on the host).
 struct KMat {
     float mu, kappa, eta;         // moduli at T0
-    float alpha, alpha_m;         // expansion coefficients (alpha_m: along the fibre)
-    float T0;
+    float alpha, alpha_m, alpha_n; // expansion coefficients (alpha_m: along the fibre m, alpha_n: along n)
     float k, k_m;                 // conductivities
-    float muT_lo, muT_inv, muT_drop;
-    float sh_T, sh_inv, sh_eps;
-    float ck_lo, ck_inv;          // c(T), k(T) ramp
+    // Temperature laws are evaluated on the rise dT = T - T0 with the ramp start
+    // as an offset from T0 formed in FP64 on the host (off = T0 - T_start): an
+    // absolute temperature in FP32 is quantised to 3e-5 K near 310 K, which the
+    // steep shrinkage ramp would turn into strain errors.
+    float muT_off, muT_inv, muT_drop;
+    float sh_off, sh_inv, sh_eps;
+    float ck_off, ck_inv;         // c(T), k(T) ramp
     float c_lo, c_hi, kr_hi;      // c at lo/hi; k_hi / k
     float pc1[4], pc2[4];         // Prony: dt g/(dt + tau), tau/(dt + tau)
     float hgk;                    // hourglass: hg_coef (kappa + 4 mu / 3)
@@ -91,31 +94,55 @@ struct ElemOut {
     float Jmin;
 };
 
-// Thermal stretch (Section 3.2): lambda - 1 = alpha dT, times the optional
-// shrinkage factor; returns lambda_i - 1 and lambda_m - 1.
-__device__ __forceinline__ void stretch_m1(const KMat &m, float dTe, float &li1, float &lm1) {
-    float Te = m.T0 + dTe;
-    float a = m.alpha * dTe;
-    float b = (m.expan_mode == 1) ? m.alpha_m * dTe : a;
+// Thermal stretch (Section 3.2): lambda - 1 = alpha dT for the expansion
+// coefficient of one axis, times the optional shrinkage factor.
+__device__ __forceinline__ float stretch_m1(const KMat &m, float alpha, float dTe) {
+    float a = alpha * dTe;
     if (m.shrink_on) {
-        float s1 = m.sh_eps * clamp01f((Te - m.sh_T) * m.sh_inv);
+        const float s1 = m.sh_eps * clamp01f((dTe + m.sh_off) * m.sh_inv);
         a = a + s1 + s1 * a;
-        b = b + s1 + s1 * b;
     }
-    li1 = a;
-    lm1 = b;
+    return a;
+}
+
+// Octahedral decoding of a unit vector stored as two floats.
+__device__ __forceinline__ void oct_decode(float x, float y, float a[3]) {
+    float z = 1.0f - fabsf(x) - fabsf(y);
+    float t = fmaxf(-z, 0.0f);
+    x += (x >= 0.0f) ? -t : t;
+    y += (y >= 0.0f) ? -t : t;
+    float r = rsqrtf(x * x + y * y + z * z);
+    a[0] = x * r; a[1] = y * r; a[2] = z * r;
+}
+
+// He += beta (F v) (x) v for a unit axis v (F = I + H): one axis term of
+// F F_th^-1 with F_th^-1 = I / lambda_i + sum_v beta_v v (x) v (Eq. 11).
+__device__ __forceinline__ void add_axis_term(float He[9], const float H[9], const float v[3], float beta) {
+    const float Fv[3] = {v[0] + H[0] * v[0] + H[1] * v[1] + H[2] * v[2],
+                         v[1] + H[3] * v[0] + H[4] * v[1] + H[5] * v[2],
+                         v[2] + H[6] * v[0] + H[7] * v[1] + H[8] * v[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) He[3 * i + j] += beta * Fv[i] * v[j];
 }
 
 // Per-element physics.  H: displacement gradient (row-major), gT: reference
 // temperature gradient, dTe: element temperature rise over T0, a: unit fibre,
-// theta: Prony state (n_prony x 6, updated in place).
-template <int NP>
+// theta: Prony state (n_prony x 6, updated in place), aniso + 2 e: the
+// element's two float4 of anisotropy data (second expansion axis in
+// octahedral coordinates, conductivity tensor: (n.x, n.y, Dxx, Dyy),
+// (Dzz, Dxy, Dyz, Dxz)), read only inside the orthotropic expansion and tensor
+// conduction branches.  ANISO = false compiles those two modes out (the
+// kernels for every other mode then keep the register budget of the
+// isotropic and transversely isotropic code); ANISO = true handles every mode.
+template <int NP, bool ANISO>
 __device__ __forceinline__ void element_physics(const KMat &m, const float H[9], const float gT[3],
                                                 float dTe, const float a[3], float V0, float *theta,
-                                                bool want_psi, ElemOut &o) {
+                                                bool want_psi, ElemOut &o, const float4 *__restrict__ aniso,
+                                                int e) {
     // ---- thermal split, Eqs. 7-8, 11
-    float li1, lm1;
-    stretch_m1(m, dTe, li1, lm1);
+    const float li1 = stretch_m1(m, m.alpha, dTe);
     const float li = 1.0f + li1, inv_li = rcp(li);
     float He[9];
 #pragma unroll
@@ -124,18 +151,25 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     He[4] -= li1 * inv_li;
     He[8] -= li1 * inv_li;
     float beta = 0.0f, lm = 1.0f;
-    if (m.expan_mode == 1) {
-        // F_e = F/li + beta (F a) (x) a, beta = 1/lm - 1/li = (li1 - lm1)/(li lm)
-        lm = 1.0f + lm1;
-        beta = (li1 - lm1) * inv_li * rcp(lm);
-        float Fa0 = a[0] + H[0] * a[0] + H[1] * a[1] + H[2] * a[2];
-        float Fa1 = a[1] + H[3] * a[0] + H[4] * a[1] + H[5] * a[2];
-        float Fa2 = a[2] + H[6] * a[0] + H[7] * a[1] + H[8] * a[2];
-        float Fa[3] = {Fa0, Fa1, Fa2};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) He[3 * i + j] += beta * Fa[i] * a[j];
+    if (!ANISO) {
+        if (m.expan_mode == 1) {
+            // F_e = F/li + beta (F a) (x) a, beta = 1/lm - 1/li = (li1 - lm1)/(li lm)
+            const float lm1 = stretch_m1(m, m.alpha_m, dTe);
+            lm = 1.0f + lm1;
+            beta = (li1 - lm1) * inv_li * rcp(lm);
+            add_axis_term(He, H, a, beta);
+        }
+    } else if (m.expan_mode != 0) {
+        // F_e = F/li + b_m (F m) (x) m [+ b_n (F n) (x) n], b = 1/l - 1/li = (li1 - l1)/(li l)
+        const float lm1 = stretch_m1(m, m.alpha_m, dTe);
+        add_axis_term(He, H, a, (li1 - lm1) * inv_li * rcp(1.0f + lm1));
+        if (m.expan_mode == 2) {
+            float nv[3];
+            const float4 q = aniso[2 * size_t(e)];
+            oct_decode(q.x, q.y, nv);
+            const float ln1 = stretch_m1(m, m.alpha_n, dTe);
+            add_axis_term(He, H, nv, (li1 - ln1) * inv_li * rcp(1.0f + ln1));
+        }
     }
     // ---- Green strain of the elastic part
     Sym3 E;
@@ -158,7 +192,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     Sym3 dev{E.xx - trE * (1.0f / 3.0f), E.yy - trE * (1.0f / 3.0f), E.zz - trE * (1.0f / 3.0f), E.xy, E.yz, E.xz};
     Sym3 M = sym_prod(Ci, dev);  // C^-1 dev E  (= (I - I1/3 C^-1)/2)
     float scale = 1.0f;
-    if (m.muT_on) scale = 1.0f - m.muT_drop * clamp01f((m.T0 + dTe - m.muT_lo) * m.muT_inv);
+    if (m.muT_on) scale = 1.0f - m.muT_drop * clamp01f((dTe + m.muT_off) * m.muT_inv);
     const float mu = m.mu * scale, eta = m.eta * scale;
     const float aEa = a[0] * (E.xx * a[0] + E.xy * a[1] + E.xz * a[2]) +
                       a[1] * (E.xy * a[0] + E.yy * a[1] + E.yz * a[2]) +
@@ -181,7 +215,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     if (m.expan_mode == 0) {
         detFth = li * li * li;
         S.xx *= li; S.yy *= li; S.zz *= li; S.xy *= li; S.yz *= li; S.xz *= li;
-    } else {
+    } else if (!ANISO) {
         // det(Fth) Fth^-1 S Fth^-T, Fth^-1 = I/li + beta a(x)a
         detFth = li * li * lm;
         float Sa[3] = {S.xx * a[0] + S.xy * a[1] + S.xz * a[2], S.xy * a[0] + S.yy * a[1] + S.yz * a[2],
@@ -194,6 +228,36 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
                  c0 * S.xy + c1 * (a[0] * Sa[1] + Sa[0] * a[1]) + c2 * a[0] * a[1],
                  c0 * S.yz + c1 * (a[1] * Sa[2] + Sa[1] * a[2]) + c2 * a[1] * a[2],
                  c0 * S.xz + c1 * (a[0] * Sa[2] + Sa[0] * a[2]) + c2 * a[0] * a[2]};
+    } else {
+        // det(Fth) P S P with P = Fth^-1 = I/li + b_m m (x) m + b_n n (x) n (m = a; b_n = 0
+        // in the transversely isotropic mode):
+        //   P S P = S/li^2 + (1/li) sum_v b_v (v (S v)^T + (S v) v^T) + sum_{v,w} b_v b_w (v.S w) v (x) w
+        const float lm1 = stretch_m1(m, m.alpha_m, dTe), lm = 1.0f + lm1;
+        const float bm = (li1 - lm1) * inv_li * rcp(lm);
+        float nv[3] = {0.0f, 0.0f, 0.0f}, bn = 0.0f, ln = li;
+        if (m.expan_mode == 2) {
+            const float4 q = aniso[2 * size_t(e)];
+            oct_decode(q.x, q.y, nv);
+            const float ln1 = stretch_m1(m, m.alpha_n, dTe);
+            ln = 1.0f + ln1;
+            bn = (li1 - ln1) * inv_li * rcp(ln);
+        }
+        detFth = li * lm * ln;
+        const float Sa[3] = {S.xx * a[0] + S.xy * a[1] + S.xz * a[2], S.xy * a[0] + S.yy * a[1] + S.yz * a[2],
+                             S.xz * a[0] + S.yz * a[1] + S.zz * a[2]};
+        const float Sn[3] = {S.xx * nv[0] + S.xy * nv[1] + S.xz * nv[2], S.xy * nv[0] + S.yy * nv[1] + S.yz * nv[2],
+                             S.xz * nv[0] + S.yz * nv[1] + S.zz * nv[2]};
+        const float aSa = a[0] * Sa[0] + a[1] * Sa[1] + a[2] * Sa[2];
+        const float nSn = nv[0] * Sn[0] + nv[1] * Sn[1] + nv[2] * Sn[2];
+        const float aSn = a[0] * Sn[0] + a[1] * Sn[1] + a[2] * Sn[2];
+        const float c0 = detFth * inv_li * inv_li, cm = detFth * bm * inv_li, cn = detFth * bn * inv_li;
+        const float cmm = detFth * bm * bm * aSa, cnn = detFth * bn * bn * nSn, cmn = detFth * bm * bn * aSn;
+#define TLED_PSP(i, j)                                                                                       \
+    (cm * (a[i] * Sa[j] + Sa[i] * a[j]) + cn * (nv[i] * Sn[j] + Sn[i] * nv[j]) + cmm * a[i] * a[j] +            \
+     cnn * nv[i] * nv[j] + cmn * (a[i] * nv[j] + nv[i] * a[j]))
+        S = Sym3{c0 * S.xx + TLED_PSP(0, 0), c0 * S.yy + TLED_PSP(1, 1), c0 * S.zz + TLED_PSP(2, 2),
+                 c0 * S.xy + TLED_PSP(0, 1), c0 * S.yz + TLED_PSP(1, 2), c0 * S.xz + TLED_PSP(0, 2)};
+#undef TLED_PSP
     }
     if (want_psi) {
         float I1b3 = 3.0f * j23m1 + 2.0f * j23 * trE;  // I1bar - 3
@@ -225,7 +289,7 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
     const float Jt1 = det_m1(H);
     const float Jt = 1.0f + Jt1;
     float kscale = 1.0f;
-    if (m.ckT_on) kscale = 1.0f + clamp01f((m.T0 + dTe - m.ck_lo) * m.ck_inv) * (m.kr_hi - 1.0f);
+    if (m.ckT_on) kscale = 1.0f + clamp01f((dTe + m.ck_off) * m.ck_inv) * (m.kr_hi - 1.0f);
     float K[6];
     if (m.cond_mode == 0) {
         // J k C^-1 = k adj(C) / J with C = I + H + H^T + H^T H
@@ -239,37 +303,48 @@ __device__ __forceinline__ void element_physics(const KMat &m, const float H[9],
         const float f = m.k * kscale * rcp(Jt);
         K[0] = f * A.xx; K[1] = f * A.yy; K[2] = f * A.zz; K[3] = f * A.xy; K[4] = f * A.yz; K[5] = f * A.xz;
     } else {
-        // adj(F) D adj(F)^T / J, D = k I + (k_m - k) a a
+        // adj(F) D adj(F)^T / J
         const float F[9] = {1.0f + H[0], H[1], H[2], H[3], 1.0f + H[4], H[5], H[6], H[7], 1.0f + H[8]};
         float Ad[9] = {F[4] * F[8] - F[5] * F[7], F[2] * F[7] - F[1] * F[8], F[1] * F[5] - F[2] * F[4],
                        F[5] * F[6] - F[3] * F[8], F[0] * F[8] - F[2] * F[6], F[2] * F[3] - F[0] * F[5],
                        F[3] * F[7] - F[4] * F[6], F[1] * F[6] - F[0] * F[7], F[0] * F[4] - F[1] * F[3]};
-        const float kk = m.k * kscale, km = m.k_m * kscale, iJt = rcp(Jt);
-        float Aa[3] = {Ad[0] * a[0] + Ad[1] * a[1] + Ad[2] * a[2], Ad[3] * a[0] + Ad[4] * a[1] + Ad[5] * a[2],
-                       Ad[6] * a[0] + Ad[7] * a[1] + Ad[8] * a[2]};
+        const float iJt = rcp(Jt);
         float r[3][3];
+        if (!ANISO || m.cond_mode == 1) {
+            // D = k I + (k_m - k) a a
+            const float kk = m.k * kscale, km = m.k_m * kscale;
+            float Aa[3] = {Ad[0] * a[0] + Ad[1] * a[1] + Ad[2] * a[2], Ad[3] * a[0] + Ad[4] * a[1] + Ad[5] * a[2],
+                           Ad[6] * a[0] + Ad[7] * a[1] + Ad[8] * a[2]};
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                r[i][j] = (kk * (Ad[3 * i] * Ad[3 * j] + Ad[3 * i + 1] * Ad[3 * j + 1] + Ad[3 * i + 2] * Ad[3 * j + 2]) +
-                           (km - kk) * Aa[i] * Aa[j]) * iJt;
+                for (int j = 0; j < 3; ++j)
+                    r[i][j] = (kk * (Ad[3 * i] * Ad[3 * j] + Ad[3 * i + 1] * Ad[3 * j + 1] +
+                                     Ad[3 * i + 2] * Ad[3 * j + 2]) +
+                               (km - kk) * Aa[i] * Aa[j]) * iJt;
+        } else {
+            // the element's tensor D (times k(T)/k)
+            const float4 d0 = aniso[2 * size_t(e)], d1 = aniso[2 * size_t(e) + 1];
+            const float Dm[9] = {d0.z, d1.y, d1.w, d1.y, d0.w, d1.z, d1.w, d1.z, d1.x};
+            float AD[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    AD[3 * i + j] = Ad[3 * i] * Dm[j] + Ad[3 * i + 1] * Dm[3 + j] + Ad[3 * i + 2] * Dm[6 + j];
+            const float f = kscale * iJt;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    r[i][j] = (AD[3 * i] * Ad[3 * j] + AD[3 * i + 1] * Ad[3 * j + 1] + AD[3 * i + 2] * Ad[3 * j + 2]) * f;
+        }
         K[0] = r[0][0]; K[1] = r[1][1]; K[2] = r[2][2]; K[3] = r[0][1]; K[4] = r[1][2]; K[5] = r[0][2];
     }
     o.qV[0] = V0 * (K[0] * gT[0] + K[3] * gT[1] + K[5] * gT[2]);
     o.qV[1] = V0 * (K[3] * gT[0] + K[1] * gT[1] + K[4] * gT[2]);
     o.qV[2] = V0 * (K[5] * gT[0] + K[4] * gT[1] + K[2] * gT[2]);
     o.Jmin = fminf(J, Jt);
-}
-
-// Octahedral decoding of a unit vector stored as two floats.
-__device__ __forceinline__ void oct_decode(float x, float y, float a[3]) {
-    float z = 1.0f - fabsf(x) - fabsf(y);
-    float t = fmaxf(-z, 0.0f);
-    x += (x >= 0.0f) ? -t : t;
-    y += (y >= 0.0f) ? -t : t;
-    float r = rsqrtf(x * x + y * y + z * z);
-    a[0] = x * r; a[1] = y * r; a[2] = z * r;
 }
 
 }  // namespace tled

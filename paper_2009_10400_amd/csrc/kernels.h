@@ -22,7 +22,7 @@ struct NodeParams {
     float T0;
     float rho;
     float abl_T;      // ablation threshold temperature, K
-    float ck_lo, ck_inv, c_lo, c_hi;   // c(T) law (when ckT_on)
+    float ck_off, ck_inv, c_lo, c_hi;  // c(T) law (when ckT_on) on dT: ramp start offset T0 - ckT_lo (FP64 -> FP32)
     int ckT_on;
     long long n_on, n_off;             // source active for n_on <= step < n_off
 };
@@ -48,6 +48,7 @@ struct TwoPassArgs {
     float *theta;
     float4 *out;                         // ne * npe element-slot outputs
     const int *rowptr, *inc;
+    const float4 *aniso;                 // 2 per element: (n_oct, Dxx, Dyy), (Dzz, Dxy, Dyz, Dxz), or null
     const long long *step_base;
     unsigned *status;
     double *part_elem, *part_node;
@@ -63,6 +64,7 @@ struct PatchArgs {
     const float *lX;            // per-patch local reference coordinates (x, y, z)
     const int *lx_begin;
     const float2 *fib;          // fibre, octahedral coordinates
+    const float4 *aniso;        // 2 per element: (n_oct, Dxx, Dyy), (Dzz, Dxy, Dyz, Dxz), or null
     const float4 *g0, *g1, *g2, *hg0, *hg1, *hg2;   // precomputed geometry (plane variant)
     const float *khg;
     float4 *nu4, *nv4;
@@ -80,6 +82,15 @@ struct PatchArgs {
     const int *patch_scen;      // per patch
     const int *shared_scen;     // per shared node
     const long long *scen_end;  // per scenario: steps to run (the scenario holds afterwards)
+    // work-queue schedule of a batch: per-XCD patch counters (zero between
+    // steps) and the union positions in order of descending end step, with the
+    // patch and shared-node counts of the prefix that ends at each position
+    int *queue;                 // kNumXcd counters
+    long long *qcount;          // [parity of the step][patches, shared nodes] of the running scenarios
+    const long long *pos_end;
+    const int *pos_patch_hi;
+    const long long *pos_shared_hi;
+    int n_pos;
 };
 
 // Optional timing of one launch: both events are taken by the dispatch itself.
@@ -98,6 +109,14 @@ void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, cons
 int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a);
 void launch_shared_nodes(bool mon, bool batch, const PatchArgs &a, int j, hipStream_t s,
                          const LaunchTiming *ev = nullptr);
+// Work-queue schedule of a batch (256-thread workgroups): `grid` workgroups pull
+// the step's patches from the per-XCD counters; the shared-node kernel strides
+// over the step's shared nodes with a fixed grid and resets the counters.
+void launch_patch_queue(int npe, int np, bool mon, bool geox, const PatchArgs &a, int j, int grid, hipStream_t s,
+                        const LaunchTiming *ev = nullptr);
+int patch_queue_occupancy(int npe, int np, bool geox, const PatchArgs &a);
+void launch_shared_nodes_queue(bool mon, const PatchArgs &a, int j, int grid, hipStream_t s,
+                               const LaunchTiming *ev = nullptr);
 // Per-scenario maximum temperature and lumped volume at or above T_abl, over the
 // scenario's interior node range [int_lo, int_hi) and shared range [sh_lo, sh_hi).
 void launch_scenario_monitors(const float4 *nu4, const float *Vl, const long long *ranges /* 4 per scenario */,

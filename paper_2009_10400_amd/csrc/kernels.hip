@@ -136,9 +136,9 @@ __device__ __forceinline__ GeoT4 t4_geo_coords(const float4 x[4], float2 fib) {
 }
 
 // T4 element: node data u4 = (ux, uy, uz, dT).
-template <int NP, bool MON>
+template <int NP, bool MON, bool ANISO>
 __device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], const GeoT4 &g, float *th,
-                                           ElemResultT4 &r) {
+                                           ElemResultT4 &r, const float4 *__restrict__ aniso, int e) {
     float d[3][4];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -157,7 +157,7 @@ __device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], con
     for (int j = 0; j < 3; ++j) gT[j] = d[0][3] * g.b[0][j] + d[1][3] * g.b[1][j] + d[2][3] * g.b[2][j];
     const float dTe = 0.25f * (u[0].w + u[1].w + u[2].w + u[3].w);
     ElemOut eo;
-    element_physics<NP>(m, H, gT, dTe, g.a, g.V0, th, MON, eo);
+    element_physics<NP, ANISO>(m, H, gT, dTe, g.a, g.V0, th, MON, eo, aniso, e);
     float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -176,11 +176,9 @@ __device__ __forceinline__ void t4_compute(const KMat &m, const float4 u[4], con
     r.nonfinite = !(finite4(r.o[0]) && finite4(r.o[1]) && finite4(r.o[2]) && finite4(r.o[3]));
 }
 
-// H8 natural-coordinate signs (---),(+--),(++-),(-+-),(--+),(+-+),(+++),(-++) and
-// hourglass base vectors eta zeta, zeta xi, xi eta, xi eta zeta.
-__device__ __forceinline__ float hsx(int a) { return (a == 1 || a == 2 || a == 5 || a == 6) ? 1.f : -1.f; }
-__device__ __forceinline__ float hsy(int a) { return (a == 2 || a == 3 || a == 6 || a == 7) ? 1.f : -1.f; }
-__device__ __forceinline__ float hsz(int a) { return (a >= 4) ? 1.f : -1.f; }
+// H8 local nodes carry the natural-coordinate signs (xi, eta, zeta) = (---), (+--),
+// (++-), (-+-), (--+), (+-+), (+++), (-++); the hourglass base vectors are eta zeta,
+// zeta xi, xi eta, xi eta zeta.
 
 struct ElemResultH8 {
     float4 o[8];
@@ -211,29 +209,67 @@ __device__ __forceinline__ GeoH8 h8_geo_planes(float4 g0, float4 g1, float4 g2, 
     return g;
 }
 
+// Walsh-Hadamard butterflies over the eight nodes of an H8, taken in the binary
+// order of their natural-coordinate signs (bit 0: xi > 0, bit 1: eta > 0,
+// bit 2: zeta > 0; node n sits at position kH8Bin[n], and the map is its own
+// inverse).  The sign functions of the element are the products
+// prod_{d in m} s_d over subsets m of the three directions: m = 1, 2, 4 are
+// xi, eta, zeta (the one-point gradient), m = 6, 5, 3, 7 the hourglass modes
+// eta zeta, zeta xi, xi eta, xi eta zeta, m = 0 the constant.  wht8 turns
+// nodal values v into all eight sums sum_b f_m(b) v_b (24 additions instead of
+// 56 for the seven sums formed one by one); iwht8 turns coefficients of the
+// eight functions into nodal values.
+__device__ constexpr int kH8Bin[8] = {0, 1, 3, 2, 4, 5, 7, 6};
+
+__device__ __forceinline__ void wht8(float v[8]) {
+#pragma unroll
+    for (int h = 1; h < 8; h <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(i & h)) {
+                const float a = v[i], b = v[i + h];
+                v[i] = b + a;
+                v[i + h] = b - a;
+            }
+}
+
+__device__ __forceinline__ void iwht8(float v[8]) {
+#pragma unroll
+    for (int h = 1; h < 8; h <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(i & h)) {
+                const float a = v[i], b = v[i + h];
+                v[i] = a - b;
+                v[i + h] = a + b;
+            }
+}
+
 // From reference coordinates: J0 = sum_a X_a (x) s_a / 8, G = J0^-T, V0 = 8 det J0,
 // c_alpha = sum_a h_alpha,a X_a, k_hg = hg (kappa + 4 mu / 3) V0 tr(G^T G) / 64
-// (sum_a |G s_a / 8|^2 = tr(G^T G) / 8 since sum_a s_a s_a^T = 8 I).
+// (sum_a |G s_a / 8|^2 = tr(G^T G) / 8 since sum_a s_a s_a^T = 8 I).  The sums are
+// the sign-function sums of each coordinate (wht8); they do not see a common
+// translation of the nodes.
 __device__ __forceinline__ GeoH8 h8_geo_coords(const float4 x[8], float2 fib, float hgk) {
     GeoH8 g;
-    float J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float J[9];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) g.c[i] = 0.f;
+    for (int i = 0; i < 3; ++i) {
+        float v[8];
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        const float s[3] = {hsx(n), hsy(n), hsz(n)};
-        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
-        const float xv[3] = {x[n].x - x[0].x, x[n].y - x[0].y, x[n].z - x[0].z};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) J[3 * i + j] += xv[i] * s[j];
-#pragma unroll
-            for (int al = 0; al < 4; ++al) g.c[3 * al + i] += h[al] * xv[i];
+        for (int b = 0; b < 8; ++b) {
+            const float4 xb = x[kH8Bin[b]];
+            v[b] = i == 0 ? xb.x : (i == 1 ? xb.y : xb.z);
         }
+        wht8(v);
+        J[3 * i] = 0.125f * v[1];
+        J[3 * i + 1] = 0.125f * v[2];
+        J[3 * i + 2] = 0.125f * v[4];
+        g.c[i] = v[6];          // eta zeta
+        g.c[3 + i] = v[5];      // zeta xi
+        g.c[6 + i] = v[3];      // xi eta
+        g.c[9 + i] = v[7];      // xi eta zeta
     }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) J[i] *= 0.125f;
     // G = J0^-T = cof(J0) / det J0
     const float cof[9] = {J[4] * J[8] - J[5] * J[7], J[5] * J[6] - J[3] * J[8], J[3] * J[7] - J[4] * J[6],
                           J[2] * J[7] - J[1] * J[8], J[0] * J[8] - J[2] * J[6], J[1] * J[6] - J[0] * J[7],
@@ -252,32 +288,32 @@ __device__ __forceinline__ GeoH8 h8_geo_coords(const float4 x[8], float2 fib, fl
     return g;
 }
 
-template <int NP, bool MON>
+template <int NP, bool MON, bool ANISO>
 __device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], const GeoH8 &g, float *th,
-                                           ElemResultH8 &r) {
+                                           ElemResultH8 &r, const float4 *__restrict__ aniso, int e) {
     const float *G = g.G;
     const float *c = g.c;
     const float V0 = g.V0, khg = g.khg;
     const float *a = g.a;
-    // U_ik = sum_a u_a,i s_a,k / 8 ; t_k = sum_a dT_a s_a,k / 8 ; hourglass sums
-    float U[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, t[3] = {0, 0, 0};
-    float hu[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    float dsum = 0.f;
+    // sign-function sums of every nodal component (wht8): U_ik = sum_a u_a,i s_a,k,
+    // t_k = sum_a dT_a s_a,k, hourglass sums hu_alpha,i = sum_a h_alpha,a u_a,i
+    float U[3][3], t[3], hu[4][3], dsum;
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        const float s[3] = {hsx(n), hsy(n), hsz(n)};
-        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
-        const float uv[4] = {u[n].x, u[n].y, u[n].z, u[n].w};
+    for (int i = 0; i < 4; ++i) {
+        float v[8];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) U[i][k] += s[k] * uv[i];
-#pragma unroll
-            for (int al = 0; al < 4; ++al) hu[al][i] += h[al] * uv[i];
+        for (int b = 0; b < 8; ++b) {
+            const float4 ub = u[kH8Bin[b]];
+            v[b] = i == 0 ? ub.x : (i == 1 ? ub.y : (i == 2 ? ub.z : ub.w));
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) t[k] += s[k] * uv[3];
-        dsum += uv[3];
+        wht8(v);
+        if (i < 3) {
+            U[i][0] = v[1]; U[i][1] = v[2]; U[i][2] = v[4];
+            hu[0][i] = v[6]; hu[1][i] = v[5]; hu[2][i] = v[3]; hu[3][i] = v[7];
+        } else {
+            t[0] = v[1]; t[1] = v[2]; t[2] = v[4];
+            dsum = v[0];
+        }
     }
     float H[9], gT[3];
 #pragma unroll
@@ -289,7 +325,7 @@ __device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], con
     for (int j = 0; j < 3; ++j) gT[j] = 0.125f * (G[3 * j] * t[0] + G[3 * j + 1] * t[1] + G[3 * j + 2] * t[2]);
     const float dTe = 0.125f * dsum;
     ElemOut eo;
-    element_physics<NP>(m, H, gT, dTe, a, V0, th, MON, eo);
+    element_physics<NP, ANISO>(m, H, gT, dTe, a, V0, th, MON, eo, aniso, e);
     // hourglass: q_alpha = sum_a h_alpha,a u_a - H c_alpha ; W = sum_alpha q_alpha c_alpha^T
     float q[4][3], W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float ehg = 0.f;
@@ -318,16 +354,27 @@ __device__ __forceinline__ void h8_compute(const KMat &m, const float4 u[8], con
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         rq[k] = 0.125f * (G[k] * eo.qV[0] + G[3 + k] * eo.qV[1] + G[6 + k] * eo.qV[2]);
+    // nodal values from the coefficients of the sign functions (iwht8):
+    // f_a = Q s_a + khg sum_alpha h_alpha,a q_alpha, heat s_a . rq
+    float fv[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float* v = fv[i];
+        if (i < 3) {
+            v[0] = 0.f;
+            v[1] = Q[3 * i]; v[2] = Q[3 * i + 1]; v[4] = Q[3 * i + 2];
+            v[6] = khg * q[0][i]; v[5] = khg * q[1][i]; v[3] = khg * q[2][i]; v[7] = khg * q[3][i];
+        } else {
+            v[0] = 0.f; v[3] = 0.f; v[5] = 0.f; v[6] = 0.f; v[7] = 0.f;
+            v[1] = rq[0]; v[2] = rq[1]; v[4] = rq[2];
+        }
+        iwht8(v);
+    }
     bool nf = false;
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
-        const float s[3] = {hsx(n), hsy(n), hsz(n)};
-        const float h[4] = {s[1] * s[2], s[2] * s[0], s[0] * s[1], s[0] * s[1] * s[2]};
-        float4 f;
-        f.x = Q[0] * s[0] + Q[1] * s[1] + Q[2] * s[2] + khg * (h[0] * q[0][0] + h[1] * q[1][0] + h[2] * q[2][0] + h[3] * q[3][0]);
-        f.y = Q[3] * s[0] + Q[4] * s[1] + Q[5] * s[2] + khg * (h[0] * q[0][1] + h[1] * q[1][1] + h[2] * q[2][1] + h[3] * q[3][1]);
-        f.z = Q[6] * s[0] + Q[7] * s[1] + Q[8] * s[2] + khg * (h[0] * q[0][2] + h[1] * q[1][2] + h[2] * q[2][2] + h[3] * q[3][2]);
-        f.w = rq[0] * s[0] + rq[1] * s[1] + rq[2] * s[2];
+        const int b = kH8Bin[n];
+        const float4 f = make_float4(fv[0][b], fv[1][b], fv[2][b], fv[3][b]);
         r.o[n] = f;
         nf |= !finite4(f);
     }
@@ -377,7 +424,7 @@ __device__ __forceinline__ NodeNew node_advance(const NodeParams &p, float4 u, f
     if (!(mk & 8u)) {
         float dtC = th.x;
         if (p.ckT_on) {
-            float w = clamp01f((p.T0 + dT - p.ck_lo) * p.ck_inv);
+            float w = clamp01f((dT + p.ck_off) * p.ck_inv);
             dtC = dtC / (p.c_lo + w * (p.c_hi - p.c_lo));
         }
         dT = dT + dtC * (-acc.w - th.y * dT + th.z + src * th.w);
@@ -408,13 +455,13 @@ __device__ __forceinline__ void node_monitor(const NodeParams &p, const NodeNew 
 }
 
 template <int BS>
-__device__ __forceinline__ void write_node_partials(NodeMon mo, double *part, double *shd, float *shf) {
+__device__ __forceinline__ void write_node_partials(NodeMon mo, double *part, int idx, double *shd, float *shf) {
     double ke = block_sum<BS>(mo.ke, shd);
     double abl = block_sum<BS>(mo.abl, shd);
     float tmax = block_max<BS>(mo.tmax, shf);
     float tmin = -block_max<BS>(-mo.tmin, shf);
     if (threadIdx.x == 0) {
-        double *pp = part + 4 * size_t(blockIdx.x);
+        double *pp = part + 4 * size_t(idx);
         pp[0] = ke; pp[1] = tmax; pp[2] = tmin; pp[3] = abl;
     }
 }
@@ -426,11 +473,12 @@ __device__ __forceinline__ float source_switch(const NodeParams &p, const long l
 
 // ---------------------------------------------------------------- two-pass kernels
 
-template <int NP, bool MON>
+template <int NP, bool MON, bool ANISO>
 __global__ __launch_bounds__(kBlock) void t4_element_kernel(
     const int4 *__restrict__ conn, const float4 *__restrict__ g0, const float4 *__restrict__ g1,
     const float4 *__restrict__ g2, const float4 *__restrict__ nu4, float *__restrict__ theta,
-    float4 *__restrict__ out, int ne, KMat m, unsigned *__restrict__ status, double *__restrict__ part) {
+    float4 *__restrict__ out, int ne, KMat m, unsigned *__restrict__ status, double *__restrict__ part,
+    const float4 *__restrict__ aniso) {
     __shared__ double shd[kBlock / 64];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int e = blk * kBlock + threadIdx.x;
@@ -442,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void t4_element_kernel(
         float th[6 * NP + 1];
         load_theta(theta, ne, e, NP, th);
         ElemResultT4 r;
-        t4_compute<NP, MON>(m, u, t4_geo_planes(g0[e], g1[e], g2[e]), th, r);
+        t4_compute<NP, MON, ANISO>(m, u, t4_geo_planes(g0[e], g1[e], g2[e]), th, r, aniso, e);
         store_theta(theta, ne, e, NP, th);
 #pragma unroll
         for (int k = 0; k < 4; ++k) out[4 * size_t(e) + k] = r.o[k];
@@ -457,13 +505,13 @@ __global__ __launch_bounds__(kBlock) void t4_element_kernel(
     }
 }
 
-template <int NP, bool MON>
+template <int NP, bool MON, bool ANISO>
 __global__ __launch_bounds__(kBlock) void h8_element_kernel(
     const int4 *__restrict__ conn0, const int4 *__restrict__ conn1, const float4 *__restrict__ g0,
     const float4 *__restrict__ g1, const float4 *__restrict__ g2, const float4 *__restrict__ hg0,
     const float4 *__restrict__ hg1, const float4 *__restrict__ hg2, const float *__restrict__ khg,
     const float4 *__restrict__ nu4, float *__restrict__ theta, float4 *__restrict__ out, int ne, KMat m,
-    unsigned *__restrict__ status, double *__restrict__ part) {
+    unsigned *__restrict__ status, double *__restrict__ part, const float4 *__restrict__ aniso) {
     __shared__ double shd[kBlock / 64];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int e = blk * kBlock + threadIdx.x;
@@ -475,7 +523,8 @@ __global__ __launch_bounds__(kBlock) void h8_element_kernel(
         float th[6 * NP + 1];
         load_theta(theta, ne, e, NP, th);
         ElemResultH8 r;
-        h8_compute<NP, MON>(m, u, h8_geo_planes(g0[e], g1[e], g2[e], hg0[e], hg1[e], hg2[e], khg[e]), th, r);
+        h8_compute<NP, MON, ANISO>(m, u, h8_geo_planes(g0[e], g1[e], g2[e], hg0[e], hg1[e], hg2[e], khg[e]), th, r,
+                            aniso, e);
         store_theta(theta, ne, e, NP, th);
 #pragma unroll
         for (int k = 0; k < 8; ++k) out[8 * size_t(e) + k] = r.o[k];
@@ -517,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
         if (MON) node_monitor(p, r, Vl[a], mo);
     }
     raise_flags(status, nf, false);
-    if (MON) write_node_partials<kBlock>(mo, part, shd, shf);
+    if (MON) write_node_partials<kBlock>(mo, part, blk, shd, shf);
 }
 
 // ---------------------------------------------------------------- fused patch kernels
@@ -526,19 +575,37 @@ __global__ __launch_bounds__(kBlock) void node_kernel(
 // coordinates (float4 each per local node) and the element-slot outputs
 // (float4 per element slot, grouped by local node: each element writes its
 // slots at their precomputed positions, and each node sums its contiguous run).  GEOX: element geometry rebuilt from the staged
-// coordinates (else read from the precomputed planes).
-template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH>
-__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
-    extern __shared__ float4 lds[];
-    __shared__ double shd[BS / 64];
-    __shared__ float shf[BS / 64];
-    const int pid = xcd_block(blockIdx.x, gridDim.x);
+// coordinates (else read from the precomputed planes).  ANISO: the orthotropic
+// expansion and tensor conduction modes are compiled in.
+// A value the whole wavefront shares, read from memory that the kernel also
+// writes elsewhere: the compiler cannot prove it unchanged since the kernel
+// started, so it would keep it in vector registers (and branch on it per lane);
+// readfirstlane puts every word in a scalar register.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized fields");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, p, sizeof(T));      // the words of the value (memcpy: no type punning)
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+__device__ __forceinline__ int uniform_int(const int *p) { return __builtin_amdgcn_readfirstlane(*p); }
+
+// UNI: the patch index comes from a work queue (loads after earlier stores in
+// the same kernel), so its per-patch values are read with uniform_load.
+template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO, bool UNI = false>
+__device__ __forceinline__ void patch_work(const PatchArgs &A, const int pid, const int j, float4 *lds, double *shd,
+                                           float *shf) {
     // BATCH: per-scenario constants and end steps; else the single problem's
     // constants at index 0 (no scenario lookups, fewer scalar registers live)
     int sc = 0;
     if (BATCH) {
-        sc = A.patch_scen[pid];
-        if (*A.step_base + j >= A.scen_end[sc]) {   // this scenario has finished: hold it
+        sc = UNI ? uniform_int(A.patch_scen + pid) : A.patch_scen[pid];
+        const long long end = UNI ? uniform_load(A.scen_end + sc) : A.scen_end[sc];
+        if (*A.step_base + j >= end) {   // this scenario has finished: hold it
             if (MON && threadIdx.x == 0) {
                 A.part_elem[pid] = 0.0;
                 double *pp = A.part_node + 4 * size_t(pid);
@@ -547,16 +614,19 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
             return;
         }
     }
-    const KMat m = A.km[sc];
-    const NodeParams p = A.np[sc];
-    const int e0 = A.elem_begin[pid], e1 = A.elem_begin[pid + 1];
-    const int ib = A.int_begin[pid], ie = A.int_begin[pid + 1];
-    const int sb = A.shared_begin[pid], se = A.shared_begin[pid + 1];
+    const KMat m = UNI ? uniform_load(A.km + sc) : A.km[sc];
+    const NodeParams p = UNI ? uniform_load(A.np + sc) : A.np[sc];
+    const int e0 = UNI ? uniform_int(A.elem_begin + pid) : A.elem_begin[pid];
+    const int e1 = UNI ? uniform_int(A.elem_begin + pid + 1) : A.elem_begin[pid + 1];
+    const int ib = UNI ? uniform_int(A.int_begin + pid) : A.int_begin[pid];
+    const int ie = UNI ? uniform_int(A.int_begin + pid + 1) : A.int_begin[pid + 1];
+    const int sb = UNI ? uniform_int(A.shared_begin + pid) : A.shared_begin[pid];
+    const int se = UNI ? uniform_int(A.shared_begin + pid + 1) : A.shared_begin[pid + 1];
     const int nint = ie - ib, nloc = nint + (se - sb);
     float4 *lnode = lds;                                   // nloc: (u, dT)
     float4 *lxyz = lds + A.max_nodes;                      // nloc: reference coordinates (GEOX)
     float4 *lout = lds + (GEOX ? 2 : 1) * A.max_nodes;     // (e1 - e0) * NPE
-    const float *gx = GEOX ? A.lX + 3 * size_t(A.lx_begin[pid]) : nullptr;
+    const float *gx = GEOX ? A.lX + 3 * size_t(UNI ? uniform_int(A.lx_begin + pid) : A.lx_begin[pid]) : nullptr;
     // Stage the local nodes.  The node ids of a thread's first two local nodes
     // are requested before their data, so the id -> data chain is paid once.
     // GEOX: the fourth float of a shared node's staged coordinate carries the
@@ -603,7 +673,7 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
                 g = t4_geo_planes(A.g0[e], A.g1[e], A.g2[e]);
             }
             ElemResultT4 r;
-            t4_compute<NP, MON>(m, u, g, th, r);
+            t4_compute<NP, MON, ANISO>(m, u, g, th, r, A.aniso, e);
             lout[ps.x] = r.o[0];
             lout[ps.y] = r.o[1];
             lout[ps.z] = r.o[2];
@@ -627,7 +697,7 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
                 g = h8_geo_planes(A.g0[e], A.g1[e], A.g2[e], A.hg0[e], A.hg1[e], A.hg2[e], A.khg[e]);
             }
             ElemResultH8 r;
-            h8_compute<NP, MON>(m, u, g, th, r);
+            h8_compute<NP, MON, ANISO>(m, u, g, th, r, A.aniso, e);
             lout[pa.x] = r.o[0];
             lout[pa.y] = r.o[1];
             lout[pa.z] = r.o[2];
@@ -645,7 +715,7 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     __syncthreads();
     // assemble local nodes in a fixed order
     const float src = source_switch(p, A.step_base, j);
-    const uint16_t *lrow = A.lrow + A.lrow_begin[pid];
+    const uint16_t *lrow = A.lrow + (UNI ? uniform_int(A.lrow_begin + pid) : A.lrow_begin[pid]);
     NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
     for (int l = threadIdx.x; l < nloc; l += BS) {
         const bool interior = l < nint;
@@ -679,7 +749,77 @@ __global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
     if (MON) {
         double s = block_sum<BS>(double(psi), shd);
         if (threadIdx.x == 0) A.part_elem[pid] = s;
-        write_node_partials<BS>(mo, A.part_node, shd, shf);
+        write_node_partials<BS>(mo, A.part_node, pid, shd, shf);
+    }
+}
+
+// One workgroup per patch (a launch covers the first gridDim.x patches).
+template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO>
+__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
+    extern __shared__ float4 lds[];
+    __shared__ double shd[BS / 64];
+    __shared__ float shf[BS / 64];
+    patch_work<NPE, NP, MON, BS, GEOX, BATCH, ANISO>(A, xcd_block(blockIdx.x, gridDim.x), j, lds, shd, shf);
+}
+
+// Batch scenarios still running at `step`: the union positions run in order of
+// descending end step, so they are the first m positions with pos_end > step.
+__device__ __forceinline__ int running_positions(const PatchArgs &A, long long step) {
+    int lo = 0, hi = A.n_pos;   // first position whose end step is <= step
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A.pos_end[mid] > step) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Work-queue form of the batch patch kernel: launched with the workgroups that
+// are resident at once, which pull patches until the step's patches run out
+// (all patches at a monitor step, where finished ones write neutral monitor
+// partials; else only those of the scenarios still running: their count for
+// the step was left by the previous step's shared-node kernel in the slot of
+// the step's parity, so one captured graph serves every step).  Workgroups
+// beyond that count leave at once.  XCD x draws from its own counter over the
+// x-th eighth of the patches (neighbouring patches share nodes, so they stay in
+// one L2), then helps the other eighths in turn, reading a counter before
+// incrementing it so that exhausted ones cost no atomic.  The counters are
+// reset to zero by the step's shared-node kernel, which runs after every
+// workgroup here has finished.  No workgroup waits for another.
+template <int NPE, int NP, bool MON, bool GEOX>
+__global__ __launch_bounds__(kBlock) void patch_queue_kernel(PatchArgs A, int j) {
+    extern __shared__ float4 lds[];
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    __shared__ int s_item;
+    const long long step = *A.step_base + j;
+    const int n = MON ? A.n_patches : int(A.qcount[2 * (step & 1)]);
+    if (int(blockIdx.x) >= n) return;
+    int x = int(blockIdx.x % kNumXcd), tries = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < kNumXcd) {
+                const int lo = int((long long)n * x / kNumXcd), hi = int((long long)n * (x + 1) / kNumXcd);
+                if (lo + __hip_atomic_load(&A.queue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
+                    const int c = lo + atomicAdd(&A.queue[x], 1);
+                    if (c < hi) {
+                        it = c;
+                        break;
+                    }
+                }
+                ++tries;                     // this eighth is done: help the next one
+                x = (x + 1) % kNumXcd;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        // the item is the same for the whole workgroup: kept in a scalar register, so that
+        // everything derived from it (ranges, scenario constants) stays scalar as in patch_kernel
+        const int pid = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();                     // every thread has read the item before it is replaced
+        if (pid < 0) break;
+        patch_work<NPE, NP, MON, kBlock, GEOX, true, false, true>(A, pid, j, lds, shd, shf);
     }
 }
 
@@ -718,7 +858,57 @@ __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j)
         if (MON) node_monitor(p, r, A.Vl[a], mo);
     }
     raise_flags(A.status, nf, false);
-    if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), shd, shf);
+    if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), blk, shd, shf);
+}
+
+// Shared-node kernel of the work-queue schedule: a fixed grid strides over the
+// shared nodes of the scenarios still running (all of them at a monitor step),
+// counted on the device; block 0 then resets the patch queue counters for the
+// next step.
+template <bool MON>
+__global__ __launch_bounds__(kBlock) void shared_node_queue_kernel(PatchArgs A, int j) {
+    __shared__ double shd[kBlock / 64];
+    __shared__ float shf[kBlock / 64];
+    const long long step = *A.step_base + j;
+    const int64_t n = MON ? int64_t(A.n_shared) : int64_t(A.qcount[2 * (step & 1) + 1]);
+    // the running scenarios' patch and shared-node counts of the next step, into
+    // the other parity's slots (read by the next step's kernels only)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int m = running_positions(A, step + 1);
+        long long *nx = A.qcount + 2 * ((step + 1) & 1);
+        nx[0] = m ? A.pos_patch_hi[m - 1] : 0;
+        nx[1] = m ? A.pos_shared_hi[m - 1] : 0;
+    }
+    NodeMon mo{0.0, -INFINITY, INFINITY, 0.0};
+    bool nf = false;
+    for (int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x; s < n; s += int64_t(gridDim.x) * kBlock) {
+        const int sc = A.shared_scen[s];
+        if (step >= A.scen_end[sc]) continue;
+        const NodeParams p = A.np[sc];
+        const float src = (step >= p.n_on && step < p.n_off) ? 1.0f : 0.0f;
+        const int64_t a = A.n_interior + s;
+        const float4 u0 = A.nu4[a], v0 = A.nv4[a], th = A.nth[a];
+        const unsigned mk = A.mask[a];
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int k0 = A.srow[s], k1 = A.srow[s + 1];
+        for (int k = k0; k < k1; k += 4) {
+            float4 o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = (k + q < k1) ? A.partial[k + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc.x += o[q].x; acc.y += o[q].y; acc.z += o[q].z; acc.w += o[q].w;
+            }
+        }
+        NodeNew r = node_advance(p, u0, v0, th, mk, acc, src);
+        A.nu4[a] = r.u;
+        A.nv4[a] = r.v;
+        nf |= r.nonfinite;
+        if (MON) node_monitor(p, r, A.Vl[a], mo);
+    }
+    raise_flags(A.status, nf, false);
+    if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), int(blockIdx.x), shd, shf);
+    if (blockIdx.x == 0 && threadIdx.x < kNumXcd) A.queue[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- monitors
@@ -761,49 +951,66 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const double *__restrict
 // ---------------------------------------------------------------- launchers
 
 namespace {
-template <int NP>
-void launch_t4_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
+template <int NP, bool ANISO>
+void launch_t4_element_a(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
     dim3 grid((a.ne + kBlock - 1) / kBlock);
     if (mon)
-        TLED_LAUNCH(ev, (t4_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
-                    a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (t4_element_kernel<NP, true, ANISO>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2,
+                    a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem, a.aniso);
     else
-        TLED_LAUNCH(ev, (t4_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2, a.nu4,
-                    a.theta, a.out, a.ne, m, a.status, a.part_elem);
+        TLED_LAUNCH(ev, (t4_element_kernel<NP, false, ANISO>), grid, dim3(kBlock), 0, s, a.conn4, a.g0, a.g1, a.g2,
+                    a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem, a.aniso);
+}
+template <int NP, bool ANISO>
+void launch_h8_element_a(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
+    dim3 grid((a.ne + kBlock - 1) / kBlock);
+    if (mon)
+        TLED_LAUNCH(ev, (h8_element_kernel<NP, true, ANISO>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1,
+                    a.g2, a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem, a.aniso);
+    else
+        TLED_LAUNCH(ev, (h8_element_kernel<NP, false, ANISO>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0,
+                    a.g1, a.g2, a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem,
+                    a.aniso);
+}
+// The anisotropy plane is present exactly when the orthotropic expansion or the tensor conduction is on.
+template <int NP>
+void launch_t4_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
+    if (a.aniso) launch_t4_element_a<NP, true>(mon, a, m, s, ev);
+    else launch_t4_element_a<NP, false>(mon, a, m, s, ev);
 }
 template <int NP>
 void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s, const LaunchTiming *ev) {
-    dim3 grid((a.ne + kBlock - 1) / kBlock);
-    if (mon)
-        TLED_LAUNCH(ev, (h8_element_kernel<NP, true>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1, a.g2,
-                    a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
-    else
-        TLED_LAUNCH(ev, (h8_element_kernel<NP, false>), grid, dim3(kBlock), 0, s, a.conn4, a.conn4b, a.g0, a.g1,
-                    a.g2, a.hg0, a.hg1, a.hg2, a.khg, a.nu4, a.theta, a.out, a.ne, m, a.status, a.part_elem);
+    if (a.aniso) launch_h8_element_a<NP, true>(mon, a, m, s, ev);
+    else launch_h8_element_a<NP, false>(mon, a, m, s, ev);
 }
 
 // occ != nullptr: report the resident workgroups per CU of the instantiation
 // instead of launching it.
-template <int NPE, int NP, int BS, bool GEOX, bool BATCH>
+template <int NPE, int NP, int BS, bool GEOX, bool BATCH, bool ANISO = false>
 void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s, int *occ,
                     const LaunchTiming *ev) {
     if (occ) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX, BATCH>), BS, lds) !=
-            hipSuccess)
+                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO>), BS,
+                lds) != hipSuccess)
             *occ = -1;
         return;
     }
     dim3 grid(a.n_patches);
-    if (mon) TLED_LAUNCH(ev, (patch_kernel<NPE, NP, true, BS, GEOX, BATCH>), grid, dim3(BS), lds, s, a, j);
-    else TLED_LAUNCH(ev, (patch_kernel<NPE, NP, false, BS, GEOX, BATCH>), grid, dim3(BS), lds, s, a, j);
+    if (mon) TLED_LAUNCH(ev, (patch_kernel<NPE, NP, true, BS, GEOX, BATCH, ANISO>), grid, dim3(BS), lds, s, a, j);
+    else TLED_LAUNCH(ev, (patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO>), grid, dim3(BS), lds, s, a, j);
 }
 
-// Batches run with 256-thread workgroups only.
+// Batches run with 256-thread workgroups only; so do single problems with the
+// orthotropic expansion or the tensor conduction (the anisotropy plane is
+// present exactly then).
 template <int NPE, int NP>
 void launch_patch_np(bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j, size_t lds,
                      hipStream_t s, int *occ, const LaunchTiming *ev) {
-    if (batch) {
+    if (a.aniso && !batch) {
+        if (geox) launch_patch_g<NPE, NP, 256, true, false, true>(mon, a, j, lds, s, occ, ev);
+        else launch_patch_g<NPE, NP, 256, false, false, true>(mon, a, j, lds, s, occ, ev);
+    } else if (batch) {
         if (geox) launch_patch_g<NPE, NP, 256, true, true>(mon, a, j, lds, s, occ, ev);
         else launch_patch_g<NPE, NP, 256, false, true>(mon, a, j, lds, s, occ, ev);
     } else if (NPE == 4 && bs == 512) {
@@ -875,6 +1082,58 @@ void patch_dispatch(int npe, int np, bool mon, bool geox, int bs, bool batch, co
 void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
                   hipStream_t s, const LaunchTiming *ev) {
     patch_dispatch(npe, np, mon, geox, bs, batch, a, j, s, nullptr, ev);
+}
+
+namespace {
+// occ != nullptr: report resident workgroups per CU instead of launching.
+template <int NPE, int NP, bool GEOX>
+void launch_queue_g(bool mon, const PatchArgs &a, int j, int grid, size_t lds, hipStream_t s, int *occ,
+                    const LaunchTiming *ev) {
+    if (occ) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                occ, reinterpret_cast<const void *>(&patch_queue_kernel<NPE, NP, false, GEOX>), kBlock, lds) !=
+            hipSuccess)
+            *occ = -1;
+        return;
+    }
+    if (mon) TLED_LAUNCH(ev, (patch_queue_kernel<NPE, NP, true, GEOX>), dim3(grid), dim3(kBlock), lds, s, a, j);
+    else TLED_LAUNCH(ev, (patch_queue_kernel<NPE, NP, false, GEOX>), dim3(grid), dim3(kBlock), lds, s, a, j);
+}
+template <int NPE>
+void queue_np(int np, bool mon, bool geox, const PatchArgs &a, int j, int grid, size_t lds, hipStream_t s, int *occ,
+              const LaunchTiming *ev) {
+#define TLED_QNP(NPV)                                                            \
+    if (geox) launch_queue_g<NPE, NPV, true>(mon, a, j, grid, lds, s, occ, ev);  \
+    else launch_queue_g<NPE, NPV, false>(mon, a, j, grid, lds, s, occ, ev);
+    switch (np) {
+        case 0: TLED_QNP(0) break;
+        case 1: TLED_QNP(1) break;
+        case 2: TLED_QNP(2) break;
+        case 3: TLED_QNP(3) break;
+        default: TLED_QNP(4) break;
+    }
+#undef TLED_QNP
+}
+}  // namespace
+
+void launch_patch_queue(int npe, int np, bool mon, bool geox, const PatchArgs &a, int j, int grid, hipStream_t s,
+                        const LaunchTiming *ev) {
+    const size_t lds = patch_lds_bytes(npe, geox, a);
+    if (npe == 4) queue_np<4>(np, mon, geox, a, j, grid, lds, s, nullptr, ev);
+    else queue_np<8>(np, mon, geox, a, j, grid, lds, s, nullptr, ev);
+}
+
+int patch_queue_occupancy(int npe, int np, bool geox, const PatchArgs &a) {
+    int occ = 0;
+    const size_t lds = patch_lds_bytes(npe, geox, a);
+    if (npe == 4) queue_np<4>(np, false, geox, a, 0, 1, lds, nullptr, &occ, nullptr);
+    else queue_np<8>(np, false, geox, a, 0, 1, lds, nullptr, &occ, nullptr);
+    return occ;
+}
+
+void launch_shared_nodes_queue(bool mon, const PatchArgs &a, int j, int grid, hipStream_t s, const LaunchTiming *ev) {
+    if (mon) TLED_LAUNCH(ev, (shared_node_queue_kernel<true>), dim3(grid), dim3(kBlock), 0, s, a, j);
+    else TLED_LAUNCH(ev, (shared_node_queue_kernel<false>), dim3(grid), dim3(kBlock), 0, s, a, j);
 }
 
 int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a) {

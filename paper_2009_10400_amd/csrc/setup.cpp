@@ -166,8 +166,32 @@ tled_status check_inputs(const HostProblem &p, std::string *err) {
     if (m.shrink_on && !(m.shrink_width > 0)) { *err = "shrink_width must be > 0"; return TLED_E_ARG; }
     if (m.ckT_on && !(m.ckT_hi > m.ckT_lo)) { *err = "ckT_hi must exceed ckT_lo"; return TLED_E_ARG; }
     if (m.ckT_on && (!(m.c_hi > 0) || m.k_hi < 0)) { *err = "c_hi > 0 and k_hi >= 0 required"; return TLED_E_ARG; }
-    if (m.expan_mode < 0 || m.expan_mode > 1 || m.cond_mode < 0 || m.cond_mode > 1) {
-        *err = "expan_mode and cond_mode must be 0 or 1"; return TLED_E_ARG;
+    if (m.expan_mode < 0 || m.expan_mode > 2 || m.cond_mode < 0 || m.cond_mode > 2) {
+        *err = "expan_mode and cond_mode must be 0, 1 or 2"; return TLED_E_ARG;
+    }
+    if (m.expan_mode == 2 && int64_t(p.n0.size()) != 3 * p.ne) {
+        *err = "expan_mode 2 needs the second expansion axes (tled_set_expansion_axes)"; return TLED_E_ARG;
+    }
+    if (m.cond_mode == 2 && int64_t(p.Dc.size()) != 6 * p.ne) {
+        *err = "cond_mode 2 needs the element conductivity tensors (tled_set_conductivity)"; return TLED_E_ARG;
+    }
+    if (m.cond_mode == 2) {
+        // each tensor symmetric positive semi-definite: all principal minors >= 0 (to rounding)
+        for (int64_t e = 0; e < p.ne; ++e) {
+            const double *d = &p.Dc[6 * e];
+            const double xx = d[0], yy = d[1], zz = d[2], xy = d[3], yz = d[4], xz = d[5];
+            bool finite = true;
+            for (int i = 0; i < 6; ++i) finite = finite && std::isfinite(d[i]);
+            const double sc = std::max({std::fabs(xx), std::fabs(yy), std::fabs(zz), std::fabs(xy), std::fabs(yz),
+                                        std::fabs(xz)});
+            const double tol = 1e-12 * sc * sc, tol3 = 1e-12 * sc * sc * sc;
+            const double det3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+            if (!finite || xx < 0 || yy < 0 || zz < 0 || xx * yy - xy * xy < -tol || yy * zz - yz * yz < -tol ||
+                xx * zz - xz * xz < -tol || det3 < -tol3) {
+                *err = "conductivity tensor of element " + std::to_string(e) + " is not symmetric positive semi-definite";
+                return TLED_E_ARG;
+            }
+        }
     }
     return TLED_OK;
 }
@@ -603,6 +627,8 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
     pc.geo.resize(size_t(ne) * 9);
     pc.V0.resize(ne);
     pc.a0.resize(size_t(ne) * 3);
+    if (p.mat.expan_mode == 2) pc.n0.resize(size_t(ne) * 3);
+    if (p.mat.cond_mode == 2) pc.Dc.resize(size_t(ne) * 6);
     if (npe == 8) { pc.hgc.resize(size_t(ne) * 12); pc.khg.resize(ne); }
     std::vector<double> q(ne, 0.0);
     for (int64_t ei = 0; ei < ne; ++ei) {
@@ -616,6 +642,20 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
         double an = std::sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
         if (!(an > 0.0)) { *err = "zero fibre vector at element " + std::to_string(e); return TLED_E_ARG; }
         for (int i = 0; i < 3; ++i) pc.a0[3 * ei + i] = a0[i] / an;
+        if (p.mat.expan_mode == 2) {
+            // Eq. 11's axes are orthonormal: remove n's component along m = a0, normalise
+            const double *m = &pc.a0[3 * ei], *n = &p.n0[3 * e];
+            const double nn0 = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+            const double d = n[0] * m[0] + n[1] * m[1] + n[2] * m[2];
+            const double w[3] = {n[0] - d * m[0], n[1] - d * m[1], n[2] - d * m[2]};
+            const double wn = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            if (!(wn > 1e-6 * nn0)) {
+                *err = "second expansion axis parallel to the fibre (or zero) at element " + std::to_string(e);
+                return TLED_E_ARG;
+            }
+            for (int i = 0; i < 3; ++i) pc.n0[3 * ei + i] = w[i] / wn;
+        }
+        if (p.mat.cond_mode == 2) std::memcpy(&pc.Dc[6 * ei], &p.Dc[6 * e], 6 * sizeof(double));
         if (npe == 8) {
             std::memcpy(&pc.hgc[12 * ei], g.hgc, 12 * sizeof(double));
             pc.khg[ei] = p.mat.hg_coef * (p.mat.kappa + 4.0 * p.mat.mu / 3.0) * g.V0 * g.sum_dh2 / 8.0;
@@ -654,7 +694,8 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
         const tled_material &m = p.mat;
         double kmax = m.k;
         if (m.cond_mode == 1) kmax = std::max(kmax, m.k_m);
-        if (m.ckT_on && m.k > 0.0) kmax *= std::max(1.0, m.k_hi / m.k);
+        const double kt = (m.ckT_on && m.k > 0.0) ? std::max(1.0, m.k_hi / m.k) : 1.0;
+        kmax *= kt;
         const double cmin = m.ckT_on ? std::min(m.c, m.c_hi) : m.c;
         std::vector<double> rowsum(nn, 0.0);
         for (int64_t ei = 0; ei < ne; ++ei) {
@@ -681,7 +722,13 @@ tled_status precompute(const HostProblem &p, const SetupOptions &opt, Precompute
             }
             double sum = 0.0;
             for (int a = 0; a < npe; ++a) sum += gn[a];
-            for (int a = 0; a < npe; ++a) rowsum[pc.conn[npe * ei + a]] += g.V0 * kmax * gn[a] * sum;
+            double ke = kmax;
+            if (m.cond_mode == 2) {   // Frobenius norm >= the tensor's largest eigenvalue
+                const double *d = &pc.Dc[6 * ei];
+                ke = kt * std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] +
+                                    2.0 * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]));
+            }
+            for (int a = 0; a < npe; ++a) rowsum[pc.conn[npe * ei + a]] += g.V0 * ke * gn[a] * sum;
         }
         pc.dt_th = std::numeric_limits<double>::infinity();
         for (int64_t a = 0; a < nn; ++a) {

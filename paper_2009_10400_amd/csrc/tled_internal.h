@@ -19,6 +19,8 @@ struct HostProblem {
     std::vector<double> X;          // nn * 3
     std::vector<int32_t> conn;      // ne * npe
     std::vector<double> a0;         // ne * 3, empty = (1,0,0)
+    std::vector<double> n0;         // ne * 3 second expansion axes (expan_mode 2), else empty
+    std::vector<double> Dc;         // ne * 6 conductivity tensors xx yy zz xy yz xz (cond_mode 2), else empty
     std::vector<double> q;          // ne, empty = 0
     std::vector<uint8_t> fix;       // nn, bit0..2 fixed u, bit3 fixed T
     std::vector<double> Tfix;       // nn
@@ -74,6 +76,8 @@ struct Precomputed {
     std::vector<double> hgc;        // ne * 12: H8 c_alpha = X^T h_alpha (alpha = 0..3)
     std::vector<double> khg;        // ne: H8 hourglass stiffness
     std::vector<double> a0;         // ne * 3 unit fibres
+    std::vector<double> n0;         // ne * 3 unit second expansion axes, orthogonal to a0 (expan_mode 2)
+    std::vector<double> Dc;         // ne * 6 conductivity tensors (cond_mode 2)
     std::vector<double> Vl, M, C, Kb, Qm, Qr;  // nn lumped quantities (C at T0)
     std::vector<uint8_t> fix;       // nn
     std::vector<double> Tfix;       // nn

@@ -271,14 +271,15 @@ def unscale(problem, duration: float, y):
     return problem.params["T0"] + sT * y[..., 0], su * y[..., 1:]
 
 
-def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, graph_steps: int = 0, log=None):
+def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, graph_steps: int = 0, log=None,
+                    batch_schedule: int = 0, progress_steps: int = 50000):
     """Runs scenarios [(Problem, duration)] in one batch, each to the end of its heating,
     and reads every scenario's fields at n_snap evenly spaced batch steps.  A snapshot
     of a scenario at heating time t is the solution of the same scenario with
     duration t (the source is on from t = 0 and the past does not depend on a later
     switch-off).  Returns (list of (scenario index, duration, u, T), solver seconds)."""
     b = tled.Batch(device, stream=stream)
-    b.set_options(graph_steps=graph_steps)
+    b.set_options(graph_steps=graph_steps, batch_schedule=batch_schedule)
     for p, dur in scenarios:
         b.add(p, cfl=p.cfl, t_end=dur)
     b.finalize()
@@ -288,11 +289,15 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
     snaps, last, done, el = [], [0] * len(scenarios), 0, 0.0
     for k in marks:
         b.sync()
-        t0 = time.perf_counter()
-        b.step(k - done)
-        b.sync()
-        el += time.perf_counter() - t0
-        done = k
+        while done < k:                      # in slices, with a progress line each (long runs)
+            c = min(k - done, progress_steps)
+            t0 = time.perf_counter()
+            b.step(c)
+            b.sync()
+            el += time.perf_counter() - t0
+            done += c
+            if log and done < k:
+                log(f"[surrogate] batch step {done}/{S}, {el:.1f}s")
         fields = b.read_all()
         for s, (u, T) in enumerate(fields):
             n = min(k, steps[s])
@@ -305,19 +310,31 @@ def solve_snapshots(scenarios, n_snap: int = 5, device: int = 0, stream=None, gr
     return snaps, el
 
 
-def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 0, torch_allocator: bool = False):
+def solve(scenarios, device: int = 0, stream=None, graph_steps: int = 0, torch_allocator: bool = False,
+          batch_schedule: int = 0, log=None, progress_steps: int = 200000):
     """Solver alone: one batch, every scenario to the end of its heating.
     Returns ([(u, T)], {"setup": s, "run": s, "total": s}): set-up = host precompute and
-    upload, run = GPU stepping and the read-back of every field."""
+    upload, run = GPU stepping and the read-back of every field.  With `log`, the steps
+    run in slices of progress_steps with a progress line after each (long runs)."""
     t0 = time.perf_counter()
     b = tled.Batch(device, stream=stream, use_torch_allocator=torch_allocator)
-    b.set_options(graph_steps=graph_steps)
+    b.set_options(graph_steps=graph_steps, batch_schedule=batch_schedule)
     for p, dur in scenarios:
         b.add(p, cfl=p.cfl, t_end=dur)
     b.finalize()
     b.sync()
     t1 = time.perf_counter()
-    b.run()
+    if log:
+        total = b.batch_info()["max_steps"]
+        done = 0
+        while done < total:
+            c = min(progress_steps, total - done)
+            b.step(c)
+            b.sync()
+            done += c
+            log(f"[surrogate] solver batch step {done}/{total}, {time.perf_counter() - t1:.1f}s")
+    else:
+        b.run()
     out = [(u.copy(), T.copy()) for u, T in b.read_all()]
     t2 = time.perf_counter()
     b.close()
@@ -341,6 +358,56 @@ def make_dataset(scenarios, snaps, t_ref: float) -> Dataset:
         ps.append(p)
         ys.append(scaled_targets(prob, dur, u, T).astype(np.float32))
         fs.append(np.full(len(x), j, np.int32))
+    return Dataset(np.concatenate(xs), np.concatenate(ps), np.concatenate(ys), np.concatenate(fs))
+
+
+def _shard_nodes(nn: int, scenario: int, ordinal: int, per_field: int, seed: int):
+    """Node subsample of one stored field: a seeded draw from (seed, scenario, snapshot ordinal)."""
+    rng = np.random.default_rng([seed, scenario, ordinal])
+    return np.sort(rng.choice(nn, size=min(nn, per_field), replace=False))
+
+
+def write_shard(path: str, scenarios, first: int, snaps, per_field: int = 2048, seed: int = 17):
+    """Stores a node subsample of every snapshot field of scenarios[first:first + len] (solver runs
+    of the training set), so that data made in separate runs can be combined: per field the global
+    scenario index, its snapshot ordinal and duration, and the scaled targets (temperature in
+    float32, displacement in float16) at nodes drawn by _shard_nodes (not stored: they are drawn
+    again when the shard is read, as are the coordinates, from the seeded scenario generator)."""
+    meta, yT, yu, ordinal = [], [], [], {}
+    for s, dur, u, T in snaps:                 # s: position in the slice that starts at `first`
+        prob = scenarios[first + s][0]
+        j = ordinal.get(s, 0)
+        ordinal[s] = j + 1
+        idx = _shard_nodes(prob.nn, first + s, j, per_field, seed)
+        y = scaled_targets(prob, dur, u[idx], T[idx])
+        meta.append((first + s, j, dur, len(idx)))
+        yT.append(y[:, 0].astype(np.float32))
+        yu.append(y[:, 1:].astype(np.float16))
+    m = np.array(meta, dtype=[("scenario", "i4"), ("ordinal", "i4"), ("duration", "f8"), ("n", "i4")])
+    np.savez_compressed(path, scenario=m["scenario"], ordinal=m["ordinal"], duration=m["duration"], n=m["n"],
+                        yT=np.concatenate(yT), yu=np.concatenate(yu), per_field=per_field, seed=seed)
+
+
+def dataset_from_shards(paths, scenarios, t_ref: float) -> Dataset:
+    """Training set from shards written by write_shard for the scenario list `scenarios` (indices
+    are global positions in it)."""
+    xs, ps, ys, fs, field = [], [], [], [], 0
+    for path in paths:
+        z = np.load(path, allow_pickle=False)
+        per, seed = int(z["per_field"]), int(z["seed"])
+        off = 0
+        for s, j, dur, n in zip(z["scenario"], z["ordinal"], z["duration"], z["n"]):
+            prob = scenarios[int(s)][0]
+            idx = _shard_nodes(prob.nn, int(s), int(j), per, seed)
+            if len(idx) != n:
+                raise ValueError(f"shard {path}: field of scenario {s} does not match the scenario list")
+            x, p = scenario_inputs(prob, float(dur), t_ref)
+            xs.append(x[idx])
+            ps.append(p[idx])
+            ys.append(np.concatenate([z["yT"][off:off + n, None], z["yu"][off:off + n].astype(np.float32)], 1))
+            fs.append(np.full(n, field, np.int32))
+            field += 1
+            off += n
     return Dataset(np.concatenate(xs), np.concatenate(ps), np.concatenate(ys), np.concatenate(fs))
 
 
@@ -471,7 +538,8 @@ def train(model: MLP, data: Dataset, epochs: int, batch: int = 16384, lr: float 
     return losses
 
 
-def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream=None):
+def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream=None, log=None,
+         batch_schedule: int = 0, graph_steps: int = 0):
     """Surrogate-first planning of items [(Problem, duration)]: every scenario is
     predicted by the ensemble; those whose disagreement estimate exceeds
     threshold_K are run by the solver instead.  Returns results and timings
@@ -487,7 +555,8 @@ def plan(ens: Ensemble, items, threshold_K: float = 0.5, device: int = 0, stream
     reject = [k for k, e in enumerate(est) if e > threshold_K]
     t_fb, fallback = {"setup": 0.0, "run": 0.0, "total": 0.0}, {}
     if reject:
-        fields, t_fb = solve([items[k] for k in reject], device=device, stream=stream)
+        fields, t_fb = solve([items[k] for k in reject], device=device, stream=stream, log=log,
+                             batch_schedule=batch_schedule, graph_steps=graph_steps)
         fallback = dict(zip(reject, fields))
     results = []
     for k, (Tm, um, _) in enumerate(preds):

@@ -53,7 +53,7 @@ _i64 = ctypes.c_int64
 class Material(ctypes.Structure):
     _fields_ = [
         ("rho", _d), ("mu", _d), ("kappa", _d), ("eta", _d), ("alpha", _d), ("alpha_m", _d),
-        ("T0", _d), ("k", _d), ("k_m", _d), ("c", _d), ("wbcb", _d), ("T_art", _d), ("Q_met", _d),
+        ("alpha_n", _d), ("T0", _d), ("k", _d), ("k_m", _d), ("c", _d), ("wbcb", _d), ("T_art", _d), ("Q_met", _d),
         ("g", _d * 4), ("tau", _d * 4),
         ("muT_lo", _d), ("muT_hi", _d), ("muT_drop", _d),
         ("shrink_T", _d), ("shrink_width", _d), ("shrink_eps", _d),
@@ -65,7 +65,8 @@ class Material(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("graph_steps", _i32), ("kernel_variant", _i32), ("reorder", _i32),
-                ("block_size", _i32), ("patch_elems", _i32), ("ablation_T", _d)]
+                ("block_size", _i32), ("patch_elems", _i32), ("ablation_T", _d),
+                ("batch_schedule", _i32), ("reserved", _i32)]
 
 
 class Monitors(ctypes.Structure):
@@ -111,6 +112,8 @@ _SIGS = {
     "tled_set_mesh": ([_P, ctypes.c_int, _i64, _dp, _i64, ctypes.POINTER(_i32)], ctypes.c_int),
     "tled_set_material": ([_P, ctypes.POINTER(Material)], ctypes.c_int),
     "tled_set_fibres": ([_P, _dp], ctypes.c_int),
+    "tled_set_expansion_axes": ([_P, _dp], ctypes.c_int),
+    "tled_set_conductivity": ([_P, _dp], ctypes.c_int),
     "tled_set_fixed_dofs": ([_P, _i64, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint8)], ctypes.c_int),
     "tled_set_fixed_temperature": ([_P, _i64, ctypes.POINTER(_i32), _dp], ctypes.c_int),
     "tled_set_heat_source": ([_P, _dp, _d, _d], ctypes.c_int),
@@ -118,6 +121,8 @@ _SIGS = {
     "tled_critical_dt": ([_P, _dp], ctypes.c_int),
     "tled_finalize": ([_P], ctypes.c_int),
     "tled_step": ([_P, _i64], ctypes.c_int),
+    "tled_stream_copy": ([ctypes.c_int, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "tled_prepare_steps": ([_P, _i64], ctypes.c_int),
     "tled_sync": ([_P], ctypes.c_int),
     "tled_read_u": ([_P, _dp], ctypes.c_int),
     "tled_read_T": ([_P, _dp], ctypes.c_int),
@@ -271,6 +276,27 @@ class Sim:
     def set_fibres(self, a0):
         self._check(_lib.tled_set_fibres(self._h, _ptr(_f64(a0))))
 
+    def set_expansion_axes(self, n0):
+        """Second axis of the orthotropic expansion per element (n_elems x 3)."""
+        if n0 is not None:
+            n0 = _f64(n0)
+            if n0.shape != (self.ne, 3):
+                raise ValueError(f"expansion axes must be ({self.ne}, 3), got {n0.shape}")
+        self._check(_lib.tled_set_expansion_axes(self._h, _ptr(n0)))
+
+    def set_conductivity(self, D):
+        """Conductivity tensor per element: n_elems x 3 x 3 (symmetric) or n_elems x 6 (xx yy zz xy yz xz)."""
+        if D is None:
+            self._check(_lib.tled_set_conductivity(self._h, None))
+            return
+        D = np.asarray(D, dtype=np.float64)
+        if D.ndim == 3 and D.shape[1:] == (3, 3):
+            D = np.stack([D[:, 0, 0], D[:, 1, 1], D[:, 2, 2], D[:, 0, 1], D[:, 1, 2], D[:, 0, 2]], 1)
+        D = _f64(D)
+        if D.shape != (self.ne, 6):
+            raise ValueError(f"conductivity tensors must be ({self.ne}, 3, 3) or ({self.ne}, 6), got {D.shape}")
+        self._check(_lib.tled_set_conductivity(self._h, _ptr(D)))
+
     def set_fixed_dofs(self, nodes, masks):
         nodes = np.ascontiguousarray(nodes, dtype=np.int32)
         masks = np.ascontiguousarray(masks, dtype=np.uint8)
@@ -301,6 +327,10 @@ class Sim:
     # ------------------------------------------------------------------ run
     def step(self, n: int):
         self._check(_lib.tled_step(self._h, int(n)))
+
+    def prepare(self, n: int):
+        """Capture the hipGraphs a following step(n) replays, without running anything."""
+        self._check(_lib.tled_prepare_steps(self._h, int(n)))
 
     def sync(self):
         self._check(_lib.tled_sync(self._h))
@@ -372,6 +402,20 @@ class Sim:
         return {"element_ms": ms[0], "node_ms": ms[1], "finish_ms": ms[2]}
 
 
+def stream_copy(dst, src, stream=None):
+    """The library's plain streaming copy of one device tensor into another of the same size."""
+    import torch
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("stream_copy needs contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or dst.device != src.device:
+        raise ValueError("stream_copy needs tensors of one size on one device")
+    st = _lib.tled_stream_copy(int(src.device.index), _P(dst.data_ptr()), _P(src.data_ptr()), nbytes,
+                               _P(int(stream) if stream is not None else torch.cuda.current_stream(src.device).cuda_stream))
+    if st != OK:
+        raise TledError(st, "tled_stream_copy failed")
+
+
 def from_problem(problem, dt=None, device: int = 0, stream=None, finalize: bool = True,
                  use_torch_allocator: bool = False, **options) -> Sim:
     """Set up a :class:`Sim` from a :class:`workloads.Problem` (dt defaults to cfl * critical step)."""
@@ -382,6 +426,10 @@ def from_problem(problem, dt=None, device: int = 0, stream=None, finalize: bool 
     s.set_material(problem.params)
     if problem.a0 is not None:
         s.set_fibres(problem.a0)
+    if problem.n0 is not None:
+        s.set_expansion_axes(problem.n0)
+    if problem.D is not None:
+        s.set_conductivity(problem.D)
     if problem.fix is not None:
         nodes = np.nonzero(problem.fix & 7)[0]
         if len(nodes):

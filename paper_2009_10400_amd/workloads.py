@@ -105,6 +105,8 @@ class Problem:
     conn: np.ndarray         # ne x npe
     params: dict
     a0: np.ndarray | None = None      # ne x 3
+    n0: np.ndarray | None = None      # ne x 3 second thermal-expansion axis (orthotropic mode)
+    D: np.ndarray | None = None       # ne x 3 x 3 conductivity tensors (tensor mode)
     q: np.ndarray | None = None       # ne, W/m^3
     fix: np.ndarray | None = None     # nn uint8 (bit0..2 u, bit3 T)
     Tfix: np.ndarray | None = None    # nn

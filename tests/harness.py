@@ -24,7 +24,7 @@ def log(*a):
 def oracle_sim(problem: W.Problem, dt: float) -> oracle.OracleSim:
     return oracle.OracleSim(problem.npe, problem.X, problem.conn, problem.params, a0=problem.a0,
                             q=problem.q, fix=problem.fix, Tfix=problem.Tfix, t_on=problem.t_on,
-                            t_off=problem.t_off, dt=dt, gamma=problem.gamma)
+                            t_off=problem.t_off, dt=dt, gamma=problem.gamma, n0=problem.n0, D=problem.D)
 
 
 def gpu_sim(problem: W.Problem, dt=None, **opts):

@@ -25,14 +25,15 @@ def critical_dt(problem):
     return dt
 
 
-@pytest.mark.parametrize("graph_steps", [40, -1])
-def test_batch_equals_single_runs_bitwise_and_holds(graph_steps):
+@pytest.mark.parametrize("graph_steps,schedule", [(40, 0), (-1, 0), (40, 1), (-1, 1), (7, 1)])
+def test_batch_equals_single_runs_bitwise_and_holds(graph_steps, schedule):
     # scenarios end at different steps, most of them inside a chunk: a step launches only the
-    # scenarios still running (graph chunks: those running at the chunk's first step)
+    # scenarios still running (graph chunks: those running at the chunk's first step); the work
+    # queue (schedule 1) counts them on the device and the resident workgroups pull their patches
     from paper_2009_10400_amd import tled
     sc, steps = small_batch()
     b = tled.Batch(0)
-    b.set_options(graph_steps=graph_steps)
+    b.set_options(graph_steps=graph_steps, batch_schedule=schedule)
     dts = []
     for (p, _), n in zip(sc, steps):
         dt = 0.8 * critical_dt(p)
@@ -51,8 +52,8 @@ def test_batch_equals_single_runs_bitwise_and_holds(graph_steps):
                               patch_elems=448 if p.npe == 4 else 256)
         s.step(n)
         us, Ts = s.read_u(), s.read_T()
-        assert np.array_equal(ub, us), k
-        assert np.array_equal(Tb, Ts), k
+        assert np.array_equal(ub, us), (k, float(np.abs(ub - us).max()), float(np.abs(us).max()))
+        assert np.array_equal(Tb, Ts), (k, float(np.abs(Tb - Ts).max()))
         assert Tb.max() > p.params["T0"]
     # stepping further changes nothing: every scenario has reached its end
     before = [b.read(k) for k in range(len(sc))]

@@ -67,6 +67,41 @@ def test_physics_variants(name, npe):
     assert err["T_abs"] <= T_ABS_TOL
 
 
+def _anisotropic(p, expansion: bool, conduction: bool, seed: int = 17):
+    """Orthotropic expansion (Eq. 11: a second axis per element, given with a component along the
+    fibre that the library removes) and/or a conductivity tensor per element (Eqs. 15-16: random
+    symmetric positive definite, eigenvalues 0.3-1.5 W/(m K))."""
+    rng = np.random.default_rng(seed)
+    ne = p.ne
+    if expansion:
+        p.params = dict(p.params, expan_mode=2, alpha_m=3e-4, alpha_n=-1.5e-4)
+        a0 = p.a0 if p.a0 is not None else np.tile([1.0, 0.0, 0.0], (ne, 1))
+        n = rng.standard_normal((ne, 3))
+        p.n0 = n + 0.3 * a0
+    if conduction:
+        p.params = dict(p.params, cond_mode=2)
+        q, r = np.linalg.qr(rng.standard_normal((ne, 3, 3)))
+        lam = rng.uniform(0.3, 1.5, (ne, 3))
+        p.D = np.einsum("eij,ej,ekj->eik", q, lam, q)
+    return p
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("npe", [4, 8])
+@pytest.mark.parametrize("mode", ["ortho_expansion", "tensor_conduction", "both_with_kT"])
+def test_anisotropic_variants(mode, npe, variant):
+    """Orthotropic thermal expansion and per-element conductivity tensors against the oracle,
+    all three kernel variants, T4 and H8."""
+    p = W.cube_t4(n=6, L=0.024) if npe == 4 else W.cube_h8(n=8, L=0.04, power=5.0)
+    p = _anisotropic(p, mode != "tensor_conduction", mode != "ortho_expansion")
+    if mode == "both_with_kT":
+        p.params = dict(p.params, ckT_on=1, ckT_lo=310.15, ckT_hi=312.0, c_hi=4300.0, k_hi=0.75)
+    err, _, _ = run_parity(p, 400, kernel_variant=variant)
+    assert err["u_rel"] <= U_REL_TOL
+    assert err["T_abs"] <= T_ABS_TOL
+    assert err["u_max"] > 1e-8            # the field is not trivially zero
+
+
 def test_fixed_temperature_and_flipped_elements():
     """Dirichlet T on one face, 30 % of tets given with negative orientation, random numbering."""
     p = W.cube_t4(n=6, L=0.024)

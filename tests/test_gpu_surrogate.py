@@ -124,14 +124,23 @@ def test_gradient_matches_fp64_reference(torch_dev, depth, width):
     lr, gr = R.loss_and_grad(_ref_theta(mlp), x.astype(np.float64), p.astype(np.float64), t.astype(np.float64),
                              B, cfg)
     assert abs(loss - lr) <= 1e-2 * lr
+    mag = R.grad_magnitude(_ref_theta(mlp), x.astype(np.float64), p.astype(np.float64), t.astype(np.float64),
+                           B, cfg)
     lay, _, _ = R.layout(**cfg)
     for l, (ws, _, bs) in enumerate(lay):
         for sl in (ws, bs):
-            a, b = g[sl].astype(np.float64), gr[sl]
+            a, b, m = g[sl].astype(np.float64), gr[sl], mag[sl]
+            err = np.abs(a - b)
             rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-            print(f"  layer {l} {'W' if sl is ws else 'b'}: rel {rel:.2e} cos {cos:.6f}", flush=True)
-            assert rel < 4e-2 and cos > 0.999, (l, rel, cos)
+            elem = err.max() / np.abs(b).max()              # every element, against the layer's largest
+            term = (err / np.maximum(m, 1e-300)).max()      # every element, against its terms' magnitude
+            print(f"  layer {l} {'W' if sl is ws else 'b'}: norm rel {rel:.2e}, max elem err / max |g| "
+                  f"{elem:.2e}, max elem err / sum|terms| {term:.2e}", flush=True)
+            # element-wise: every gradient entry within 0.5 % of the layer's largest entry, and
+            # within 3 % of the sum of the magnitudes of the terms that make it (bfloat16
+            # activations and weights round at 2^-9 relative, a few times through the layers)
+            assert elem <= 5e-3, (l, elem)
+            assert term <= 3e-2, (l, term)
 
 
 def test_training_reduces_loss_and_is_deterministic(torch_dev):

@@ -404,3 +404,42 @@ def test_bisection_patches_match_an_independent_implementation(n, P):
     assert info["n_patches"] == -(-p.ne // P)
     assert info["n_shared_nodes"] == n_shared
     assert info["patch_max_nodes"] == max_nodes
+
+
+def test_anisotropic_setup_errors_and_thermal_bound():
+    """Orthotropic expansion (Eq. 11) and element conductivity tensors (Eqs. 15-16) at set-up: a
+    missing second axis or tensor, an axis parallel to the fibre and a tensor that is not positive
+    semi-definite are refused with TLED_E_ARG; batches refuse both modes; the explicit thermal bound
+    with a tensor k I is no larger than with the scalar k (its Frobenius norm bounds the largest
+    eigenvalue)."""
+    from paper_2009_10400_amd import tled
+    cases = ((dict(expan_mode=2), None, None), (dict(cond_mode=2), None, None),
+             (dict(expan_mode=2), lambda ne: np.tile([2.0, 0.0, 0.0], (ne, 1)), None),
+             (dict(cond_mode=2), None, lambda ne: np.tile(np.diag([1.0, -0.5, 1.0]), (ne, 1, 1))),
+             (dict(cond_mode=2), None, lambda ne: np.tile([[1.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 1.0]],
+                                                          (ne, 1, 1))))
+    for params, n0, D in cases:
+        q = W.cube_t4(n=2, L=0.01)
+        q.params = dict(q.params, **params)
+        q.n0 = n0(q.ne) if n0 else None
+        q.D = D(q.ne) if D else None
+        with pytest.raises(tled.TledError) as ei:
+            host_sim(q)
+        assert ei.value.status == tled.E_ARG, params
+    p = W.cube_t4(n=3, L=0.012)
+    ok = W.cube_t4(n=3, L=0.012)
+    ok.params = dict(ok.params, cond_mode=2, expan_mode=2, alpha_m=3e-4, alpha_n=-1e-4)
+    ok.D = np.tile(ok.params["k"] * np.eye(3), (ok.ne, 1, 1))
+    ok.n0 = np.tile([0.2, 1.0, 0.0], (ok.ne, 1))
+    dt_iso, dt_ten = host_sim(p).info()["dt_thermal"], host_sim(ok).info()["dt_thermal"]
+    assert 0.0 < dt_ten <= dt_iso
+    b = tled.Batch(-1)
+    with pytest.raises(tled.TledError) as ei:
+        b.add(ok, dt=1e-5, n_steps=1)
+    assert ei.value.status == tled.E_UNSUPPORTED
+    s = tled.Sim(-1)
+    s.set_mesh(4, p.X, p.conn)
+    with pytest.raises(ValueError):
+        s.set_expansion_axes(np.zeros((p.ne + 1, 3)))
+    with pytest.raises(ValueError):
+        s.set_conductivity(np.zeros((p.ne, 5)))
