@@ -44,11 +44,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--variant", type=int, default=2)
+    ap.add_argument("--variant", type=int, default=0, help="kernel variant (0: the library default)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="steps per hipGraph chunk (0: library default, 50 for a problem, eager steps for a batch)")
     ap.add_argument("--patch-elems", type=int, default=0, help="elements per patch (0: library default)")
     ap.add_argument("--block-size", type=int, default=0, help="patch kernel threads per workgroup (0: default)")
+    ap.add_argument("--shared-update", type=int, default=0, choices=[0, 1, 2],
+                    help="shared nodes advanced inside the next step's patch kernel (1, the default where "
+                         "available) or by a kernel of their own after every step (2)")
     ap.add_argument("--reorder", type=int, default=0,
                     help="element order: 0/1 Morton with bisection patches, 2 Morton runs, -1 as generated")
     ap.add_argument("--elems", type=int, default=1_000_000)
@@ -66,7 +69,7 @@ def parse():
                     help="sweep heating durations are U(30, 300) s times this factor")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--schedule", default="auto", choices=["auto"] + ["prefix-eager", "prefix-graph-50",
-                                                                        "queue-graph-100", "queue-graph-400"],
+                                                                        "persistent-graph-100", "persistent-graph-400"],
                     help="batch launch schedule of the sweep (auto: chosen by the autotuner)")
     ap.add_argument("--surrogate", type=int, default=0, metavar="N_TRAIN",
                     help="instead of the headline run: train the surrogate ensemble on N_TRAIN planning runs and "
@@ -81,7 +84,7 @@ def parse():
                          "separate runs)")
     ap.add_argument("--shard-nodes", type=int, default=2048, help="nodes stored per snapshot field")
     ap.add_argument("--surrogate-schedule", type=int, default=0, choices=[0, 1],
-                    help="batch schedule of the surrogate's solver runs (1: work queue in graph chunks of 100)")
+                    help="batch schedule of the surrogate's solver runs (1: persistent kernels in graph chunks of 100)")
     ap.add_argument("--calib", type=int, default=100, help="solver runs held back to calibrate the disagreement")
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--members", type=int, default=4)
@@ -152,10 +155,13 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
     f = _counter_means(fetch_db, "FETCH_SIZE")
     w = _counter_means(write_db, "WRITE_SIZE")
 
-    def pick(d, name):
-        """The instantiation of the kernel with the most dispatches (the steady-state one)."""
-        k = max((k for k in d if f"{name}<" in k), key=lambda k: d[k][1])
-        return d[k]
+    def pick(d, name, second=False):
+        """The instantiation of the kernel with the most dispatches (the steady-state one), or
+        with second=True the one with the next most (None if there is none)."""
+        ks = sorted((k for k in d if f"{name}<" in k), key=lambda k: -d[k][1])
+        if second:
+            return d[ks[1]] if len(ks) > 1 else None
+        return d[ks[0]]
 
     fk, nd = pick(f, "patch_kernel")
     wk, _ = pick(w, "patch_kernel")
@@ -165,15 +171,25 @@ def counters_summary(workload, fetch_db, write_db, copy_fetch_db, copy_write_db,
     h = tled.from_problem(p, device=-1)
     info = h.info()
     h.close()
-    alg = elem_bytes(p.npe, info["n_prony"]) * p.ne + NODE_BYTES * (info["n_nodes"] - info["n_shared_nodes"])
+    fused = info["shared_update"] == 1
+    # a fused launch advances every node (its patch's interior nodes by this step, its shared
+    # nodes by the previous one); an unfused one the interior nodes only
+    alg = elem_bytes(p.npe, info["n_prony"]) * p.ne + NODE_BYTES * (
+        info["n_nodes"] if fused else info["n_nodes"] - info["n_shared_nodes"])
+    first = None
+    if fused:   # the first step of each chunk runs the unfused patch kernel
+        f2, w2 = pick(f, "patch_kernel", True), pick(w, "patch_kernel", True)
+        if f2 is not None and w2 is not None:
+            first = [f2[0], w2[0]]
     out = {"kernel": "patch_kernel", "workload": workload, "source_digest": source_digest(),
            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk, "fetch_scale": fetch_scale,
            "write_scale": write_scale,
            "bytes_per_launch": fk * 1024.0 * fetch_scale + wk * 1024.0 * write_scale,
            "algorithmic_bytes_per_launch": alg, "dispatches": nd,
            "layout": {"kernel_variant": info["kernel_variant"], "n_patches": info["n_patches"],
-                      "n_shared_nodes": info["n_shared_nodes"]},
+                      "n_shared_nodes": info["n_shared_nodes"], "shared_update": info["shared_update"]},
            "shared_node_kernel_kib": [sf, sw],
+           "chunk_first_patch_kernel_kib": first,
            "note": f"scales from a plain {copy_mib} MiB device copy (FETCH_SIZE read {cf[1][0]:.1f} KiB, "
                    f"WRITE_SIZE {cw[1][0]:.1f} KiB)"}
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -196,7 +212,8 @@ def traffic_record(workload: str, info=None):
             return None
         if info is not None:
             lay = d.get("layout", {})
-            if any(lay.get(k) != info[k] for k in ("kernel_variant", "n_patches", "n_shared_nodes")):
+            if any(lay.get(k) != info[k] for k in ("kernel_variant", "n_patches", "n_shared_nodes",
+                                                    "shared_update")):
                 return None
         return d
     except Exception:  # noqa: BLE001
@@ -386,7 +403,7 @@ def sweep(args):
                    "duration_scale": args.duration_scale, "autotune": {str(k): v for k, v in choice.items()},
                    "schedule": sched, "schedule_options": sched_opts,
                    "launch": ({0: "each step launches the patches of the scenarios still running, counted on the host",
-                               1: "work queue: resident workgroups pull the step's patches; running scenarios "
+                               1: "persistent: resident workgroups walk the step's patches; running scenarios "
                                   "counted on the device"}[sched_opts.get("batch_schedule", 0)] +
                               (f"; hipGraph chunks of {sched_opts['graph_steps']} steps"
                                if sched_opts.get("graph_steps", 0) > 0 else "; eager steps"))},
@@ -578,7 +595,7 @@ def main():
     stream = torch.cuda.Stream(device=0)
     sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, kernel_variant=args.variant,
                             graph_steps=args.graph_steps, patch_elems=args.patch_elems,
-                            block_size=args.block_size, reorder=args.reorder)
+                            block_size=args.block_size, reorder=args.reorder, shared_update=args.shared_update)
     info = sim.info()
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
     sim.step(args.warmup)
@@ -607,9 +624,18 @@ def main():
     sim.sync()
     kname = "patch_kernel" if info["kernel_variant"] >= 2 else ("t4_element_kernel" if p.npe == 4 else "h8_element_kernel")
     eb = elem_bytes(p.npe, info["n_prony"])
+    fused = info["shared_update"] == 1
+    chunk = args.graph_steps if args.graph_steps > 0 else (50 if args.graph_steps == 0 else 100)
+
+    def n_chunks(k):   # tled_step(k) and tled_kernel_times(k) run ceil(k / chunk) chunks
+        return -(-k // chunk)
+
     if info["kernel_variant"] >= 2:
         n_interior = info["n_nodes"] - info["n_shared_nodes"]
-        alg_bytes = eb * p.ne + NODE_BYTES * n_interior
+        # per launch, averaged over the timed steps: a fused launch also advances the shared
+        # nodes by the previous step; the first launch of each chunk does not
+        f_frac = (args.kernel_steps - n_chunks(args.kernel_steps)) / args.kernel_steps if fused else 0.0
+        alg_bytes = eb * p.ne + NODE_BYTES * (n_interior + f_frac * info["n_shared_nodes"])
     else:
         alg_bytes = eb * p.ne + 16.0 * p.npe * p.ne   # plus the nodal outputs it writes
     achieved = alg_bytes / (kt["element_ms"] * 1e-3) / 1e9
@@ -625,7 +651,17 @@ def main():
     rec = traffic_record(key, info) if info["kernel_variant"] >= 2 else None
     if rec is not None:
         sf, sw = rec["shared_node_kernel_kib"]
-        step_bytes = rec["bytes_per_launch"] + 1024.0 * (sf * rec["fetch_scale"] + sw * rec["write_scale"])
+        shared_bytes = 1024.0 * (sf * rec["fetch_scale"] + sw * rec["write_scale"])
+        if fused:
+            # per timed step: the fused patch kernel, except the unfused first launch of each
+            # chunk, and one shared-node kernel per chunk
+            nc = n_chunks(args.steps)
+            first = rec.get("chunk_first_patch_kernel_kib")
+            first_bytes = (1024.0 * (first[0] * rec["fetch_scale"] + first[1] * rec["write_scale"])
+                           if first else rec["bytes_per_launch"])
+            step_bytes = ((args.steps - nc) * rec["bytes_per_launch"] + nc * (first_bytes + shared_bytes)) / args.steps
+        else:
+            step_bytes = rec["bytes_per_launch"] + shared_bytes
         gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
         cbw = copy_bandwidth()
         step_hbm = {"bytes_counted": step_bytes, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
@@ -651,6 +687,8 @@ def main():
                    "shared_node_fraction": info["n_shared_nodes"] / max(1, info["n_nodes"]),
                    "patch_lds_bytes": info["patch_lds_bytes"],
                    "patch_wgs_per_cu": info["patch_wgs_per_cu"],
+                   "shared_update": {1: "fused into the next step's patch kernel",
+                                     2: "shared-node kernel every step"}.get(info["shared_update"], "none"),
                    "patch_order": {-1: "as generated", 2: "Morton runs"}.get(args.reorder, "coordinate bisection"),
                    "dt": sim.dt},
         "roofline": roof,

@@ -107,10 +107,10 @@ typedef struct {
                                  the scenarios still running; a batch's graph launches those
                                  running at its first step and is captured again when that
                                  set has changed.                                             */
-    int32_t kernel_variant;   /* 0: default (2); 1: two-pass element/node kernels with precomputed
-                                 geometry; 2: fused patch kernels rebuilding the geometry from
-                                 patch-local coordinates; 3: fused patch kernels reading the
-                                 precomputed geometry                                          */
+    int32_t kernel_variant;   /* 0: default (2 for T4, 3 for H8); 1: two-pass element/node
+                                 kernels with precomputed geometry; 2: fused patch kernels
+                                 rebuilding the geometry from patch-local coordinates; 3: fused
+                                 patch kernels reading the precomputed geometry               */
     int32_t reorder;          /* 0: auto (= 1); 1: elements along a Morton curve of their
                                  centroids, and for the fused variants patches cut by recursive
                                  coordinate bisection; 2: Morton order, patches are runs of it;
@@ -125,13 +125,23 @@ typedef struct {
     int32_t batch_schedule;   /* batches only, set before finalize.  0: each step launches the
                                  patches of the scenarios still running, counted on the host
                                  (eager steps, or hipGraph chunks captured again whenever that
-                                 set changes); 1: work queue: the patch kernel runs with the
-                                 workgroups that are resident at once, which pull the step's
-                                 patches from per-XCD device counters, and the running
-                                 scenarios are counted on the device from the step counter, so
-                                 one captured chunk of graph_steps steps (default 100) serves
-                                 the whole batch                                             */
-    int32_t reserved;
+                                 set changes); 1: persistent: the patch kernel runs with the
+                                 workgroups that are resident at once, which walk the step's
+                                 patches (each XCD's workgroups an eighth of them), and the
+                                 running scenarios are counted on the device from the step
+                                 counter, so one captured chunk of graph_steps steps (default
+                                 100) serves the whole batch                                             */
+    int32_t shared_update;    /* set before finalize.  How the nodes shared between patches are
+                                 advanced (Eqs. 20 and 27 on their summed patch partials):
+                                 0: default (1 where available, else 2); 1: inside the next
+                                 step's patch kernel: every patch holding a shared node sums its
+                                 partials and advances it while staging, the patch that wrote
+                                 its first partial stores it, and one shared-node kernel ends
+                                 each chunk (single problems with kernel_variant 2, 256-thread
+                                 workgroups and neither the orthotropic expansion nor the
+                                 tensor conduction; elsewhere as 2); 2: a shared-node kernel
+                                 after every step's patch kernel.  The fields are the same
+                                 bits either way                                              */
 } tled_options;
 
 typedef struct {
@@ -159,7 +169,9 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the handle                              */
     double  dt, dt_critical;
     int32_t patch_wgs_per_cu; /* fused variant on a device: resident patch workgroups per CU  */
-    int32_t reserved;
+    int32_t shared_update;   /* fused variant with shared nodes: 1 advanced inside the next
+                                step's patch kernel, 2 by a kernel of their own each step (see
+                                tled_options.shared_update); else 0                           */
     double  dt_thermal;      /* explicit thermal stability bound (Gershgorin, reference
                                 geometry, largest k and smallest c the material reaches);
                                 finalize refuses a dt above it                             */

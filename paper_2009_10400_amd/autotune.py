@@ -8,8 +8,8 @@ workgroups that can fill the GPU and the idle tail of the last round.  For each
 size bucket the tuner builds a small batch of that bucket's scenarios, times a
 few steps of it per candidate patch size (HIP events on the library's stream)
 and keeps the fastest.  The schedule (how each batch step is launched: eager steps or hipGraph
-chunks over the scenarios the host counts as running, or the work queue in graph chunks of a given
-length) is a property of the whole batch: the tuner runs a sample of the batch's scenarios, with
+chunks over the scenarios the host counts as running, or the persistent kernels in graph chunks of
+a given length) is a property of the whole batch: the tuner runs a sample of the batch's scenarios, with
 their uneven end steps scaled down, to completion under each candidate and keeps the fastest.
 Timing only: the physics does not depend on either choice (a scenario's fields are the same bits
 under every schedule).
@@ -25,8 +25,8 @@ CANDIDATES = (192, 256, 320, 384, 448, 504)
 SCHEDULES = {
     "prefix-eager": dict(batch_schedule=0, graph_steps=-1),
     "prefix-graph-50": dict(batch_schedule=0, graph_steps=50),
-    "queue-graph-100": dict(batch_schedule=1, graph_steps=100),
-    "queue-graph-400": dict(batch_schedule=1, graph_steps=400),
+    "persistent-graph-100": dict(batch_schedule=1, graph_steps=100),
+    "persistent-graph-400": dict(batch_schedule=1, graph_steps=400),
 }
 
 

@@ -22,7 +22,7 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 # The solver kernels fuse a multiply and an add only inside one source expression
 # (-ffp-contract=on), never across statements: every instantiation of a kernel
-# (single problem, batch, work queue) then rounds the same way, which keeps a
+# (single problem, batch, persistent batch) then rounds the same way, which keeps a
 # batch's scenarios equal bit for bit to their single runs.
 SOURCE_FLAGS = {"kernels.hip": ["-ffp-contract=on"]}
 

@@ -87,9 +87,14 @@ struct tled_sim {
     // the patch and shared-node counts of the prefix ending at the position
     std::vector<int64_t> pos_end, pos_shared_hi;
     std::vector<int32_t> pos_patch_hi;
-    // work-queue schedule: grids of the patch and shared-node kernels
+    // persistent schedule of a batch: grids of the patch and shared-node kernels
     bool queue = false;
     int q_grid = 0, q_sgrid = 0;
+    // shared nodes advanced inside the next step's patch kernel: the second
+    // partial buffer and the second shared-node state buffer (the first ones
+    // are pa.partial and the shared tail of nu4, nv4)
+    bool fuse = false;
+    float4 *d_part2 = nullptr, *d_sux = nullptr, *d_svx = nullptr;
 };
 
 namespace {
@@ -111,6 +116,24 @@ int default_patch_elems(int npe, int64_t ne, int block_size) {
         const int64_t pe = ((ne + k * slots - 1) / (k * slots) + 7) / 8 * 8;
         if (pe <= pe_max) return int(std::max<int64_t>(pe, 128));
     }
+}
+
+// Default kernel variant: fused patches for both element types; T4 rebuilds the
+// geometry from the staged coordinates (variant 2), H8 reads the precomputed
+// geometry planes (variant 3), whose smaller LDS footprint (no staged
+// coordinates: 39.2 KB for 256-element patches, against 45.7 KB) lets four
+// workgroups share a CU, and whose kernel is compiled for four waves per SIMD
+// (64³ cube: 20.1 us per step against 23.0 us for variant 2).
+int default_variant(int npe) { return npe == 8 ? 3 : 2; }
+
+// Whether the shared nodes of a finalized handle are advanced inside the next
+// step's patch kernel: single problems with kernel variant 2, 256-thread
+// workgroups, no anisotropy plane and some shared node, unless shared_update = 2.
+bool fused_shared_nodes(const tled_sim *s) {
+    const tled_material &m = s->prob.mat;
+    return !s->is_batch && s->variant == 2 && (s->opt.block_size == 0 || s->opt.block_size == kBlock) &&
+           m.expan_mode != 2 && m.cond_mode != 2 && s->opt.shared_update != 2 &&
+           s->pc.nn > s->pc.patches.n_interior;
 }
 
 tled_status fail(tled_sim *s, tled_status st, const std::string &msg) {
@@ -423,6 +446,24 @@ tled_status upload_all(tled_sim *s) {
         float4 *dpart;
         TRY(zeros(s, &dpart, std::max<size_t>(P.shared_ids.size(), 1)));
         a.partial = dpart;
+        a.su_in = dnu4 + a.n_interior;
+        a.sv_in = dnv4 + a.n_interior;
+        s->fuse = fused_shared_nodes(s);
+        if (s->fuse) {
+            // per shared entry, its node's range of partials
+            std::vector<int32_t> sr(2 * P.shared_ids.size());
+            for (size_t q = 0; q < P.shared_ids.size(); ++q) {
+                const int64_t sn = P.shared_ids[q] - P.n_interior;
+                sr[2 * q] = P.srow[sn];
+                sr[2 * q + 1] = P.srow[sn + 1];
+            }
+            int *dsr;
+            TRY(upload(s, &dsr, sr));
+            a.srange = reinterpret_cast<const int2 *>(dsr);
+            TRY(zeros(s, &s->d_part2, P.shared_ids.size()));
+            TRY(zeros(s, &s->d_sux, size_t(a.n_shared)));
+            TRY(zeros(s, &s->d_svx, size_t(a.n_shared)));
+        }
         a.step_base = s->d_step;
         a.status = s->d_status;
         s->n_elem_parts = P.n;
@@ -433,7 +474,7 @@ tled_status upload_all(tled_sim *s) {
             int cus = 0;
             HIPCHK(s, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device));
             const int occ = patch_queue_occupancy(npe, s->np, s->variant == 2, a);
-            if (occ <= 0) return fail(s, TLED_E_HIP, "work-queue patch kernel does not fit on a CU");
+            if (occ <= 0) return fail(s, TLED_E_HIP, "persistent patch kernel does not fit on a CU");
             s->q_grid = std::max(1, std::min(a.n_patches, occ * cus));
             s->q_sgrid = int(std::max<int64_t>(1, std::min<int64_t>((a.n_shared + kBlock - 1) / kBlock, 8 * cus)));
             s->n_node_parts = P.n + s->q_sgrid;
@@ -461,9 +502,6 @@ tled_status upload_all(tled_sim *s) {
         TRY(upload(s, &s->d_ranges, rng));
         TRY(zeros(s, &s->d_scen_mon, 2 * S));
         if (s->queue) {
-            int *dq;
-            TRY(zeros(s, &dq, kNumXcd));
-            a.queue = dq;
             std::vector<long long> pe(s->pos_end.begin(), s->pos_end.end()), ps(s->pos_shared_hi.begin(),
                                                                                 s->pos_shared_hi.end());
             long long *dpe, *dps;
@@ -502,7 +540,7 @@ void single_scenario(tled_sim *s) {
 void active_counts(const tled_sim *s, int64_t step, int *n_patches, int64_t *n_shared) {
     *n_patches = s->pa.n_patches;
     *n_shared = s->pa.n_shared;
-    if (!s->is_batch || s->queue || s->pos_end.empty()) return;   // the work queue counts on the device
+    if (!s->is_batch || s->queue || s->pos_end.empty()) return;   // the persistent kernels count on the device
     const auto it = std::partition_point(s->pos_end.begin(), s->pos_end.end(), [&](int64_t e) { return e > step; });
     const size_t m = size_t(it - s->pos_end.begin());
     // never more than the union holds (a batch may have no shared node at all)
@@ -510,7 +548,7 @@ void active_counts(const tled_sim *s, int64_t step, int *n_patches, int64_t *n_s
     *n_shared = std::min<int64_t>(s->pa.n_shared, std::max<int64_t>(1, m ? s->pos_shared_hi[m - 1] : 0));
 }
 
-// Work-queue schedule: the running scenarios' patch and shared-node counts of
+// Persistent schedule: the running scenarios' patch and shared-node counts of
 // step `step`, written into that step's parity slot (the kernels keep the slots
 // current from then on).  Asynchronous on the library's stream; `h` must stay
 // alive until the stream has passed the copy.
@@ -558,11 +596,37 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
             launch_shared_nodes_queue(mon, s->pa, j, s->q_sgrid, s->stream, ev ? &t1 : nullptr);
             continue;
         }
-        if (s->variant == 1) launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
-        else launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, pa, j, s->stream, ev ? &t0 : nullptr);
+        // Fused shared nodes (chunks of two or more steps): step j > 0's patch
+        // kernel first advances the shared nodes by step j - 1 from that step's
+        // partials; partials and shared state alternate between two buffers
+        // (state buffer 0 is the shared tail of nu4, nv4); one shared-node
+        // kernel after the chunk's last step writes the shared state to nu4, nv4.
+        const bool fuse = s->fuse && k >= 2;
+        bool shared_launch = s->variant != 1 && pa.n_shared > 0;
+        if (fuse) {
+            float4 *const part[2] = {s->pa.partial, s->d_part2};
+            float4 *const su[2] = {s->pa.nu4 + pa.n_interior, s->d_sux};
+            float4 *const sv[2] = {s->pa.nv4 + pa.n_interior, s->d_svx};
+            pa.partial = part[j & 1];
+            pa.partial_prev = part[(j + 1) & 1];
+            pa.su_in = su[(j + 1) & 1];
+            pa.sv_in = sv[(j + 1) & 1];
+            pa.su_out = su[j & 1];
+            pa.sv_out = sv[j & 1];
+            launch_patch(npe, s->np, mon, true, bs, false, pa, j, s->stream, ev ? &t0 : nullptr, j > 0);
+            shared_launch = (j == k - 1);
+            if (shared_launch) {   // reads the state this step's patch kernel stored
+                pa.su_in = su[j & 1];
+                pa.sv_in = sv[j & 1];
+            }
+        } else if (s->variant == 1) {
+            launch_element(npe, s->np, mon, s->tp, s->km, s->stream, ev ? &t0 : nullptr);
+        } else {
+            launch_patch(npe, s->np, mon, s->variant == 2, bs, s->is_batch, pa, j, s->stream, ev ? &t0 : nullptr);
+        }
         if (s->variant == 1) launch_node(mon, s->tp, s->nparams, j, s->stream, ev ? &t1 : nullptr);
-        else if (pa.n_shared > 0) launch_shared_nodes(mon, s->is_batch, pa, j, s->stream, ev ? &t1 : nullptr);
-        else if (ev) {   // no shared node, nothing to launch: the timed launch takes zero time
+        else if (shared_launch) launch_shared_nodes(mon, s->is_batch, pa, j, s->stream, ev ? &t1 : nullptr);
+        else if (ev) {   // no shared-node launch at this step: the timed launch takes zero time
             HIPCHK(s, hipEventRecord(t1.start, s->stream));
             HIPCHK(s, hipEventRecord(t1.stop, s->stream));
         }
@@ -641,6 +705,15 @@ tled_status check_status(tled_sim *s) {
         if (flags & TLED_FLAG_INVERTED) m += " inverted elements (det F <= 0)";
         return fail(s, TLED_E_UNSTABLE, m);
     }
+    return TLED_OK;
+}
+
+// LDS a patch workgroup may take: the device's per-workgroup limit less 1 KiB
+// for the kernels' static reduction arrays (host-only handles assume 64 KiB).
+tled_status patch_lds_limit(tled_sim *s, size_t *lim) {
+    int v = 65536;
+    if (s->device >= 0) HIPCHK(s, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device));
+    *lim = size_t(v) - 1024;
     return TLED_OK;
 }
 
@@ -753,9 +826,11 @@ tled_status tled_set_options(tled_sim *sim, const tled_options *opt) {
         return fail(sim, TLED_E_UNSUPPORTED, "block_size must be 256 or 512");
     if (opt->batch_schedule < 0 || opt->batch_schedule > 1) return fail(sim, TLED_E_ARG, "batch_schedule must be 0 or 1");
     if (opt->batch_schedule == 1 && !sim->is_batch)
-        return fail(sim, TLED_E_ARG, "batch_schedule 1 (work queue) is for batch handles");
+        return fail(sim, TLED_E_ARG, "batch_schedule 1 (persistent) is for batch handles");
+    if (opt->shared_update < 0 || opt->shared_update > 2) return fail(sim, TLED_E_ARG, "shared_update must be 0..2");
     if (sim->finalized && (opt->kernel_variant != sim->opt.kernel_variant || opt->reorder != sim->opt.reorder ||
-                           opt->patch_elems != sim->opt.patch_elems || opt->batch_schedule != sim->opt.batch_schedule))
+                           opt->patch_elems != sim->opt.patch_elems || opt->batch_schedule != sim->opt.batch_schedule ||
+                           opt->block_size != sim->opt.block_size || opt->shared_update != sim->opt.shared_update))
         return fail(sim, TLED_E_STATE, "layout options must be set before tled_finalize");
     sim->opt = *opt;
     if (sim->opt.graph_steps == 0) sim->opt.graph_steps = !sim->is_batch ? 50 : (sim->opt.batch_schedule == 1 ? 100 : -1);
@@ -896,7 +971,7 @@ tled_status tled_critical_dt(tled_sim *sim, double *dt_cr) {
 tled_status tled_finalize(tled_sim *sim) {
     TRY(need_single_setup(sim));
     if (!sim->prob.have_time) return fail(sim, TLED_E_STATE, "call tled_set_time first");
-    int v = sim->opt.kernel_variant == 0 ? 2 : sim->opt.kernel_variant;
+    int v = sim->opt.kernel_variant == 0 ? default_variant(sim->prob.npe) : sim->opt.kernel_variant;
     SetupOptions so;
     so.reorder = sim->opt.reorder >= 0;
     so.bisect = sim->opt.reorder != 2;
@@ -922,7 +997,9 @@ tled_status tled_finalize(tled_sim *sim) {
         PatchArgs probe{};
         probe.max_nodes = sim->pc.patches.max_nodes;
         probe.max_elems = sim->pc.patches.max_elems;
-        if (patch_lds_bytes(sim->prob.npe, v == 2, probe) > 65536 - 1024)
+        size_t lim = 0;
+        TRY(patch_lds_limit(sim, &lim));
+        if (patch_lds_bytes(sim->prob.npe, v == 2, probe) > lim)
             return fail(sim, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
     }
     single_scenario(sim);
@@ -1074,11 +1151,13 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out) {
             probe.max_nodes = sim->pc.patches.max_nodes;
             probe.max_elems = sim->pc.patches.max_elems;
             out->patch_lds_bytes = int32_t(patch_lds_bytes(sim->prob.npe, sim->variant == 2, probe));
+            const bool fs = fused_shared_nodes(sim);
             if (sim->device >= 0) {
                 const int bs = sim->opt.block_size > 0 ? sim->opt.block_size : kBlock;
                 out->patch_wgs_per_cu =
-                    patch_occupancy(sim->prob.npe, sim->np, sim->variant == 2, bs, sim->is_batch, probe);
+                    patch_occupancy(sim->prob.npe, sim->np, sim->variant == 2, bs, sim->is_batch, probe, fs);
             }
+            if (out->n_shared_nodes > 0) out->shared_update = fs ? 1 : 2;
         }
         out->device_bytes = sim->device_bytes;
         out->dt_critical = sim->pc.dt_cr;
@@ -1326,7 +1405,7 @@ tled_status tled_batch_finalize(tled_batch *b) {
     TRY(need_setup(b));
     if (!b->is_batch) return fail(b, TLED_E_STATE, "not a batch handle");
     if (b->scen.empty()) return fail(b, TLED_E_STATE, "no scenario added");
-    const int v = b->opt.kernel_variant == 0 ? 2 : b->opt.kernel_variant;
+    const int v = b->opt.kernel_variant == 0 ? default_variant(b->scen[0].npe) : b->opt.kernel_variant;
     if (v == 1) return fail(b, TLED_E_UNSUPPORTED, "batches run on the fused kernels (variant 2 or 3)");
     if (b->opt.block_size == 512)
         return fail(b, TLED_E_UNSUPPORTED, "batches run with 256-thread workgroups (block_size 0 or 256)");
@@ -1365,7 +1444,9 @@ tled_status tled_batch_finalize(tled_batch *b) {
     PatchArgs probe{};
     probe.max_nodes = b->pc.patches.max_nodes;
     probe.max_elems = b->pc.patches.slot_stride;
-    if (patch_lds_bytes(b->scen[0].npe, v == 2, probe) > 65536 - 1024)
+    size_t lim = 0;
+    TRY(patch_lds_limit(b, &lim));
+    if (patch_lds_bytes(b->scen[0].npe, v == 2, probe) > lim)
         return fail(b, TLED_E_ARG, "patch too large for LDS; lower patch_elems");
     {
         const size_t S = b->scen.size();
@@ -1386,7 +1467,7 @@ tled_status tled_batch_finalize(tled_batch *b) {
     }
     b->queue = b->opt.batch_schedule == 1;
     if (b->queue && (b->pos_end.empty() || v != 2 && v != 3))
-        return fail(b, TLED_E_STATE, "the work-queue schedule needs the fused kernels and end-step ordered scenarios");
+        return fail(b, TLED_E_STATE, "the persistent schedule needs the fused kernels and end-step ordered scenarios");
     b->variant = v;
     b->prob = b->scen[0];
     b->prob.nn = b->pc.nn;

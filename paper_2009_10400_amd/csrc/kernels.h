@@ -73,6 +73,16 @@ struct PatchArgs {
     const float *Vl;
     float *theta;
     float4 *partial;
+    // Shared nodes updated inside the next step's patch kernel (single problems):
+    // per shared entry (a patch's copy of a shared node) the range [x, y) of the
+    // node's partials; the shared-node state the step starts from and the buffer
+    // the first patch of each node writes the update to (n_shared each; the
+    // shared-node kernel reads su_in, sv_in and writes nu4, nv4); the partials of
+    // the previous step.
+    const int2 *srange;
+    const float4 *su_in, *sv_in;
+    float4 *su_out, *sv_out;
+    const float4 *partial_prev;
     const long long *step_base;
     unsigned *status;
     double *part_elem, *part_node;
@@ -82,10 +92,10 @@ struct PatchArgs {
     const int *patch_scen;      // per patch
     const int *shared_scen;     // per shared node
     const long long *scen_end;  // per scenario: steps to run (the scenario holds afterwards)
-    // work-queue schedule of a batch: per-XCD patch counters (zero between
-    // steps) and the union positions in order of descending end step, with the
-    // patch and shared-node counts of the prefix that ends at each position
-    int *queue;                 // kNumXcd counters
+    // persistent schedule of a batch: the union positions in order of
+    // descending end step, with the patch and shared-node counts of the prefix
+    // that ends at each position, and the running counts of the current and
+    // next step
     long long *qcount;          // [parity of the step][patches, shared nodes] of the running scenarios
     const long long *pos_end;
     const int *pos_patch_hi;
@@ -103,15 +113,19 @@ void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat 
 void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s,
                  const LaunchTiming *ev = nullptr);
 // batch: per-scenario constants and end steps (256-thread workgroups only).
+// fused: the patch kernel first advances its shared nodes by the previous step
+// (single problems, geometry rebuilt from coordinates, 256 threads, no
+// anisotropy plane).
 void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
-                  hipStream_t s, const LaunchTiming *ev = nullptr);
+                  hipStream_t s, const LaunchTiming *ev = nullptr, bool fused = false);
 // Resident workgroups per CU of the patch kernel in this configuration (-1 on error).
-int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a);
+int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a, bool fused = false);
 void launch_shared_nodes(bool mon, bool batch, const PatchArgs &a, int j, hipStream_t s,
                          const LaunchTiming *ev = nullptr);
-// Work-queue schedule of a batch (256-thread workgroups): `grid` workgroups pull
-// the step's patches from the per-XCD counters; the shared-node kernel strides
-// over the step's shared nodes with a fixed grid and resets the counters.
+// Persistent schedule of a batch (256-thread workgroups): `grid` resident
+// workgroups walk the step's patches, each XCD's workgroups an eighth of them;
+// the shared-node kernel strides over the step's shared nodes with a fixed grid
+// and counts the next step's running patches and shared nodes.
 void launch_patch_queue(int npe, int np, bool mon, bool geox, const PatchArgs &a, int j, int grid, hipStream_t s,
                         const LaunchTiming *ev = nullptr);
 int patch_queue_occupancy(int npe, int np, bool geox, const PatchArgs &a);

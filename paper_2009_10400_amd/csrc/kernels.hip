@@ -471,6 +471,23 @@ __device__ __forceinline__ float source_switch(const NodeParams &p, const long l
     return (n >= p.n_on && n < p.n_off) ? 1.0f : 0.0f;
 }
 
+// Sum of a shared node's partials [k0, k1) in their stored order (groups of four
+// independent loads).  The shared-node kernels and the fused patch kernel both
+// use it, so a shared node's update has the same bits wherever it is computed.
+__device__ __forceinline__ float4 sum_node_partials(const float4 *partial, int k0, int k1) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = k0; k < k1; k += 4) {
+        float4 o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (k + q < k1) ? partial[k + q] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc.x += o[q].x; acc.y += o[q].y; acc.z += o[q].z; acc.w += o[q].w;
+        }
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------- two-pass kernels
 
 template <int NP, bool MON, bool ANISO>
@@ -594,9 +611,14 @@ __device__ __forceinline__ T uniform_load(const T *p) {
 }
 __device__ __forceinline__ int uniform_int(const int *p) { return __builtin_amdgcn_readfirstlane(*p); }
 
-// UNI: the patch index comes from a work queue (loads after earlier stores in
-// the same kernel), so its per-patch values are read with uniform_load.
-template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO, bool UNI = false>
+// UNI: several patches per workgroup (loads after earlier stores in the same
+// kernel), so the per-patch values are read with uniform_load.
+// FUSED (single problems): the shared nodes have not yet been advanced by the
+// previous step.  Every patch holding one sums its partials of that step and
+// advances it while staging (the shared-node kernel's arithmetic, so the same
+// bits); the patch that wrote the node's first partial stores the update, into
+// the other buffer of the pair the step reads its shared state from.
+template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO, bool UNI = false, bool FUSED = false>
 __device__ __forceinline__ void patch_work(const PatchArgs &A, const int pid, const int j, float4 *lds, double *shd,
                                            float *shf) {
     // BATCH: per-scenario constants and end steps; else the single problem's
@@ -631,7 +653,32 @@ __device__ __forceinline__ void patch_work(const PatchArgs &A, const int pid, co
     // are requested before their data, so the id -> data chain is paid once.
     // GEOX: the fourth float of a shared node's staged coordinate carries the
     // position of its partial (read in the node phase without a global load).
-    {
+    bool nf_stage = false;
+    if (FUSED) {
+        const float src_prev = source_switch(p, A.step_base, j - 1);
+        for (int l = threadIdx.x; l < nloc; l += BS) {
+            if (l < nint) {
+                lnode[l] = A.nu4[ib + l];
+                if (GEOX) lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2], 0.f);
+            } else {
+                const int q = sb + l - nint;
+                const int id = A.shared_ids[q], pp = A.ppos[q];
+                const int2 kr = A.srange[q];                       // independent of the id
+                const int sn = id - A.n_interior;
+                const float4 u0 = A.su_in[sn], v0 = A.sv_in[sn], th = A.nth[id];
+                const unsigned mk = A.mask[id];
+                const float4 acc = sum_node_partials(A.partial_prev, kr.x, kr.y);
+                const NodeNew r = node_advance(p, u0, v0, th, mk, acc, src_prev);
+                lnode[l] = r.u;
+                if (GEOX) lxyz[l] = make_float4(gx[3 * l], gx[3 * l + 1], gx[3 * l + 2], __int_as_float(pp));
+                if (pp == kr.x) {
+                    A.su_out[sn] = r.u;
+                    A.sv_out[sn] = r.v;
+                    nf_stage |= r.nonfinite;
+                }
+            }
+        }
+    } else {
         int nid[2];
 #pragma unroll
         for (int it = 0; it < 2; ++it) {
@@ -657,7 +704,7 @@ __device__ __forceinline__ void patch_work(const PatchArgs &A, const int pid, co
     }
     __syncthreads();
     float psi = 0.f;
-    bool nf = false, inv = false;
+    bool nf = nf_stage, inv = false;
     for (int e = e0 + threadIdx.x; e < e1; e += BS) {
         float th[6 * NP + 1];
         load_theta(A.theta, A.ne, e, NP, th);
@@ -754,12 +801,18 @@ __device__ __forceinline__ void patch_work(const PatchArgs &A, const int pid, co
 }
 
 // One workgroup per patch (a launch covers the first gridDim.x patches).
-template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO>
-__global__ __launch_bounds__(BS) void patch_kernel(PatchArgs A, int j) {
+// H8 with precomputed geometry: compiled for four waves per SIMD (at most 128
+// VGPRs, a few values spilled), which its LDS footprint allows; 3 waves per SIMD
+// at 144 VGPRs otherwise.  Rebuilding the geometry needs the staged coordinates
+// in LDS, which leave room for three workgroups per CU only.
+template <int NPE, int NP, bool MON, int BS, bool GEOX, bool BATCH, bool ANISO, bool FUSED = false>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(NPE == 8 && !GEOX ? 4 : 1)))
+void patch_kernel(PatchArgs A, int j) {
     extern __shared__ float4 lds[];
     __shared__ double shd[BS / 64];
     __shared__ float shf[BS / 64];
-    patch_work<NPE, NP, MON, BS, GEOX, BATCH, ANISO>(A, xcd_block(blockIdx.x, gridDim.x), j, lds, shd, shf);
+    patch_work<NPE, NP, MON, BS, GEOX, BATCH, ANISO, false, FUSED>(A, xcd_block(blockIdx.x, gridDim.x), j, lds, shd,
+                                                                  shf);
 }
 
 // Batch scenarios still running at `step`: the union positions run in order of
@@ -774,53 +827,30 @@ __device__ __forceinline__ int running_positions(const PatchArgs &A, long long s
     return lo;
 }
 
-// Work-queue form of the batch patch kernel: launched with the workgroups that
-// are resident at once, which pull patches until the step's patches run out
-// (all patches at a monitor step, where finished ones write neutral monitor
-// partials; else only those of the scenarios still running: their count for
-// the step was left by the previous step's shared-node kernel in the slot of
-// the step's parity, so one captured graph serves every step).  Workgroups
-// beyond that count leave at once.  XCD x draws from its own counter over the
-// x-th eighth of the patches (neighbouring patches share nodes, so they stay in
-// one L2), then helps the other eighths in turn, reading a counter before
-// incrementing it so that exhausted ones cost no atomic.  The counters are
-// reset to zero by the step's shared-node kernel, which runs after every
-// workgroup here has finished.  No workgroup waits for another.
+// Persistent form of the batch patch kernel: launched with the workgroups that
+// are resident at once, which walk the step's patches (all patches at a monitor
+// step, where finished ones write neutral monitor partials; else only those of
+// the scenarios still running: their count for the step was left by the
+// previous step's shared-node kernel in the slot of the step's parity, so one
+// captured graph serves every step).  The workgroups of XCD x (dispatch is
+// round-robin over the XCDs) take the x-th eighth of the patches in a strided
+// walk, so that neighbouring patches, which share nodes, stay in one L2.  The
+// assignment is static: pulling patches one by one from device-wide counters
+// measured 3.8 times slower (every pull is an atomic on one of a few
+// addresses, served in order at the coherence point of the XCDs).  No
+// workgroup waits for another.
 template <int NPE, int NP, bool MON, bool GEOX>
 __global__ __launch_bounds__(kBlock) void patch_queue_kernel(PatchArgs A, int j) {
     extern __shared__ float4 lds[];
     __shared__ double shd[kBlock / 64];
     __shared__ float shf[kBlock / 64];
-    __shared__ int s_item;
     const long long step = *A.step_base + j;
     const int n = MON ? A.n_patches : int(A.qcount[2 * (step & 1)]);
-    if (int(blockIdx.x) >= n) return;
-    int x = int(blockIdx.x % kNumXcd), tries = 0;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            int it = -1;
-            while (tries < kNumXcd) {
-                const int lo = int((long long)n * x / kNumXcd), hi = int((long long)n * (x + 1) / kNumXcd);
-                if (lo + __hip_atomic_load(&A.queue[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < hi) {
-                    const int c = lo + atomicAdd(&A.queue[x], 1);
-                    if (c < hi) {
-                        it = c;
-                        break;
-                    }
-                }
-                ++tries;                     // this eighth is done: help the next one
-                x = (x + 1) % kNumXcd;
-            }
-            s_item = it;
-        }
-        __syncthreads();
-        // the item is the same for the whole workgroup: kept in a scalar register, so that
-        // everything derived from it (ranges, scenario constants) stays scalar as in patch_kernel
-        const int pid = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();                     // every thread has read the item before it is replaced
-        if (pid < 0) break;
+    const int G = int(gridDim.x), x = int(blockIdx.x) % kNumXcd, i = int(blockIdx.x) / kNumXcd;
+    const int gx = G / kNumXcd + (x < G % kNumXcd ? 1 : 0);          // workgroups on XCD x
+    const int lo = int((long long)n * x / kNumXcd), hi = int((long long)n * (x + 1) / kNumXcd);
+    for (int pid = lo + i; pid < hi; pid += gx)
         patch_work<NPE, NP, MON, kBlock, GEOX, true, false, true>(A, pid, j, lds, shd, shf);
-    }
 }
 
 template <bool MON, bool BATCH>
@@ -837,20 +867,9 @@ __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j)
         const NodeParams p = A.np[sc];
         const float src = (step >= p.n_on && step < p.n_off) ? 1.0f : 0.0f;
         const int a = A.n_interior + s;
-        const float4 u0 = A.nu4[a], v0 = A.nv4[a], th = A.nth[a];   // independent of the partials
+        const float4 u0 = A.su_in[s], v0 = A.sv_in[s], th = A.nth[a];   // independent of the partials
         const unsigned mk = A.mask[a];
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int k0 = A.srow[s], k1 = A.srow[s + 1];
-        // partials in groups of four independent loads (fixed order within and across groups)
-        for (int k = k0; k < k1; k += 4) {
-            float4 o[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = (k + q < k1) ? A.partial[k + q] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc.x += o[q].x; acc.y += o[q].y; acc.z += o[q].z; acc.w += o[q].w;
-            }
-        }
+        const float4 acc = sum_node_partials(A.partial, A.srow[s], A.srow[s + 1]);
         NodeNew r = node_advance(p, u0, v0, th, mk, acc, src);
         A.nu4[a] = r.u;
         A.nv4[a] = r.v;
@@ -861,10 +880,10 @@ __global__ __launch_bounds__(kBlock) void shared_node_kernel(PatchArgs A, int j)
     if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), blk, shd, shf);
 }
 
-// Shared-node kernel of the work-queue schedule: a fixed grid strides over the
+// Shared-node kernel of the persistent schedule: a fixed grid strides over the
 // shared nodes of the scenarios still running (all of them at a monitor step),
-// counted on the device; block 0 then resets the patch queue counters for the
-// next step.
+// counted on the device; block 0 also counts the next step's running patches
+// and shared nodes.
 template <bool MON>
 __global__ __launch_bounds__(kBlock) void shared_node_queue_kernel(PatchArgs A, int j) {
     __shared__ double shd[kBlock / 64];
@@ -889,17 +908,7 @@ __global__ __launch_bounds__(kBlock) void shared_node_queue_kernel(PatchArgs A, 
         const int64_t a = A.n_interior + s;
         const float4 u0 = A.nu4[a], v0 = A.nv4[a], th = A.nth[a];
         const unsigned mk = A.mask[a];
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int k0 = A.srow[s], k1 = A.srow[s + 1];
-        for (int k = k0; k < k1; k += 4) {
-            float4 o[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) o[q] = (k + q < k1) ? A.partial[k + q] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc.x += o[q].x; acc.y += o[q].y; acc.z += o[q].z; acc.w += o[q].w;
-            }
-        }
+        const float4 acc = sum_node_partials(A.partial, A.srow[s], A.srow[s + 1]);
         NodeNew r = node_advance(p, u0, v0, th, mk, acc, src);
         A.nu4[a] = r.u;
         A.nv4[a] = r.v;
@@ -908,7 +917,6 @@ __global__ __launch_bounds__(kBlock) void shared_node_queue_kernel(PatchArgs A, 
     }
     raise_flags(A.status, nf, false);
     if (MON) write_node_partials<kBlock>(mo, A.part_node + 4 * size_t(A.n_patches), int(blockIdx.x), shd, shf);
-    if (blockIdx.x == 0 && threadIdx.x < kNumXcd) A.queue[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------- monitors
@@ -923,7 +931,10 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const double *__restrict
     __shared__ float shf[kBlock / 64];
     double se = 0.0, ke = 0.0, abl = 0.0;
     float tmax = -INFINITY, tmin = INFINITY;
+    // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 4
     for (int i = threadIdx.x; i < n_elem_parts; i += kBlock) se += part_elem[i];
+#pragma unroll 4
     for (int i = threadIdx.x; i < n_node_parts; i += kBlock) {
         ke += part_node[4 * i];
         tmax = fmaxf(tmax, float(part_node[4 * i + 1]));
@@ -986,36 +997,44 @@ void launch_h8_element(bool mon, const TwoPassArgs &a, const KMat &m, hipStream_
 
 // occ != nullptr: report the resident workgroups per CU of the instantiation
 // instead of launching it.
-template <int NPE, int NP, int BS, bool GEOX, bool BATCH, bool ANISO = false>
+template <int NPE, int NP, int BS, bool GEOX, bool BATCH, bool ANISO = false, bool FUSED = false>
 void launch_patch_g(bool mon, const PatchArgs &a, int j, size_t lds, hipStream_t s, int *occ,
                     const LaunchTiming *ev) {
     if (occ) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO>), BS,
-                lds) != hipSuccess)
+                occ, reinterpret_cast<const void *>(&patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO, FUSED>),
+                BS, lds) != hipSuccess)
             *occ = -1;
         return;
     }
     dim3 grid(a.n_patches);
-    if (mon) TLED_LAUNCH(ev, (patch_kernel<NPE, NP, true, BS, GEOX, BATCH, ANISO>), grid, dim3(BS), lds, s, a, j);
-    else TLED_LAUNCH(ev, (patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO>), grid, dim3(BS), lds, s, a, j);
+    if (mon)
+        TLED_LAUNCH(ev, (patch_kernel<NPE, NP, true, BS, GEOX, BATCH, ANISO, FUSED>), grid, dim3(BS), lds, s, a, j);
+    else
+        TLED_LAUNCH(ev, (patch_kernel<NPE, NP, false, BS, GEOX, BATCH, ANISO, FUSED>), grid, dim3(BS), lds, s, a, j);
 }
 
 // Batches run with 256-thread workgroups only; so do single problems with the
 // orthotropic expansion or the tensor conduction (the anisotropy plane is
-// present exactly then).
+// present exactly then).  The fused form exists for single problems with the
+// geometry rebuilt from coordinates, 256 threads and no anisotropy plane (the
+// library enables it only then).
 template <int NPE, int NP>
 void launch_patch_np(bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j, size_t lds,
-                     hipStream_t s, int *occ, const LaunchTiming *ev) {
-    if (a.aniso && !batch) {
+                     hipStream_t s, int *occ, const LaunchTiming *ev, bool fused) {
+    if (fused) {
+        launch_patch_g<NPE, NP, 256, true, false, false, true>(mon, a, j, lds, s, occ, ev);
+    } else if (a.aniso && !batch) {
         if (geox) launch_patch_g<NPE, NP, 256, true, false, true>(mon, a, j, lds, s, occ, ev);
         else launch_patch_g<NPE, NP, 256, false, false, true>(mon, a, j, lds, s, occ, ev);
     } else if (batch) {
         if (geox) launch_patch_g<NPE, NP, 256, true, true>(mon, a, j, lds, s, occ, ev);
         else launch_patch_g<NPE, NP, 256, false, true>(mon, a, j, lds, s, occ, ev);
     } else if (NPE == 4 && bs == 512) {
-        if (geox) launch_patch_g<NPE, NP, 512, true, false>(mon, a, j, lds, s, occ, ev);
-        else launch_patch_g<NPE, NP, 512, false, false>(mon, a, j, lds, s, occ, ev);
+        if constexpr (NPE == 4) {   // 512-thread workgroups exist for T4 only
+            if (geox) launch_patch_g<NPE, NP, 512, true, false>(mon, a, j, lds, s, occ, ev);
+            else launch_patch_g<NPE, NP, 512, false, false>(mon, a, j, lds, s, occ, ev);
+        }
     } else {
         if (geox) launch_patch_g<NPE, NP, 256, true, false>(mon, a, j, lds, s, occ, ev);
         else launch_patch_g<NPE, NP, 256, false, false>(mon, a, j, lds, s, occ, ev);
@@ -1057,31 +1076,31 @@ void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hip
 
 namespace {
 void patch_dispatch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
-                    hipStream_t s, int *occ, const LaunchTiming *ev) {
+                    hipStream_t s, int *occ, const LaunchTiming *ev, bool fused) {
     const size_t lds = patch_lds_bytes(npe, geox, a);
     if (npe == 4) {
         switch (np) {
-            case 0: launch_patch_np<4, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 1: launch_patch_np<4, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 2: launch_patch_np<4, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 3: launch_patch_np<4, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            default: launch_patch_np<4, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 0: launch_patch_np<4, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 1: launch_patch_np<4, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 2: launch_patch_np<4, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 3: launch_patch_np<4, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            default: launch_patch_np<4, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
         }
     } else {
         switch (np) {
-            case 0: launch_patch_np<8, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 1: launch_patch_np<8, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 2: launch_patch_np<8, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            case 3: launch_patch_np<8, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
-            default: launch_patch_np<8, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev); break;
+            case 0: launch_patch_np<8, 0>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 1: launch_patch_np<8, 1>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 2: launch_patch_np<8, 2>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            case 3: launch_patch_np<8, 3>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
+            default: launch_patch_np<8, 4>(mon, geox, bs, batch, a, j, lds, s, occ, ev, fused); break;
         }
     }
 }
 }  // namespace
 
 void launch_patch(int npe, int np, bool mon, bool geox, int bs, bool batch, const PatchArgs &a, int j,
-                  hipStream_t s, const LaunchTiming *ev) {
-    patch_dispatch(npe, np, mon, geox, bs, batch, a, j, s, nullptr, ev);
+                  hipStream_t s, const LaunchTiming *ev, bool fused) {
+    patch_dispatch(npe, np, mon, geox, bs, batch, a, j, s, nullptr, ev, fused);
 }
 
 namespace {
@@ -1136,9 +1155,9 @@ void launch_shared_nodes_queue(bool mon, const PatchArgs &a, int j, int grid, hi
     else TLED_LAUNCH(ev, (shared_node_queue_kernel<false>), dim3(grid), dim3(kBlock), 0, s, a, j);
 }
 
-int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a) {
+int patch_occupancy(int npe, int np, bool geox, int bs, bool batch, const PatchArgs &a, bool fused) {
     int occ = 0;
-    patch_dispatch(npe, np, false, geox, bs, batch, a, 0, nullptr, &occ, nullptr);
+    patch_dispatch(npe, np, false, geox, bs, batch, a, 0, nullptr, &occ, nullptr, fused);
     return occ;
 }
 

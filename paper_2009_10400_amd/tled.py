@@ -66,7 +66,7 @@ class Material(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("graph_steps", _i32), ("kernel_variant", _i32), ("reorder", _i32),
                 ("block_size", _i32), ("patch_elems", _i32), ("ablation_T", _d),
-                ("batch_schedule", _i32), ("reserved", _i32)]
+                ("batch_schedule", _i32), ("shared_update", _i32)]
 
 
 class Monitors(ctypes.Structure):
@@ -92,7 +92,7 @@ class Info(ctypes.Structure):
                 ("n_swapped", _i64), ("kernel_variant", _i32), ("n_patches", _i32),
                 ("n_shared_nodes", _i64), ("patch_max_nodes", _i32), ("patch_lds_bytes", _i32),
                 ("device_bytes", _i64), ("dt", _d), ("dt_critical", _d), ("patch_wgs_per_cu", _i32),
-                ("reserved", _i32), ("dt_thermal", _d)]
+                ("shared_update", _i32), ("dt_thermal", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -28,8 +28,8 @@ def critical_dt(problem):
 @pytest.mark.parametrize("graph_steps,schedule", [(40, 0), (-1, 0), (40, 1), (-1, 1), (7, 1)])
 def test_batch_equals_single_runs_bitwise_and_holds(graph_steps, schedule):
     # scenarios end at different steps, most of them inside a chunk: a step launches only the
-    # scenarios still running (graph chunks: those running at the chunk's first step); the work
-    # queue (schedule 1) counts them on the device and the resident workgroups pull their patches
+    # scenarios still running (graph chunks: those running at the chunk's first step); the
+    # persistent schedule (1) counts them on the device and the resident workgroups walk their patches
     from paper_2009_10400_amd import tled
     sc, steps = small_batch()
     b = tled.Batch(0)
@@ -127,15 +127,16 @@ def test_batch_fields_independent_of_host_threads_and_duration_api(monkeypatch):
         assert np.array_equal(u1, u) and np.array_equal(T1, T)
 
 
-def test_h8_batch_equals_single_runs_bitwise():
+@pytest.mark.parametrize("variant", [2, 3])
+def test_h8_batch_equals_single_runs_bitwise(variant):
     """H8 scenarios of different sizes and materials in one batch: each equal bit for bit to its own
-    run with the same patch size, and held after its step count."""
+    run with the same patch size and kernel variant, and held after its step count."""
     from paper_2009_10400_amd import tled
     probs = [W.cube_h8(n=n, L=0.02 * n / 6, power=p) for n, p in ((6, 2.0), (9, 5.0), (7, 3.0))]
     probs[1].params = dict(probs[1].params, mu=1500.0, eta=3000.0)
     steps = [120, 200, 60]
     b = tled.Batch(0)
-    b.set_options(graph_steps=40)
+    b.set_options(graph_steps=40, kernel_variant=variant)
     for p, n in zip(probs, steps):
         b.add(p, cfl=0.8, t_end=1e9, patch_elems=128)
     b.finalize()
@@ -143,14 +144,14 @@ def test_h8_batch_equals_single_runs_bitwise():
     # explicit step counts: rebuild with the chosen dt
     b.close()
     b = tled.Batch(0)
-    b.set_options(graph_steps=40)
+    b.set_options(graph_steps=40, kernel_variant=variant)
     for p, dt, n in zip(probs, dts, steps):
         b.add(p, dt, n, patch_elems=128)
     b.finalize()
     b.run()
     fields = b.read_all()
     for k, (p, dt, n) in enumerate(zip(probs, dts, steps)):
-        s = tled.from_problem(p, dt=dt, device=0, kernel_variant=2, graph_steps=40, patch_elems=128)
+        s = tled.from_problem(p, dt=dt, device=0, kernel_variant=variant, graph_steps=40, patch_elems=128)
         s.step(n)
         assert np.array_equal(fields[k][0], s.read_u()), k
         assert np.array_equal(fields[k][1], s.read_T()), k

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 def _run(p, segments):
     """Steps the segments in order; returns the fields and the monitors after each segment."""
-    sim = gpu_sim(p, kernel_variant=2)
+    sim = gpu_sim(p)                     # the library's default kernel variant
     mons = []
     for n in segments:
         sim.step(n)
@@ -34,7 +34,7 @@ def _heat_bounds(sim, p, T, t_heat):
 
 def test_cube_h8_64_heating_and_cooling_90s():
     p = W.cube_h8(n=64)                  # 10 W point source on for 60 s
-    sim0 = gpu_sim(p, kernel_variant=2)
+    sim0 = gpu_sim(p)
     dt = sim0.dt
     sim0.close()
     n_heat = int(round(60.0 / dt))
