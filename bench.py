@@ -618,6 +618,21 @@ def main():
     value = p.ne / (ms_per_step * 1e-3)
     log(f"[bench] {len(reps)} timed regions of {args.steps} steps (ms/step): {[round(r, 5) for r in reps]}, "
         f"median {ms_per_step:.5f} -> {value:.4g} element-updates/s")
+    # context for short regions: every timed region, whatever its length, carries a fixed cost
+    # of tens of microseconds on the GPU (its own HIP events show it), which K = 20 spreads over
+    # few steps; one more region of at least 2000 steps gives the per-step time it approaches
+    steady = None
+    if args.steps < 2000:
+        n_long = 2000
+        sim.prepare(n_long)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.step(n_long)
+        torch.cuda.synchronize()
+        ms_long = 1e3 * (time.perf_counter() - t1) / n_long
+        steady = {"steps": n_long, "ms_per_step": ms_long, "value": p.ne / (ms_long * 1e-3),
+                  "note": "one further timed region of this many steps, same bracketing; context only"}
+        log(f"[bench] one region of {n_long} steps: {ms_long:.5f} ms/step")
 
     # dominant kernel, timed with HIP events on the library's stream
     kt = sim.kernel_times(args.kernel_steps)
@@ -695,6 +710,7 @@ def main():
         "step_hbm": step_hbm,
         "repeats": {"ms_per_step": reps, "median_ms_per_step": ms_per_step,
                     "note": "value and ms_per_step are the median of these timed regions of K steps each"},
+        "long_region": steady,
     }
     if not args.no_cpu_baseline and p.npe == 4:
         steps = args.cpu_steps or max(3, int(100e6 / p.ne))

@@ -133,15 +133,15 @@ typedef struct {
                                  100) serves the whole batch                                             */
     int32_t shared_update;    /* set before finalize.  How the nodes shared between patches are
                                  advanced (Eqs. 20 and 27 on their summed patch partials):
-                                 0: default (1 where available, else 2); 1: inside the next
-                                 step's patch kernel: every patch holding a shared node sums its
-                                 partials and advances it while staging, the patch that wrote
-                                 its first partial stores it, and one shared-node kernel ends
-                                 each chunk (single problems with kernel_variant 2, 256-thread
-                                 workgroups and neither the orthotropic expansion nor the
-                                 tensor conduction; elsewhere as 2); 2: a shared-node kernel
-                                 after every step's patch kernel.  The fields are the same
-                                 bits either way                                              */
+                                 0: default (= 2); 1: inside the next step's patch kernel:
+                                 every patch holding a shared node sums its partials and
+                                 advances it while staging, the patch that wrote its first
+                                 partial stores it, and one shared-node kernel ends each chunk
+                                 (single problems with kernel_variant 2, 256-thread workgroups
+                                 and neither the orthotropic expansion nor the tensor
+                                 conduction; elsewhere as 2); 2: a shared-node kernel after
+                                 every step's patch kernel.  The fields are the same bits
+                                 either way                                                   */
 } tled_options;
 
 typedef struct {

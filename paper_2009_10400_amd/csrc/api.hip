@@ -127,12 +127,14 @@ int default_patch_elems(int npe, int64_t ne, int block_size) {
 int default_variant(int npe) { return npe == 8 ? 3 : 2; }
 
 // Whether the shared nodes of a finalized handle are advanced inside the next
-// step's patch kernel: single problems with kernel variant 2, 256-thread
-// workgroups, no anisotropy plane and some shared node, unless shared_update = 2.
+// step's patch kernel: asked for (shared_update = 1), single problems with kernel
+// variant 2, 256-thread workgroups, no anisotropy plane and some shared node.
+// Not the default: on the 1M-tet ellipsoid it saved under 1 % of a step in long
+// runs and measured slower in runs of 20 steps.
 bool fused_shared_nodes(const tled_sim *s) {
     const tled_material &m = s->prob.mat;
     return !s->is_batch && s->variant == 2 && (s->opt.block_size == 0 || s->opt.block_size == kBlock) &&
-           m.expan_mode != 2 && m.cond_mode != 2 && s->opt.shared_update != 2 &&
+           m.expan_mode != 2 && m.cond_mode != 2 && s->opt.shared_update == 1 &&
            s->pc.nn > s->pc.patches.n_interior;
 }
 

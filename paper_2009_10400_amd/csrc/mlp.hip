@@ -211,7 +211,8 @@ __global__ void splitk_reduce_kernel(int nz, int M, int N, const float *__restri
     const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= long(M) * N) return;
     float s = 0.f;
-    for (int z = 0; z < nz; ++z) s += part[size_t(z) * M * N + i];
+#pragma unroll 8
+    for (int z = 0; z < nz; ++z) s += part[size_t(z) * M * N + i];   // loads in flight, additions in order
     const long m = i / N, n = i % N;
     C[m * scm + n * scn] = s;
 }
@@ -278,7 +279,8 @@ __global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict_
     if (j >= N) return;
     float s = 0.f;
     const long r1 = std::min(M, r0 + chunk);
-    for (long r = r0; r < r1; ++r) s += bf2f(X[r * N + j]);
+#pragma unroll 8
+    for (long r = r0; r < r1; ++r) s += bf2f(X[r * N + j]);        // loads in flight, additions in order
     part[size_t(blockIdx.y) * N + j] = s;
 }
 
@@ -290,8 +292,10 @@ __global__ __launch_bounds__(kThreads) void colsum_final_kernel(int nchunks, int
     __shared__ float sh[4][64];
     const int c = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
     float a = 0.f;
-    if (c < N)
+    if (c < N) {
+#pragma unroll 8
         for (int ch = q; ch < nchunks; ch += 4) a += part[size_t(ch) * N + c];
+    }
     sh[q][threadIdx.x & 63] = a;
     __syncthreads();
     if (q == 0 && c < N) {

@@ -446,26 +446,28 @@ def test_anisotropic_setup_errors_and_thermal_bound():
 
 
 def test_shared_update_option():
-    """Where the shared nodes are advanced: inside the next step's patch kernel for single
-    problems with kernel variant 2, 256 threads and no anisotropy plane; a kernel of their own
-    elsewhere or when asked; nothing to report without patches.  Set before finalize only."""
+    """Where the shared nodes are advanced: by a kernel of their own unless asked otherwise;
+    inside the next step's patch kernel when asked, for single problems with kernel variant 2,
+    256 threads and no anisotropy plane; nothing to report without patches.  Set before
+    finalize only."""
     from paper_2009_10400_amd import tled
     t4, h8 = W.cube_t4(), W.cube_h8(n=8)
-    assert host_sim(t4).info()["shared_update"] == 1
-    assert host_sim(h8).info()["shared_update"] == 2                     # H8 default: variant 3
-    assert host_sim(h8, kernel_variant=2).info()["shared_update"] == 1
+    assert host_sim(t4).info()["shared_update"] == 2                     # default: a kernel of their own
+    assert host_sim(h8).info()["shared_update"] == 2
+    assert host_sim(h8, shared_update=1).info()["shared_update"] == 2    # H8 default: variant 3
+    assert host_sim(h8, kernel_variant=2, shared_update=1).info()["shared_update"] == 1
     assert host_sim(t4, shared_update=1).info()["shared_update"] == 1
     assert host_sim(t4, shared_update=2).info()["shared_update"] == 2
-    assert host_sim(t4, kernel_variant=3).info()["shared_update"] == 2
-    assert host_sim(t4, block_size=512).info()["shared_update"] == 2
+    assert host_sim(t4, kernel_variant=3, shared_update=1).info()["shared_update"] == 2
+    assert host_sim(t4, block_size=512, shared_update=1).info()["shared_update"] == 2
     assert host_sim(t4, kernel_variant=1).info()["shared_update"] == 0
     ortho = W.cube_t4()
     ortho.params = dict(ortho.params, cond_mode=2)
     ortho.D = np.tile(np.array([0.5, 0.6, 0.7, 0.0, 0.0, 0.0]), (ortho.ne, 1))
-    assert host_sim(ortho).info()["shared_update"] == 2
+    assert host_sim(ortho, shared_update=1).info()["shared_update"] == 2
     s = host_sim(t4)
     with pytest.raises(tled.TledError) as e:
-        s.set_options(shared_update=2)
+        s.set_options(shared_update=1)
     assert e.value.status == tled.E_STATE
     with pytest.raises(tled.TledError) as e:
         host_sim(t4, shared_update=3)
