@@ -282,6 +282,26 @@ tled_status tled_get_info(tled_sim *sim, tled_info *out);
 tled_status tled_get_lumped(tled_sim *sim, double *Vl, double *M, double *C, double *Kb,
                             double *Qm, double *Qr);
 
+/* --- thermal dose ---------------------------------------------------------
+ * Section 7 names thermal-damage models as the clinical measures of an
+ * ablation besides an isotherm (the 60 C ablated-volume monitor above).  With
+ * tled_set_thermal_dose (single problems, before tled_finalize) every step adds,
+ * per node and at the temperature T the step ends at (K; T_C = T - 273.15):
+ *   CEM43 (Sapareto and Dewey), equivalent minutes at 43 C:
+ *     (dt / 60) R^(43 - T_C), R = 0.5 for T_C >= 43 and 0.25 below;
+ *   the Arrhenius damage integral (Henriques and Moritz):
+ *     dt A exp(-Ea / (R_gas T)), R_gas = 8.314462618 J/(mol K),
+ * with the caller's frequency factor A (1/s; 0 leaves the integral at zero)
+ * and activation energy Ea (J/mol).  Both sums are held in FP64 on the device
+ * and updated by a kernel of their own after each step (the shared nodes are
+ * then advanced by their own kernel every step, whatever shared_update asks);
+ * they are part of the opaque state.  TLED_E_UNSUPPORTED on batch handles,
+ * TLED_E_ARG for negative or non-finite parameters.
+ * tled_read_thermal_dose: both sums in caller numbering, n_nodes each (either
+ * pointer may be NULL); TLED_E_STATE when the dose was not enabled. */
+tled_status tled_set_thermal_dose(tled_sim *sim, double arrhenius_A, double arrhenius_Ea);
+tled_status tled_read_thermal_dose(tled_sim *sim, double *cem43_min, double *omega);
+
 /* --- state --------------------------------------------------------------
  * Typed state in caller numbering: u n_nodes x 3 (m), v n_nodes x 3 velocity
  * at the last half step (m/s), T n_nodes (K), theta n_elems x n_prony x 6

@@ -106,6 +106,8 @@ def _load(path: str):
     L.orc_element.argtypes = [ctypes.POINTER(Material), ctypes.c_int32, dp, dp, dp, dp, dp, dp, dp,
                               ctypes.c_double, dp, dp, dp]
     L.orc_element.restype = ctypes.c_int
+    L.orc_thermal_dose.argtypes = [ctypes.c_int64, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
+    L.orc_thermal_dose.restype = None
     return L
 
 
@@ -264,9 +266,31 @@ class OracleSim:
         state["step"] = int(state["step"]) + int(nsteps)
         return mon
 
+    def run_with_dose(self, state: dict, nsteps: int, A: float, Ea: float):
+        """Advance ``state`` by ``nsteps`` one step at a time and add each step's thermal dose at
+        the temperatures it ends at to ``state["cem43"]`` and ``state["omega"]`` (created as
+        zeros when absent); see ``thermal_dose``."""
+        for k in ("cem43", "omega"):
+            if k not in state:
+                state[k] = np.zeros(self.nn)
+        for _ in range(int(nsteps)):
+            self.run(state, 1)
+            thermal_dose(state["T"], self.dt, A, Ea, state["cem43"], state["omega"])
+
     def loads(self, u, T):
         """Internal forces (nn x 3) and conduction loads (nn) for a state, without a Prony update."""
         F = np.zeros((self.nn, 3))
         H = np.zeros(self.nn)
         self._L.orc_loads(self._h, _dp(_f64(u)), _dp(_f64(T)), _dp(F), _dp(H))
         return F, H
+
+
+def thermal_dose(T, dt: float, A: float, Ea: float, cem43, omega):
+    """One time step's thermal dose at nodal temperatures T (kelvin), added in place: CEM43
+    (Sapareto and Dewey) += (dt/60) R^(43 - T_C), R = 0.5 at T_C >= 43 C and 0.25 below;
+    Arrhenius damage (Henriques and Moritz) += dt A exp(-Ea / (R_gas T)) (nothing when A <= 0)."""
+    L = lib()
+    T = _f64(T)
+    assert cem43.dtype == np.float64 and omega.dtype == np.float64
+    assert cem43.flags.c_contiguous and omega.flags.c_contiguous
+    L.orc_thermal_dose(int(T.size), _dp(T), float(dt), float(A), float(Ea), _dp(cem43), _dp(omega))

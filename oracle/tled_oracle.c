@@ -777,3 +777,25 @@ int orc_run(const orc_sim *s, int64_t nsteps, int64_t step0, double *u, double *
     free(Fint); free(Hc); free(un); free(Tn);
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Thermal dose.  Section 7 names thermal-damage models as the clinical    */
+/* measures of an ablation besides an isotherm; their published             */
+/* definitions, one time step's contribution at the temperature the step   */
+/* ends at (a rectangle rule in time):                                     */
+/*   CEM43 (Sapareto and Dewey), cumulative equivalent minutes at 43 C:    */
+/*     (dt / 60) R^(43 - T_C), R = 0.5 for T_C >= 43 C, 0.25 below;         */
+/*   Arrhenius damage integral (Henriques and Moritz):                     */
+/*     dt A exp(-Ea / (R_gas T)), T in kelvin, R_gas = 8.314462618 J/(mol K); */
+/*     nothing is added when A <= 0.                                       */
+/* ---------------------------------------------------------------------- */
+void orc_thermal_dose(int64_t nn, const double *T, double dt, double A, double Ea, double *cem43, double *omega)
+{
+    const double R_gas = 8.314462618;
+    for (int64_t a = 0; a < nn; ++a) {
+        double Tc = T[a] - 273.15;
+        double R = Tc >= 43.0 ? 0.5 : 0.25;
+        cem43[a] += dt / 60.0 * pow(R, 43.0 - Tc);
+        if (A > 0.0) omega[a] += dt * A * exp(-Ea / (R_gas * T[a]));
+    }
+}

@@ -95,6 +95,11 @@ struct tled_sim {
     // are pa.partial and the shared tail of nu4, nv4)
     bool fuse = false;
     float4 *d_part2 = nullptr, *d_sux = nullptr, *d_svx = nullptr;
+    // thermal dose (tled_set_thermal_dose): per node (CEM43 minutes, Arrhenius integral)
+    bool dose_on = false;
+    double dose_A = 0.0, dose_Ea = 0.0;
+    double2 *d_dose = nullptr;
+    DoseParams dq{};
 };
 
 namespace {
@@ -128,13 +133,14 @@ int default_variant(int npe) { return npe == 8 ? 3 : 2; }
 
 // Whether the shared nodes of a finalized handle are advanced inside the next
 // step's patch kernel: asked for (shared_update = 1), single problems with kernel
-// variant 2, 256-thread workgroups, no anisotropy plane and some shared node.
+// variant 2, 256-thread workgroups, no anisotropy plane, no thermal dose (its
+// kernel reads every node's temperature after each step) and some shared node.
 // Not the default: on the 1M-tet ellipsoid it saved under 1 % of a step in long
 // runs and measured slower in runs of 20 steps.
 bool fused_shared_nodes(const tled_sim *s) {
     const tled_material &m = s->prob.mat;
     return !s->is_batch && s->variant == 2 && (s->opt.block_size == 0 || s->opt.block_size == kBlock) &&
-           m.expan_mode != 2 && m.cond_mode != 2 && s->opt.shared_update == 1 &&
+           m.expan_mode != 2 && m.cond_mode != 2 && s->opt.shared_update == 1 && !s->dose_on &&
            s->pc.nn > s->pc.patches.n_interior;
 }
 
@@ -399,6 +405,17 @@ tled_status upload_all(tled_sim *s) {
     t.nu4 = dnu4; t.nv4 = dnv4; t.nth = dnth; t.mask = dmask; t.Vl = dVl; t.theta = dtheta;
     t.step_base = s->d_step;
     t.status = s->d_status;
+    if (s->dose_on) {
+        TRY(zeros(s, &s->d_dose, size_t(nn)));
+        DoseParams &q = s->dq;
+        q.T0 = s->prob.mat.T0;
+        q.cem_off = 316.15 - s->prob.mat.T0;
+        q.dt = s->prob.dt;
+        q.dt_min = s->prob.dt / 60.0;
+        q.arrhenius = s->dose_A > 0.0 ? 1 : 0;
+        q.lnA = s->dose_A > 0.0 ? std::log(s->dose_A) : 0.0;
+        q.EaR = s->dose_Ea / 8.314462618;
+    }
 
     if (s->variant == 1) {
         int4 *dc0, *dc1 = nullptr;
@@ -632,6 +649,7 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
             HIPCHK(s, hipEventRecord(t1.start, s->stream));
             HIPCHK(s, hipEventRecord(t1.stop, s->stream));
         }
+        if (s->d_dose) launch_dose(s->tp.nu4, int(s->pc.nn), s->d_dose, s->dq, s->stream);
     }
     if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k)], s->stream));
     launch_finish(s->d_part_elem, s->n_elem_parts, s->d_part_node, s->n_node_parts, s->d_step, k, s->d_status,
@@ -961,6 +979,18 @@ tled_status tled_set_time(tled_sim *sim, double dt, double damping_gamma) {
     return TLED_OK;
 }
 
+tled_status tled_set_thermal_dose(tled_sim *sim, double arrhenius_A, double arrhenius_Ea) {
+    if (!sim) return TLED_E_ARG;
+    if (sim->is_batch) return fail(sim, TLED_E_UNSUPPORTED, "the thermal dose is for single problems");
+    TRY(need_single_setup(sim));
+    if (!(arrhenius_A >= 0.0) || !std::isfinite(arrhenius_A) || !(arrhenius_Ea >= 0.0) || !std::isfinite(arrhenius_Ea))
+        return fail(sim, TLED_E_ARG, "Arrhenius A and Ea must be finite and >= 0");
+    sim->dose_on = true;
+    sim->dose_A = arrhenius_A;
+    sim->dose_Ea = arrhenius_Ea;
+    return TLED_OK;
+}
+
 tled_status tled_critical_dt(tled_sim *sim, double *dt_cr) {
     if (!sim || !dt_cr) return TLED_E_ARG;
     if (sim->finalized) {
@@ -1104,6 +1134,21 @@ tled_status tled_read_T(tled_sim *sim, double *T) {
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
     const double T0 = sim->prob.mat.T0;
     for (int64_t a = 0; a < nn; ++a) T[sim->pc.node_new2old[a]] = T0 + double(h[a].w);
+    return check_status(sim);
+}
+
+tled_status tled_read_thermal_dose(tled_sim *sim, double *cem43, double *omega) {
+    TRY(need_single(sim));
+    if (!sim->dose_on) return fail(sim, TLED_E_STATE, "the thermal dose was not enabled before finalize");
+    const int64_t nn = sim->pc.nn;
+    std::vector<double2> h(nn);
+    HIPCHK(sim, hipMemcpyAsync(h.data(), sim->d_dose, sizeof(double2) * nn, hipMemcpyDeviceToHost, sim->stream));
+    HIPCHK(sim, hipStreamSynchronize(sim->stream));
+    for (int64_t a = 0; a < nn; ++a) {
+        const int64_t o = sim->pc.node_new2old[a];
+        if (cem43) cem43[o] = h[a].x;
+        if (omega) omega[o] = h[a].y;
+    }
     return check_status(sim);
 }
 
@@ -1269,7 +1314,8 @@ tled_status tled_write_state(tled_sim *sim, const double *u, const double *v, co
 tled_status tled_state_size(tled_sim *sim, size_t *bytes) {
     TRY(need_device(sim));
     if (!bytes) return fail(sim, TLED_E_ARG, "null output");
-    *bytes = 64 + sizeof(float4) * 2 * size_t(sim->pc.nn) + sizeof(float) * sim->theta_floats;
+    *bytes = 64 + sizeof(float4) * 2 * size_t(sim->pc.nn) + sizeof(float) * sim->theta_floats +
+             (sim->dose_on ? sizeof(double2) * size_t(sim->pc.nn) : 0);
     return TLED_OK;
 }
 
@@ -1279,7 +1325,7 @@ tled_status tled_get_state(tled_sim *sim, void *buf) {
     char *b = static_cast<char *>(buf);
     const size_t nn = sim->pc.nn;
     uint64_t hdr[8] = {kStateMagic, uint64_t(sim->pc.nn), uint64_t(sim->pc.ne), uint64_t(sim->np),
-                       uint64_t(sim->variant), 0, 0, 0};
+                       uint64_t(sim->variant), 0, 0, uint64_t(sim->dose_on ? 1 : 0)};
     long long st = 0;
     HIPCHK(sim, hipMemcpyAsync(&st, sim->d_step, sizeof(st), hipMemcpyDeviceToHost, sim->stream));
     unsigned status = 0;
@@ -1290,6 +1336,9 @@ tled_status tled_get_state(tled_sim *sim, void *buf) {
     if (sim->theta_floats)
         HIPCHK(sim, hipMemcpyAsync(b + 64 + 2 * sizeof(float4) * nn, sim->tp.theta, sizeof(float) * sim->theta_floats,
                                    hipMemcpyDeviceToHost, sim->stream));
+    if (sim->dose_on)
+        HIPCHK(sim, hipMemcpyAsync(b + 64 + 2 * sizeof(float4) * nn + sizeof(float) * sim->theta_floats, sim->d_dose,
+                                   sizeof(double2) * nn, hipMemcpyDeviceToHost, sim->stream));
     HIPCHK(sim, hipStreamSynchronize(sim->stream));
     hdr[5] = uint64_t(st);
     hdr[6] = status;
@@ -1304,7 +1353,7 @@ tled_status tled_set_state(tled_sim *sim, const void *buf) {
     uint64_t hdr[8];
     std::memcpy(hdr, b, sizeof(hdr));
     if (hdr[0] != kStateMagic || hdr[1] != uint64_t(sim->pc.nn) || hdr[2] != uint64_t(sim->pc.ne) ||
-        hdr[3] != uint64_t(sim->np) || hdr[4] != uint64_t(sim->variant))
+        hdr[3] != uint64_t(sim->np) || hdr[4] != uint64_t(sim->variant) || hdr[7] != uint64_t(sim->dose_on ? 1 : 0))
         return fail(sim, TLED_E_ARG, "state blob does not match this problem");
     const size_t nn = sim->pc.nn;
     long long st = (long long)hdr[5];
@@ -1315,6 +1364,9 @@ tled_status tled_set_state(tled_sim *sim, const void *buf) {
     if (sim->theta_floats)
         HIPCHK(sim, hipMemcpyAsync(sim->tp.theta, b + 64 + 2 * sizeof(float4) * nn, sizeof(float) * sim->theta_floats,
                                    hipMemcpyHostToDevice, sim->stream));
+    if (sim->dose_on)
+        HIPCHK(sim, hipMemcpyAsync(sim->d_dose, b + 64 + 2 * sizeof(float4) * nn + sizeof(float) * sim->theta_floats,
+                                   sizeof(double2) * nn, hipMemcpyHostToDevice, sim->stream));
     HIPCHK(sim, hipMemcpyAsync(sim->d_step, &st, sizeof(st), hipMemcpyHostToDevice, sim->stream));
     HIPCHK(sim, hipMemcpyAsync(sim->d_status, &status, sizeof(status), hipMemcpyHostToDevice, sim->stream));
     long long qc[2];

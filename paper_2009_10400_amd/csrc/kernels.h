@@ -27,6 +27,19 @@ struct NodeParams {
     long long n_on, n_off;             // source active for n_on <= step < n_off
 };
 
+// Thermal dose accumulated per node when enabled (single problems): CEM43
+// minutes and the Arrhenius damage integral, in FP64, from the node's
+// end-of-step temperature rise dT, by a kernel of its own after each step.
+struct DoseParams {
+    double T0;        // reference temperature, K
+    double cem_off;   // 316.15 K - T0 (43 C relative to T0)
+    double dt_min;    // dt / 60
+    double dt;        // s
+    double lnA;       // ln of the Arrhenius frequency factor (1/s)
+    double EaR;       // Ea / R_gas, K
+    int arrhenius;    // 1: accumulate the Arrhenius integral
+};
+
 // Monitor record written by the finish kernel.
 struct DevMonitors {
     long long step;
@@ -110,6 +123,8 @@ struct LaunchTiming {
 
 void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat &m, hipStream_t s,
                     const LaunchTiming *ev = nullptr);
+// Thermal dose of every node at the temperature the step ended at (single problems).
+void launch_dose(const float4 *nu4, int nn, double2 *dose, const DoseParams &q, hipStream_t s);
 void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s,
                  const LaunchTiming *ev = nullptr);
 // batch: per-scenario constants and end steps (256-thread workgroups only).

@@ -488,6 +488,28 @@ __device__ __forceinline__ float4 sum_node_partials(const float4 *partial, int k
     return acc;
 }
 
+// One step's thermal dose of node a at its end-of-step temperature rise dT,
+// in FP64 (CEM43 rates reach 2^(T - 43 C) per minute, far beyond FP32 at
+// ablation temperatures, and the sums run over 10^5 steps):
+//   CEM43 (Sapareto and Dewey): (dt / 60) R^(43 - T_C), R = 0.5 at T_C >= 43
+//   and 0.25 below, i.e. 2^x resp. 2^(2x) with x = T - 316.15 K;
+//   Arrhenius (Henriques and Moritz): dt A exp(-Ea / (R_gas T)).
+__device__ __forceinline__ void add_thermal_dose(double2 *dose, const DoseParams &q, size_t a, float dT) {
+    const double x = double(dT) - q.cem_off;
+    double2 d = dose[a];
+    d.x += q.dt_min * exp2(x >= 0.0 ? x : 2.0 * x);
+    if (q.arrhenius) d.y += q.dt * exp(q.lnA - q.EaR / (q.T0 + double(dT)));
+    dose[a] = d;
+}
+
+// Runs after a step's node updates (only when the dose is enabled, so the
+// solver kernels carry no trace of it).
+__global__ __launch_bounds__(kBlock) void dose_kernel(const float4 *__restrict__ nu4, int nn,
+                                                      double2 *__restrict__ dose, DoseParams q) {
+    const int a = int(blockIdx.x) * kBlock + int(threadIdx.x);
+    if (a < nn) add_thermal_dose(dose, q, size_t(a), nu4[a].w);
+}
+
 // ---------------------------------------------------------------- two-pass kernels
 
 template <int NP, bool MON, bool ANISO>
@@ -1062,6 +1084,10 @@ void launch_element(int npe, int np, bool mon, const TwoPassArgs &a, const KMat 
             default: launch_h8_element<4>(mon, a, m, s, ev); break;
         }
     }
+}
+
+void launch_dose(const float4 *nu4, int nn, double2 *dose, const DoseParams &q, hipStream_t s) {
+    if (nn > 0) hipLaunchKernelGGL(dose_kernel, dim3((nn + kBlock - 1) / kBlock), dim3(kBlock), 0, s, nu4, nn, dose, q);
 }
 
 void launch_node(bool mon, const TwoPassArgs &a, const NodeParams &p, int j, hipStream_t s, const LaunchTiming *ev) {

@@ -126,6 +126,8 @@ _SIGS = {
     "tled_sync": ([_P], ctypes.c_int),
     "tled_read_u": ([_P, _dp], ctypes.c_int),
     "tled_read_T": ([_P, _dp], ctypes.c_int),
+    "tled_set_thermal_dose": ([_P, _d, _d], ctypes.c_int),
+    "tled_read_thermal_dose": ([_P, _dp, _dp], ctypes.c_int),
     "tled_copy_fields_device": ([_P, _P, _P], ctypes.c_int),
     "tled_get_monitors": ([_P, ctypes.POINTER(Monitors)], ctypes.c_int),
     "tled_get_info": ([_P, ctypes.POINTER(Info)], ctypes.c_int),
@@ -344,6 +346,23 @@ class Sim:
         out = np.zeros(self.nn)
         self._check(_lib.tled_read_T(self._h, _ptr(out)))
         return out
+
+    def set_thermal_dose(self, arrhenius_A: float = 0.0, arrhenius_Ea: float = 0.0):
+        """Accumulate CEM43 and the Arrhenius damage integral per node (before finalize)."""
+        self._check(_lib.tled_set_thermal_dose(self._h, float(arrhenius_A), float(arrhenius_Ea)))
+
+    def read_thermal_dose(self):
+        """(CEM43 minutes, Arrhenius integral) per node, caller numbering."""
+        cem, om = np.zeros(self.nn), np.zeros(self.nn)
+        self._check(_lib.tled_read_thermal_dose(self._h, _ptr(cem), _ptr(om)))
+        return cem, om
+
+    def damage_volumes(self, cem43_min: float = 240.0, omega_min: float = 1.0) -> dict:
+        """Lumped reference volume (m^3) of the nodes whose CEM43 reaches cem43_min minutes and of
+        those whose Arrhenius integral reaches omega_min."""
+        cem, om = self.read_thermal_dose()
+        Vl = self.lumped()["Vl"]
+        return {"cem43": float(Vl[cem >= cem43_min].sum()), "arrhenius": float(Vl[om >= omega_min].sum())}
 
     def copy_fields_device(self, u_dst=None, T_dst=None):
         """Write u (nn x 3) and T (nn) as float32 into device tensors (caller numbering)."""

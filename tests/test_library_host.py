@@ -474,3 +474,31 @@ def test_shared_update_option():
     assert e.value.status == tled.E_ARG
     # one patch: no shared node
     assert host_sim(W.cube_h8(n=6)).info()["shared_update"] == 0
+
+
+def test_thermal_dose_setup_errors():
+    """tled_set_thermal_dose: before finalize, single problems only, finite non-negative
+    Arrhenius parameters; reading needs a device handle with the dose enabled."""
+    from paper_2009_10400_amd import tled
+    p = W.cube_t4(n=2, L=0.01)
+    s = tled.from_problem(p, dt=1e-5, device=-1, finalize=False)
+    for A, Ea in ((-1.0, 1e5), (1e10, -1.0), (float("inf"), 1e5), (1e10, float("nan"))):
+        with pytest.raises(tled.TledError) as e:
+            s.set_thermal_dose(A, Ea)
+        assert e.value.status == tled.E_ARG
+    s.set_thermal_dose(7.39e39, 2.577e5)
+    s.finalize()
+    f = tled.from_problem(W.cube_t4(), dt=1e-5, device=-1, finalize=False, shared_update=1)
+    f.set_thermal_dose(0.0, 0.0)
+    f.finalize()
+    assert f.info()["shared_update"] == 2          # the dose kernel needs every node after each step
+    with pytest.raises(tled.TledError) as e:
+        s.set_thermal_dose(0.0, 0.0)
+    assert e.value.status == tled.E_STATE
+    with pytest.raises(tled.TledError) as e:
+        s.read_thermal_dose()
+    assert e.value.status == tled.E_STATE          # host-only handle: no device state
+    b = tled.Batch(-1)
+    with pytest.raises(tled.TledError) as e:
+        b.set_thermal_dose(0.0, 0.0)
+    assert e.value.status == tled.E_UNSUPPORTED

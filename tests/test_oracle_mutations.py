@@ -13,6 +13,7 @@ import os
 import pytest
 
 import oracle
+import test_oracle_dose_pins as D
 import test_oracle_law_pins as P
 import test_oracle_ortho_pins as R
 import test_oracle_pins as Q
@@ -91,6 +92,22 @@ MUTATIONS = [
     ("tensor_kT_unscaled",
      "double ks = conductivity_scale(m, Te);", "double ks = 1.0;",
      [lambda: R.test_tensor_conduction_kT(336.65), lambda: R.test_tensor_conduction_kT(370.0)]),
+    ("cem43_R_swapped",
+     "double R = Tc >= 43.0 ? 0.5 : 0.25;", "double R = Tc >= 43.0 ? 0.25 : 0.5;",
+     [lambda: D.test_cem43_doubles_per_kelvin_above_and_quarters_below(3, 8.0),
+      lambda: D.test_cem43_doubles_per_kelvin_above_and_quarters_below(-2, 1.0 / 16)]),
+    ("cem43_in_seconds",
+     "cem43[a] += dt / 60.0 * pow(R, 43.0 - Tc);", "cem43[a] += dt * pow(R, 43.0 - Tc);",
+     [D.test_cem43_at_43C_counts_minutes, D.test_dose_over_a_time_loop_at_held_temperatures]),
+    ("cem43_sign_of_exponent",
+     "pow(R, 43.0 - Tc)", "pow(R, Tc - 43.0)",
+     [lambda: D.test_cem43_doubles_per_kelvin_above_and_quarters_below(1, 2.0)]),
+    ("arrhenius_in_celsius",
+     "exp(-Ea / (R_gas * T[a]))", "exp(-Ea / (R_gas * Tc))",
+     [D.test_arrhenius_rate_set_to_one_per_second]),
+    ("arrhenius_without_dt",
+     "omega[a] += dt * A * exp(", "omega[a] += A * exp(",
+     [D.test_arrhenius_rate_set_to_one_per_second]),
     # a few of the older pins, for the laws they pin
     ("pullback_missing_det",
      "for (int i = 0; i < 9; ++i) S0[i] = detFth * T2[i];", "for (int i = 0; i < 9; ++i) S0[i] = T2[i];",
