@@ -591,7 +591,7 @@ tled_status set_queue_counts(tled_sim *s, int64_t step, long long h[2]) {
 // With ev (4 events per step + 2): the element/patch and node/shared-node
 // launches of step j carry the pairs (4j, 4j+1) and (4j+2, 4j+3), taken by the
 // dispatches themselves; the finish kernel is bracketed by the last two.
-tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, double *ms = nullptr,
+tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured,
                           std::vector<hipEvent_t> *ev = nullptr) {
     const int npe = s->pc.npe;
     const int bs = s->opt.block_size > 0 ? s->opt.block_size : kBlock;
@@ -656,7 +656,6 @@ tled_status enqueue_chunk(tled_sim *s, int k, int64_t step0, bool captured, doub
                   s->d_mon, s->stream);
     if (ev) HIPCHK(s, hipEventRecord((*ev)[4 * size_t(k) + 1], s->stream));
     HIPCHK(s, hipGetLastError());
-    (void)ms;
     return TLED_OK;
 }
 
@@ -1658,7 +1657,7 @@ tled_status tled_kernel_times(tled_sim *sim, int64_t n_steps, double ms[3]) {
     tled_status st = TLED_OK;
     while (left > 0 && st == TLED_OK) {
         int c = int(std::min<int64_t>(left, chunk));
-        st = enqueue_chunk(sim, c, cur, false, nullptr, &ev);
+        st = enqueue_chunk(sim, c, cur, false, &ev);
         if (st != TLED_OK) break;
         HIPCHK(sim, hipStreamSynchronize(sim->stream));
         for (int j = 0; j < c; ++j) {

@@ -127,10 +127,11 @@ def test_batch_fields_independent_of_host_threads_and_duration_api(monkeypatch):
         assert np.array_equal(u1, u) and np.array_equal(T1, T)
 
 
-@pytest.mark.parametrize("variant", [2, 3])
-def test_h8_batch_equals_single_runs_bitwise(variant):
+@pytest.mark.parametrize("variant,schedule", [(2, 0), (3, 0), (3, 1)])
+def test_h8_batch_equals_single_runs_bitwise(variant, schedule):
     """H8 scenarios of different sizes and materials in one batch: each equal bit for bit to its own
-    run with the same patch size and kernel variant, and held after its step count."""
+    run with the same patch size and kernel variant, and held after its step count (eager prefix
+    launches, or the persistent kernels)."""
     from paper_2009_10400_amd import tled
     probs = [W.cube_h8(n=n, L=0.02 * n / 6, power=p) for n, p in ((6, 2.0), (9, 5.0), (7, 3.0))]
     probs[1].params = dict(probs[1].params, mu=1500.0, eta=3000.0)
@@ -144,7 +145,7 @@ def test_h8_batch_equals_single_runs_bitwise(variant):
     # explicit step counts: rebuild with the chosen dt
     b.close()
     b = tled.Batch(0)
-    b.set_options(graph_steps=40, kernel_variant=variant)
+    b.set_options(graph_steps=40, kernel_variant=variant, batch_schedule=schedule)
     for p, dt, n in zip(probs, dts, steps):
         b.add(p, dt, n, patch_elems=128)
     b.finalize()
