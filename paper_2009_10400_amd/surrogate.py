@@ -395,6 +395,7 @@ def dataset_from_shards(paths, scenarios, t_ref: float) -> Dataset:
     for path in paths:
         z = np.load(path, allow_pickle=False)
         per, seed = int(z["per_field"]), int(z["seed"])
+        yT, yu = z["yT"], z["yu"]              # each access to the archive decompresses the array
         off = 0
         for s, j, dur, n in zip(z["scenario"], z["ordinal"], z["duration"], z["n"]):
             prob = scenarios[int(s)][0]
@@ -404,7 +405,7 @@ def dataset_from_shards(paths, scenarios, t_ref: float) -> Dataset:
             x, p = scenario_inputs(prob, float(dur), t_ref)
             xs.append(x[idx])
             ps.append(p[idx])
-            ys.append(np.concatenate([z["yT"][off:off + n, None], z["yu"][off:off + n].astype(np.float32)], 1))
+            ys.append(np.concatenate([yT[off:off + n, None], yu[off:off + n].astype(np.float32)], 1))
             fs.append(np.full(n, field, np.int32))
             field += 1
             off += n
