@@ -49,6 +49,9 @@ def parse():
                     help="steps per hipGraph chunk (0: library default, 50 for a problem, eager steps for a batch)")
     ap.add_argument("--patch-elems", type=int, default=0, help="elements per patch (0: library default)")
     ap.add_argument("--block-size", type=int, default=0, help="patch kernel threads per workgroup (0: default)")
+    ap.add_argument("--thermal-dose", action="store_true",
+                    help="accumulate CEM43 and the Arrhenius integral per node (a published liver set, "
+                         "A = 7.39e39 /s, Ea = 2.577e5 J/mol) and report the damaged volumes")
     ap.add_argument("--shared-update", type=int, default=0, choices=[0, 1, 2],
                     help="shared nodes advanced inside the next step's patch kernel (1, the default where "
                          "available) or by a kernel of their own after every step (2)")
@@ -251,6 +254,18 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
     if not ok:
         raise RuntimeError("stream copy produced wrong data")
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def dose_summary(sim):
+    """Thermal dose after the run: largest CEM43 and Arrhenius integral, and the lumped volumes
+    past the usual thresholds (240 equivalent minutes, Omega = 1) beside the 60 C monitor."""
+    cem, om = sim.read_thermal_dose()
+    vols = sim.damage_volumes(240.0, 1.0)
+    m = sim.monitors()
+    return {"cem43_max_min": float(cem.max()), "omega_max": float(om.max()),
+            "volume_cem43_240_m3": vols["cem43"], "volume_omega_1_m3": vols["arrhenius"],
+            "volume_60C_m3": m["ablated_volume"], "T_max_K": m["T_max"], "simulated_s": m["t"],
+            "arrhenius": {"A_per_s": 7.39e39, "Ea_J_per_mol": 2.577e5}}
 
 
 def cpu_model() -> str:
@@ -595,7 +610,11 @@ def main():
     stream = torch.cuda.Stream(device=0)
     sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, kernel_variant=args.variant,
                             graph_steps=args.graph_steps, patch_elems=args.patch_elems,
-                            block_size=args.block_size, reorder=args.reorder, shared_update=args.shared_update)
+                            block_size=args.block_size, reorder=args.reorder, shared_update=args.shared_update,
+                            finalize=False)
+    if args.thermal_dose:
+        sim.set_thermal_dose(7.39e39, 2.577e5)
+    sim.finalize()
     info = sim.info()
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
     sim.step(args.warmup)
@@ -711,6 +730,7 @@ def main():
         "repeats": {"ms_per_step": reps, "median_ms_per_step": ms_per_step,
                     "note": "value and ms_per_step are the median of these timed regions of K steps each"},
         "long_region": steady,
+        "thermal_dose": None if not args.thermal_dose else dose_summary(sim),
     }
     if not args.no_cpu_baseline and p.npe == 4:
         steps = args.cpu_steps or max(3, int(100e6 / p.ne))
