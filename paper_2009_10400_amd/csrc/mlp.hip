@@ -344,6 +344,14 @@ struct NetOffsets {
     long w[kFusedMaxDepth + 1];
     long b[kFusedMaxDepth + 1];
 };
+// The training forward keeps what the backward pass reads: the features (bf16,
+// n x K0) and every hidden layer's FP32 pre-activation and bf16 activation
+// (n x W, row-major), the same arrays the layer-by-layer GEMMs write.
+struct TrainStore {
+    uint16_t *x0;
+    float *z[kFusedMaxDepth];
+    uint16_t *a[kFusedMaxDepth];
+};
 
 // Z^T (16 NT units x 64 samples per wavefront) = W A^T with A (64 x K, LDS), K
 // in steps of 32: the weights are the MFMA A operand and the activations the B
@@ -388,14 +396,16 @@ __device__ __forceinline__ void fused_layer_k(f32x4 (&acc)[4][NT], const uint16_
     }
 }
 
-template <int W>
+// TRAIN: also stores the features, pre-activations and activations (TrainStore)
+// for the backward pass.
+template <int W, bool TRAIN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(long n, const float *__restrict__ x,
                                                                  const float *__restrict__ p,
                                                                  const float *__restrict__ Bf, int nf, int np,
                                                                  int K0, int depth, int nout,
                                                                  const uint16_t *__restrict__ wb,
                                                                  const float *__restrict__ wf, NetOffsets off,
-                                                                 float *__restrict__ out) {
+                                                                 float *__restrict__ out, TrainStore ts) {
     extern __shared__ __attribute__((aligned(16))) uint16_t act[];
     const int P = (K0 > W ? K0 : W) + 8;          // LDS row pitch (elements)
     const long r0 = long(blockIdx.x) * kFusedRows;
@@ -413,7 +423,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
                 v = p[i * np + (j - 2 * nf)];
             }
         }
-        act[row * P + j] = bf16_bits(v);
+        const uint16_t bits = bf16_bits(v);
+        act[row * P + j] = bits;
+        if (TRAIN && i < n) ts.x0[i * K0 + j] = bits;
     }
     __syncthreads();
     constexpr int NT = W / 64;                     // 16-column tiles per wavefront
@@ -445,6 +457,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
                 q.x = uint32_t(bf16_bits(z0 * sigmoidf_hw(z0))) | (uint32_t(bf16_bits(z1 * sigmoidf_hw(z1))) << 16);
                 q.y = uint32_t(bf16_bits(z2 * sigmoidf_hw(z2))) | (uint32_t(bf16_bits(z3 * sigmoidf_hw(z3))) << 16);
                 *reinterpret_cast<uint2 *>(&act[row * P + u0]) = q;
+                if (TRAIN && r0 + row < n) {
+                    const size_t o = size_t(r0 + row) * W + u0;
+                    *reinterpret_cast<float4 *>(ts.z[layer] + o) = make_float4(z0, z1, z2, z3);
+                    *reinterpret_cast<uint2 *>(ts.a[layer] + o) = q;
+                }
             }
         }
         __syncthreads();
@@ -783,7 +800,9 @@ bool fused_ok(const tled_mlp *s) {
            fused_lds_bytes(s) <= 64 * 1024;
 }
 
-tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float *params, float *out) {
+// ts: the training forward (stores for the backward pass); null for inference.
+tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float *params, float *out,
+                          const TrainStore *ts = nullptr) {
     NetOffsets off{};
     for (int l = 0; l <= s->cfg.depth; ++l) {
         off.w[l] = s->layers[l].w_off;
@@ -797,13 +816,19 @@ tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float 
         MCHK(s, hipEventCreate(&e1));
         MCHK(s, hipEventRecord(e0, s->stream));
     }
-#define TLED_FUSED(WIDTH)                                                                                   \
-    hipLaunchKernelGGL(fused_forward_kernel<WIDTH>, dim3(grid), dim3(kThreads), lds, s->stream, n, coords, \
-                       params, s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->cfg.depth, s->cfg.n_out, \
-                       s->d_wb, s->d_w, off, out)
-    if (s->cfg.width == 64) TLED_FUSED(64);
-    else if (s->cfg.width == 128) TLED_FUSED(128);
-    else TLED_FUSED(256);
+#define TLED_FUSED(WIDTH, TR)                                                                               \
+    hipLaunchKernelGGL((fused_forward_kernel<WIDTH, TR>), dim3(grid), dim3(kThreads), lds, s->stream, n,    \
+                       coords, params, s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->cfg.depth,         \
+                       s->cfg.n_out, s->d_wb, s->d_w, off, out, ts ? *ts : TrainStore{})
+    if (ts) {
+        if (s->cfg.width == 64) TLED_FUSED(64, true);
+        else if (s->cfg.width == 128) TLED_FUSED(128, true);
+        else TLED_FUSED(256, true);
+    } else {
+        if (s->cfg.width == 64) TLED_FUSED(64, false);
+        else if (s->cfg.width == 128) TLED_FUSED(128, false);
+        else TLED_FUSED(256, false);
+    }
 #undef TLED_FUSED
     MCHK(s, hipGetLastError());
     if (s->timing) {
@@ -811,9 +836,15 @@ tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float 
         MCHK(s, hipEventSynchronize(e1));
         float ms = 0.f;
         MCHK(s, hipEventElapsedTime(&ms, e0, e1));
-        s->fused_ms += ms;
         const double W = s->cfg.width;
-        s->fused_flops += 2.0 * double(n) * (double(s->K0) * W + (s->cfg.depth - 1) * W * W + W * s->cfg.n_out);
+        const double fl = 2.0 * double(n) * (double(s->K0) * W + (s->cfg.depth - 1) * W * W + W * s->cfg.n_out);
+        if (ts) {   // the training forward: counted with the step's GEMMs
+            s->gemm_ms += ms;
+            s->gemm_flops += fl;
+        } else {
+            s->fused_ms += ms;
+            s->fused_flops += fl;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
@@ -821,9 +852,20 @@ tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float 
 }
 
 // Forward pass for n samples: features, hidden layers (Z, activations kept), output into d_y.
+// With the fused kernel available, one launch writes all of them (the same bits as the
+// layer-by-layer GEMMs, whose epilogue arithmetic it repeats).
 tled_status forward(tled_mlp *s, long n, const float *coords, const float *params) {
     MTRY(ensure_workspace(s, n));
     const int W = s->cfg.width;
+    if (fused_ok(s)) {
+        TrainStore ts{};
+        ts.x0 = s->d_x0;
+        for (int l = 0; l < s->cfg.depth; ++l) {
+            ts.z[l] = s->d_z[l];
+            ts.a[l] = s->d_a[l];
+        }
+        return fused_forward(s, n, coords, params, s->d_y, &ts);
+    }
     hipLaunchKernelGGL(features_kernel, dim3(blocks(n * s->K0)), dim3(kThreads), 0, s->stream, n, coords, params,
                        s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->d_x0);
     MCHK(s, hipGetLastError());

@@ -167,6 +167,26 @@ def test_training_reduces_loss_and_is_deterministic(torch_dev):
     assert np.array_equal(a.params(), b.params())
 
 
+@pytest.mark.parametrize("width,depth,n", [(64, 2, 1000), (256, 5, 4097), (128, 3, 77)])
+def test_fused_training_forward_equals_layerwise(torch_dev, width, depth, n):
+    """Training steps whose forward pass is the fused kernel (storing the features, every
+    pre-activation and activation for the backward pass) leave the same parameters, bit for bit,
+    as steps through the layer-by-layer GEMMs."""
+    import torch
+    print(f"[fused train] width={width} depth={depth} n={n}", flush=True)
+    rng = np.random.default_rng(width + depth)
+    x = torch.from_numpy(rng.uniform(-1, 1, (n, 3)).astype(np.float32)).to(torch_dev)
+    p = torch.from_numpy(rng.uniform(-1, 1, (n, 5)).astype(np.float32)).to(torch_dev)
+    t = torch.from_numpy(rng.normal(size=(n, 4)).astype(np.float32)).to(torch_dev)
+    cfg = dict(n_param=5, n_freq=32, width=width, depth=depth, n_out=4)
+    a, b = _mlp(**cfg, seed=2, sigma=0.5), _mlp(**cfg, seed=2, sigma=0.5, layerwise=True)
+    for k in range(12):
+        la = a.train_step(x, p, t, 2e-3, want_loss=k == 11)
+        lb = b.train_step(x, p, t, 2e-3, want_loss=k == 11)
+    assert la == lb
+    assert np.array_equal(a.params(), b.params())
+
+
 def test_argument_errors(torch_dev):
     import torch
     from paper_2009_10400_amd import surrogate
