@@ -100,6 +100,9 @@ def parse():
                     metavar=("WORKLOAD", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "COPY_MIB"),
                     help="write profiles/traffic_WORKLOAD.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
                          "databases of a bench run and of a --copy-calibration run")
+    ap.add_argument("--mlp-train-timing", action="store_true",
+                    help="time training steps of the surrogate network (width 256, depth 5, 16384 random "
+                         "samples), fused forward against the layer-by-layer GEMMs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 launches) to calibrate HBM counters")
     return ap.parse_args()
@@ -254,6 +257,42 @@ def copy_bandwidth(mib: int = 1024, reps: int = 5):
     if not ok:
         raise RuntimeError("stream copy produced wrong data")
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def mlp_train_timing(args):
+    """Training-step time of the surrogate network on random data: the forward pass through the
+    fused kernel (default) and through the layer-by-layer GEMMs, HIP-event GEMM time included."""
+    import torch
+    from paper_2009_10400_amd import surrogate as S
+    dev = torch.device("cuda", 0)
+    n = args.train_batch
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.uniform(-1, 1, (n, 3)).astype(np.float32)).to(dev)
+    p = torch.from_numpy(rng.uniform(-1, 1, (n, 11)).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.normal(size=(n, 4)).astype(np.float32)).to(dev)
+    out = {"metric": "surrogate training step", "samples_per_step": n,
+           "net": "64 Fourier frequencies + 11 parameters -> 5 x 256 SiLU -> 4", "data": "synthetic"}
+    for lw in (False, True):
+        m = S.MLP(0, n_freq=64, width=256, depth=5, n_out=4, seed=3, layerwise=lw)
+        for _ in range(10):
+            m.train_step(x, p, t, 1e-4)
+        m.set_timing(True)
+        for _ in range(10):
+            m.train_step(x, p, t, 1e-4)
+        tm = m.timing()
+        m.set_timing(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            m.train_step(x, p, t, 1e-4)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) / 50 * 1e3
+        key = "layer_by_layer" if lw else "fused_forward"
+        out[key] = {"train_step_ms": step_ms, "gemm_us_per_step": tm["gemm_ms"] / 10 * 1e3,
+                    "gemm_TFLOPs": tm["gemm_flops"] / (tm["gemm_ms"] * 1e-3) / 1e12}
+        log(f"[mlp] {key}: {out[key]}")
+        m.close()
+    print(json.dumps(out), flush=True)
 
 
 def dose_summary(sim):
@@ -589,6 +628,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.mlp_train_timing:
+        mlp_train_timing(args)
         return
     if args.counters_summary:
         counters_summary(*args.counters_summary)
