@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/tled_surrogate.h"
@@ -16,9 +17,13 @@
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
 
 constexpr int kThreads = 256;
+constexpr int kColChunk = 64;   // least rows per chunk of a column-sum pass
 constexpr int BM = 64, BN = 64, BK = 64, BKP = BK + 8;   // LDS rows padded against bank conflicts
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
@@ -86,18 +91,42 @@ __device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, lo
     }
 }
 
-// Stores a thread's share of half h into the LDS tile S[r][k] (row pitch BKP).
+// Stores a thread's share of half h into the LDS tile: S[r][k] (row pitch BKP), or,
+// for tiles read with rows contiguous, S[k][r] as loaded (one 16-byte store; the
+// MFMA fragments are then fetched with the transpose read, see frag()).
 template <int MODE>
 __device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t, int h) {
+    static_assert(BM == BK && BN == BK, "a k-major tile reuses the r-major tile's array");
     if (MODE == LD_RVEC) {
         const int k = 32 * h + (t >> 3), r = (t & 7) * 8;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) S[r + i][k] = q.v[i];
+        uint4 w;
+        std::memcpy(&w, q.v, 16);
+        *reinterpret_cast<uint4 *>(&S[k][r]) = w;
     } else {
         const int r = t >> 2, k = 32 * h + (t & 3) * 8;
         uint4 w;
         std::memcpy(&w, q.v, 16);
         *reinterpret_cast<uint4 *>(&S[r][k]) = w;
+    }
+}
+
+// The 16 x 32 MFMA operand fragment of rows r0..r0+15, k in [32h, 32h + 32), of an
+// LDS tile: lane l gets X(r0 + l%16, 32h + 8(l/16) + 0..7).  From an r-major tile
+// (S[r][k]) that is one 16-byte read.  From a k-major tile (S[k][r]) it takes two
+// ds_read_b64_tr_b16: each lane of a 16-lane group reads 4 consecutive values of
+// one k row, and the instruction hands lane i of the group value i%4 of lane
+// 4j + i/4's read as its value j; lane 4j + q therefore reads row k0 + j at
+// columns r0 + 4q.., which gives lane i the 4 k values of column r0 + i.
+template <int MODE>
+__device__ inline bf16x8 frag(const uint16_t (*S)[BKP], int r0, int h, int l) {
+    if (MODE == LD_RVEC) {
+        const int k = 32 * h + 8 * (l >> 4) + ((l & 15) >> 2), r = r0 + 4 * (l & 3);
+        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[k][r]));
+        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[k + 4][r]));
+        const i16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_bit_cast(bf16x8, v);
+    } else {
+        return *reinterpret_cast<const bf16x8 *>(&S[r0 + (l & 15)][32 * h + 8 * (l >> 4)]);
     }
 }
 
@@ -113,12 +142,19 @@ __device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t, 
 // s = sigmoid(z).
 // Split-K: workgroup z covers k in [z*kchunk, (z+1)*kchunk) and (EPI_F32 only)
 // writes its partial tile to C + z*M*N (row-major M x N); a reduction follows.
-template <int EPI, int AM, int BMODE>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, const uint16_t *__restrict__ A,
-                                                        long sam, long sak, const uint16_t *__restrict__ B, long sbk,
-                                                        long sbn, float *__restrict__ C, long scm, long scn,
-                                                        uint16_t *__restrict__ Act, const float *__restrict__ bias,
-                                                        int kchunk) {
+// COLS (EPI_F32 with A read along rows): the workgroups of the first column tile
+// also sum A over their k range, colsum[z*M + m] = sum_k A(m, k) (a layer's bias
+// gradient beside its weight gradient): each thread adds the 8 values it stages,
+// tile by tile in increasing k, and the 32 threads of a row group are combined in
+// thread order.
+// Four wavefronts per SIMD: the k loop waits on global memory, so occupancy is what
+// hides the latency (the accumulators live in VGPRs, no spills).
+template <int EPI, int AM, int BMODE, bool COLS = false>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel(
+    int M, int N, int K, const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *__restrict__ B, long sbk,
+    long sbn, float *__restrict__ C, long scm, long scn, uint16_t *__restrict__ Act, const float *__restrict__ bias,
+    int kchunk, float *__restrict__ colsum) {
+    static_assert(!COLS || (EPI == EPI_F32 && AM == LD_RVEC), "column sums of an A tile staged along rows");
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][BKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bt[2][BN][BKP];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -132,6 +168,8 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
     const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     if (gridDim.z > 1) C += size_t(blockIdx.z) * M * N;
     const int ntiles = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+    const bool cols = COLS && blockIdx.x == 0;
+    float cs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     TileRegs qa[2], qb[2];
     // double-buffered 64-deep k tiles: tile t + 1 is read from global memory into
     // registers while tile t is multiplied out of LDS; one barrier per tile
@@ -142,6 +180,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
             tile_load<BMODE>(qb[h], B, sbn, sbk, n0, N, kb, ke, t, h);
             tile_store<AM>(qa[h], As[0], t, h);
             tile_store<BMODE>(qb[h], Bt[0], t, h);
+            if (cols)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cs[i] += bf2f(qa[h].v[i]);
         }
     }
     __syncthreads();
@@ -160,12 +201,10 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
             if (k0 + 32 * h >= ke) break;        // the same 32-deep MFMA steps as a 32-deep loop
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const bf16x8 a =
-                    *reinterpret_cast<const bf16x8 *>(&As[cur][wm + 16 * i + (l & 15)][32 * h + 8 * (l >> 4)]);
+                const bf16x8 a = frag<AM>(As[cur], wm + 16 * i, h, l);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const bf16x8 b =
-                        *reinterpret_cast<const bf16x8 *>(&Bt[cur][wn + 16 * j + (l & 15)][32 * h + 8 * (l >> 4)]);
+                    const bf16x8 b = frag<BMODE>(Bt[cur], wn + 16 * j, h, l);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
                 }
             }
@@ -175,9 +214,25 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
             for (int h = 0; h < 2; ++h) {
                 tile_store<AM>(qa[h], As[cur ^ 1], t, h);
                 tile_store<BMODE>(qb[h], Bt[cur ^ 1], t, h);
+                if (cols)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) cs[i] += bf2f(qa[h].v[i]);
             }
         }
         __syncthreads();
+    }
+    if (cols) {
+        // thread t holds rows 8(t%8) + i summed over k = 32h + t/8 of every tile;
+        // the LDS tiles are free after the loop's last barrier
+        float *red = reinterpret_cast<float *>(&As[0][0][0]);   // [32][64]
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red[(t >> 3) * 64 + 8 * (t & 7) + i] = cs[i];
+        __syncthreads();
+        if (t < 64 && m0 + t < M) {
+            float a = 0.f;
+            for (int g = 0; g < 32; ++g) a += red[g * 64 + t];
+            colsum[size_t(blockIdx.z) * M + m0 + t] = a;
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -205,16 +260,167 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(int M, int N, int K, con
             }
 }
 
-// Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n).
+// Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n); with
+// bout, threads past M x N sum the column-sum partials (nz x M) into bout[m].
 __global__ void splitk_reduce_kernel(int nz, int M, int N, const float *__restrict__ part, float *__restrict__ C,
-                                     long scm, long scn) {
+                                     long scm, long scn, const float *__restrict__ bpart, float *__restrict__ bout) {
     const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= long(M) * N) return;
+    const long MN = long(M) * N;
+    if (i >= MN) {
+        if (!bout || i >= MN + M) return;
+        const long m = i - MN;
+        float s = 0.f;
+#pragma unroll 8
+        for (int z = 0; z < nz; ++z) s += bpart[size_t(z) * M + m];
+        bout[m] = s;
+        return;
+    }
     float s = 0.f;
 #pragma unroll 8
     for (int z = 0; z < nz; ++z) s += part[size_t(z) * M * N + i];   // loads in flight, additions in order
     const long m = i / N, n = i % N;
     C[m * scm + n * scn] = s;
+}
+
+// Output layer's gradient for n_out <= kOutMax, one pass over the last hidden
+// activations: part[c][o W + j] = sum over the rows r of chunk c of dY(r, o) a(r, j),
+// and part[c][n_out W + o] = sum_r dY(r, o) (the bias).  Products of two bfloat16
+// values are exact in FP32.  A thread takes four adjacent columns and every fourth
+// row of a block of 64 (its 16 loads in flight at once, dY of the block in LDS);
+// rows in increasing order per thread, then the four row phases combined in order.
+constexpr int kOutMax = 8;
+__global__ __launch_bounds__(kThreads) void out_grad_partial_kernel(long n, int W, int no, long rows,
+                                                                    const uint16_t *__restrict__ dY,
+                                                                    const uint16_t *__restrict__ Aact,
+                                                                    float *__restrict__ part) {
+    __shared__ float dys[64][kOutMax];
+    __shared__ float red[4][64][4 * kOutMax + kOutMax];
+    const int t = threadIdx.x, cq = t & 63, ph = t >> 6;
+    const long r0 = long(blockIdx.x) * rows, r1 = min(n, r0 + rows);
+    float *out = part + size_t(blockIdx.x) * no * (W + 1);
+    for (int cb = 0; cb < W; cb += 256) {
+        const int j = cb + 4 * cq;
+        const bool on = j < W;
+        float acc[4][kOutMax], bacc[kOutMax];
+#pragma unroll
+        for (int o = 0; o < kOutMax; ++o) {
+            bacc[o] = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c][o] = 0.f;
+        }
+        for (long b0 = r0; b0 < r1; b0 += 64) {
+            const int nb = int(min(64L, r1 - b0));
+            __syncthreads();
+            for (int e = t; e < 64 * kOutMax; e += kThreads) {
+                const int rr = e / kOutMax, o = e % kOutMax;
+                dys[rr][o] = (rr < nb && o < no) ? bf2f(dY[(b0 + rr) * no + o]) : 0.f;
+            }
+            __syncthreads();
+            uint2 av[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int rr = ph + 4 * i;
+                av[i] = (on && rr < nb) ? *reinterpret_cast<const uint2 *>(Aact + (b0 + rr) * W + j) : uint2{0u, 0u};
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int rr = ph + 4 * i;
+                const float a[4] = {bf2f(uint16_t(av[i].x & 0xffffu)), bf2f(uint16_t(av[i].x >> 16)),
+                                    bf2f(uint16_t(av[i].y & 0xffffu)), bf2f(uint16_t(av[i].y >> 16))};
+#pragma unroll
+                for (int o = 0; o < kOutMax; ++o) {
+                    const float d = dys[rr][o];   // zero past the block's rows and n_out
+                    bacc[o] += d;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c][o] += d * a[c];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < kOutMax; ++o) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[ph][cq][c * kOutMax + o] = acc[c][o];
+            red[ph][cq][4 * kOutMax + o] = bacc[o];
+        }
+        __syncthreads();
+        // the 64 column quads' 5 kOutMax values each, finished by the threads in turn
+        for (int e = t; e < 64 * 5 * kOutMax; e += kThreads) {
+            const int q = e / (5 * kOutMax), v = e % (5 * kOutMax);
+            const float sum = ((red[0][q][v] + red[1][q][v]) + red[2][q][v]) + red[3][q][v];
+            if (v < 4 * kOutMax) {
+                const int c = v / kOutMax, o = v % kOutMax, jj = cb + 4 * q + c;
+                if (o < no && jj < W) out[size_t(o) * W + jj] = sum;
+            } else if (cb == 0 && q == 0 && v - 4 * kOutMax < no) {
+                out[size_t(no) * W + (v - 4 * kOutMax)] = sum;
+            }
+        }
+    }
+}
+
+// Fixed-order sum of nparts partial vectors of length L: sixteen threads per
+// element, thread q adding parts q, q + 16, ... in order, the sixteen sums then
+// added in thread order.
+__global__ __launch_bounds__(kThreads) void parts_reduce_kernel(int nparts, long L, const float *__restrict__ part,
+                                                                float *__restrict__ out) {
+    __shared__ float sh[16][17];
+    const int q = threadIdx.x & 15, el = threadIdx.x >> 4;
+    const long e = long(blockIdx.x) * 16 + el;
+    float a = 0.f;
+    if (e < L) {
+#pragma unroll 8
+        for (int c = q; c < nparts; c += 16) a += part[size_t(c) * L + e];
+    }
+    sh[el][q] = a;
+    __syncthreads();
+    if (q == 0 && e < L) {
+        float sum = 0.f;
+        for (int k = 0; k < 16; ++k) sum += sh[el][k];
+        out[e] = sum;
+    }
+}
+
+// Row chunks of the output layer's gradient: (rows per chunk, chunks), at least
+// kColChunk rows and at most 1024 chunks.
+std::pair<long, long> out_grad_chunks(long n) {
+    const long rows = std::max<long>(kColChunk, (n + 1023) / 1024);
+    return {rows, (n + rows - 1) / rows};
+}
+
+// dZ of the last hidden layer for n_out <= kOutMax: (dY W_O)(r, j) = sum_o dY(r, o) W_O(o, j)
+// in increasing o, through the SiLU at z(r, j) (the arithmetic of the GEMM epilogue).
+// Four columns per thread (W is a multiple of 64).
+__global__ void out_back_kernel(long n, int W, int no, const uint16_t *__restrict__ dY,
+                                const uint16_t *__restrict__ WO, const float *__restrict__ Z,
+                                uint16_t *__restrict__ dZ) {
+    const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int q = W / 4;
+    if (idx >= n * q) return;
+    const long r = idx / q;
+    const int j = 4 * int(idx % q);
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < kOutMax; ++o)
+        if (o < no) {
+            const float d = bf2f(dY[r * no + o]);
+            const uint2 wv = *reinterpret_cast<const uint2 *>(WO + size_t(o) * W + j);
+            v[0] += d * bf2f(uint16_t(wv.x & 0xffffu));
+            v[1] += d * bf2f(uint16_t(wv.x >> 16));
+            v[2] += d * bf2f(uint16_t(wv.y & 0xffffu));
+            v[3] += d * bf2f(uint16_t(wv.y >> 16));
+        }
+    const float4 z4 = *reinterpret_cast<const float4 *>(Z + r * W + j);
+    const float zz[4] = {z4.x, z4.y, z4.z, z4.w};
+    uint16_t h[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float z = zz[i], sg = sigmoidf_hw(z);
+        h[i] = bf16_bits(v[i] * sg * (1.0f + z * (1.0f - sg)));
+    }
+    uint2 o2;
+    o2.x = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
+    o2.y = uint32_t(h[2]) | (uint32_t(h[3]) << 16);
+    *reinterpret_cast<uint2 *>(dZ + r * W + j) = o2;
 }
 
 // Features of sample i: [sin(2 pi B x_i), cos(2 pi B x_i), p_i, 0 ...] as bfloat16 (row of K0).
@@ -269,9 +475,8 @@ __global__ void sum_kernel(int nparts, const float *__restrict__ part, float sca
     if (threadIdx.x == 0) out[0] = sh[0] * scale;
 }
 
-// Column sums of a bfloat16 M x N matrix in chunks of rows: part[c][j]
-// (short chunks: enough workgroups to keep the loads in flight).
-constexpr int kColChunk = 64;
+// Column sums of a bfloat16 M x N matrix in chunks of rows (at least kColChunk
+// rows each): part[c][j] (short chunks: enough workgroups to keep the loads in flight).
 __global__ void colsum_partial_kernel(long M, int N, const uint16_t *__restrict__ X, float *__restrict__ part,
                                       long chunk) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -707,7 +912,9 @@ tled_status ensure_workspace(tled_mlp *s, long n) {
     MTRY(walloc(s, &s->d_dz2, size_t(cap) * W));
     MTRY(walloc(s, &s->d_part, size_t(blocks(cap * no))));
     MTRY(walloc(s, &s->d_loss, 1));
-    MTRY(walloc(s, &s->d_cpart, size_t((cap + kColChunk - 1) / kColChunk) * std::max<long>(W, no)));
+    MTRY(walloc(s, &s->d_cpart, std::max(size_t((cap + kColChunk - 1) / kColChunk) * std::max<long>(W, no),
+                                         size_t(std::min<long>(1024, (cap + kColChunk - 1) / kColChunk)) * no *
+                                             (W + 1))));   // the most chunks out_grad_chunks(n <= cap) makes
     s->cap = cap;
     return TLED_OK;
 }
@@ -722,16 +929,26 @@ int load_mode(const uint16_t *X, long sr, long sk) {
 
 // split_ext: split-K partials in a caller-held buffer of split_ext_cap floats
 // (nothing is allocated and no timing events are created); else the handle's
-// buffer, grown on demand.
+// buffer, grown on demand.  colsum (EPI_F32, both operands read along rows): also
+// colsum[m] = sum_k A(m, k), from the same staged tiles.  Split-K (EPI_F32, fewer
+// than 256 output tiles): about split_target workgroups (nz x tiles), at most 64 x
+// split_target / 512 k chunks.  The entry points keep 512; the weight gradients
+// of training ask for 1024 (their k loops are latency bound: more, shorter chunks
+// measured faster despite the larger partials).
 template <int EPI>
 tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, long sak, const uint16_t *B,
                  long sbk, long sbn, float *C, long scm, long scn, uint16_t *Act, const float *bias,
-                 float *split_ext = nullptr, size_t split_ext_cap = 0) {
+                 float *split_ext = nullptr, size_t split_ext_cap = 0, float *colsum = nullptr,
+                 int split_target = 512) {
     const long tiles = long((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     int nz = 1;
-    if (EPI == EPI_F32 && tiles < 256 && K >= 4 * BK) nz = int(std::min<long>(64, std::max<long>(1, 512 / tiles)));
+    if (EPI == EPI_F32 && tiles < 256 && K >= 4 * BK)
+        nz = int(std::min<long>(64L * split_target / 512, std::max<long>(1, split_target / tiles)));
     int kchunk = ((K + nz - 1) / nz + BK - 1) / BK * BK;
     nz = (K + kchunk - 1) / kchunk;
+    const int am = load_mode(A, sam, sak), bmode = load_mode(B, sbn, sbk);
+    if (colsum && (EPI != EPI_F32 || am != LD_RVEC || bmode != LD_RVEC || split_ext))
+        return mfail(s, TLED_E_ARG, "column sums need both operands read along rows");
     float *split = s->d_split;
     if (nz > 1 && split_ext) {
         const size_t need = size_t(nz) * M * N;
@@ -740,7 +957,7 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
                                             std::to_string(split_ext_cap) + " of the static scratch array");
         split = split_ext;
     } else if (nz > 1) {
-        const size_t need = size_t(nz) * M * N;
+        const size_t need = size_t(nz) * M * N + (colsum ? size_t(nz) * M : 0);
         if (need > s->split_cap) {
             MCHK(s, hipStreamSynchronize(s->stream));   // earlier launches may still use the old buffer
             if (s->d_split) (void)hipFree(s->d_split);
@@ -754,7 +971,7 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
         split = s->d_split;
     }
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, nz);
-    const int am = load_mode(A, sam, sak), bmode = load_mode(B, sbn, sbk);
+    float *cpart = colsum && nz > 1 ? split + size_t(nz) * M * N : colsum;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool timed = s->timing && !split_ext;
     if (timed) {
@@ -763,18 +980,26 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
         MCHK(s, hipEventRecord(e0, s->stream));
     }
     float *Cout = nz > 1 ? split : C;
-#define TLED_GEMM_LAUNCH(AMODE, BMODE_)                                                                       \
-    hipLaunchKernelGGL((gemm_kernel<EPI, AMODE, BMODE_>), grid, dim3(kThreads), 0, s->stream, M, N, K, A, sam, sak, \
-                       B, sbk, sbn, Cout, scm, scn, Act, bias, kchunk)
-    if (am == LD_KVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_KVEC);
-    else if (am == LD_KVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_RVEC);
-    else if (am == LD_RVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_RVEC);
-    else if (am == LD_RVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_KVEC);
-    else TLED_GEMM_LAUNCH(LD_SCALAR, LD_SCALAR);
+#define TLED_GEMM_LAUNCH(AMODE, BMODE_, COLS)                                                                 \
+    hipLaunchKernelGGL((gemm_kernel<EPI, AMODE, BMODE_, COLS>), grid, dim3(kThreads), 0, s->stream, M, N, K, A, sam, \
+                       sak, B, sbk, sbn, Cout, scm, scn, Act, bias, kchunk, cpart)
+    bool launched = false;
+    if constexpr (EPI == EPI_F32) {
+        if (colsum) {
+            TLED_GEMM_LAUNCH(LD_RVEC, LD_RVEC, true);
+            launched = true;
+        }
+    }
+    if (launched) {
+    } else if (am == LD_KVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_KVEC, false);
+    else if (am == LD_KVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_KVEC, LD_RVEC, false);
+    else if (am == LD_RVEC && bmode == LD_RVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_RVEC, false);
+    else if (am == LD_RVEC && bmode == LD_KVEC) TLED_GEMM_LAUNCH(LD_RVEC, LD_KVEC, false);
+    else TLED_GEMM_LAUNCH(LD_SCALAR, LD_SCALAR, false);
 #undef TLED_GEMM_LAUNCH
     if (nz > 1)
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks(long(M) * N)), dim3(kThreads), 0, s->stream, nz, M, N,
-                           split, C, scm, scn);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks(long(M) * N + (colsum ? M : 0))), dim3(kThreads), 0,
+                           s->stream, nz, M, N, split, C, scm, scn, cpart, colsum);
     MCHK(s, hipGetLastError());
     if (timed) {
         MCHK(s, hipEventRecord(e1, s->stream));
@@ -898,25 +1123,47 @@ tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
     const unsigned nchunk = unsigned((n + chunk - 1) / chunk);
     // output layer
     const Layer &O = s->layers.back();
-    MTRY(gemm<EPI_F32>(s, no, W, int(n), s->d_dy, 1, no, s->d_a[D - 1], W, 1, s->d_g + O.w_off, W, 1, nullptr,
-                       nullptr));
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3((no + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
-                       s->stream, n, no, s->d_dy, s->d_cpart, chunk);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3((no + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk), no,
-                       s->d_cpart, s->d_g + O.b_off);
-    // dZ of the last hidden layer = (dY W_O) through its SiLU, in the GEMM epilogue
     uint16_t *dz = s->d_dz, *dz_next = s->d_dz2;
-    MTRY(gemm<EPI_SILU_BACK>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, nullptr, W, 1, dz,
-                             s->d_z[D - 1]));
+    if (no <= kOutMax) {
+        // weights and bias of the output layer are contiguous in the gradient
+        const auto [rows, nc] = out_grad_chunks(n);
+        hipLaunchKernelGGL(out_grad_partial_kernel, dim3(unsigned(nc)), dim3(kThreads), 0, s->stream, n, W, no, rows,
+                           s->d_dy, s->d_a[D - 1], s->d_cpart);
+        const long L = long(no) * (W + 1);
+        hipLaunchKernelGGL(parts_reduce_kernel, dim3(unsigned((L + 15) / 16)), dim3(kThreads), 0, s->stream, int(nc),
+                           L, s->d_cpart, s->d_g + O.w_off);
+        // dZ of the last hidden layer = (dY W_O) through its SiLU
+        hipLaunchKernelGGL(out_back_kernel, dim3(blocks(n * (W / 4))), dim3(kThreads), 0, s->stream, n, W, no,
+                           s->d_dy, s->d_wb + O.w_off, s->d_z[D - 1], dz);
+        MCHK(s, hipGetLastError());
+    } else {
+        MTRY(gemm<EPI_F32>(s, no, W, int(n), s->d_dy, 1, no, s->d_a[D - 1], W, 1, s->d_g + O.w_off, W, 1, nullptr,
+                           nullptr));
+        hipLaunchKernelGGL(colsum_partial_kernel, dim3((no + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
+                           s->stream, n, no, s->d_dy, s->d_cpart, chunk);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((no + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk), no,
+                           s->d_cpart, s->d_g + O.b_off);
+        // dZ of the last hidden layer = (dY W_O) through its SiLU, in the GEMM epilogue
+        MTRY(gemm<EPI_SILU_BACK>(s, int(n), W, no, s->d_dy, no, 1, s->d_wb + O.w_off, W, 1, nullptr, W, 1, dz,
+                                 s->d_z[D - 1]));
+    }
     for (int l = D - 1; l >= 0; --l) {
         const Layer &L = s->layers[l];
         const uint16_t *ain = l > 0 ? s->d_a[l - 1] : s->d_x0;
         const int in = L.in;
-        MTRY(gemm<EPI_F32>(s, W, in, int(n), dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr));
-        hipLaunchKernelGGL(colsum_partial_kernel, dim3((W + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
-                           s->stream, n, W, dz, s->d_cpart, chunk);
-        hipLaunchKernelGGL(colsum_final_kernel, dim3((W + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk), W,
-                           s->d_cpart, s->d_g + L.b_off);
+        // the bias gradient (column sums of dZ) comes out of the weight-gradient GEMM
+        // when both operands stage along rows (aligned rows, widths of multiples of 8)
+        if (load_mode(dz, 1, W) == LD_RVEC && load_mode(ain, 1, in) == LD_RVEC) {
+            MTRY(gemm<EPI_F32>(s, W, in, int(n), dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr,
+                               nullptr, 0, s->d_g + L.b_off, 1024));
+        } else {
+            MTRY(gemm<EPI_F32>(s, W, in, int(n), dz, 1, W, ain, in, 1, s->d_g + L.w_off, in, 1, nullptr, nullptr,
+                               nullptr, 0, nullptr, 1024));
+            hipLaunchKernelGGL(colsum_partial_kernel, dim3((W + kThreads - 1) / kThreads, nchunk), dim3(kThreads), 0,
+                               s->stream, n, W, dz, s->d_cpart, chunk);
+            hipLaunchKernelGGL(colsum_final_kernel, dim3((W + 63) / 64), dim3(kThreads), 0, s->stream, int(nchunk),
+                               W, s->d_cpart, s->d_g + L.b_off);
+        }
         if (l > 0) {
             // dZ of layer l - 1 = (dZ_l W_l) through layer l - 1's SiLU
             MTRY(gemm<EPI_SILU_BACK>(s, int(n), in, W, dz, W, 1, s->d_wb + L.w_off, in, 1, nullptr, in, 1, dz_next,

@@ -112,11 +112,15 @@ def test_frequencies_are_gaussian():
     assert abs(B.mean()) < 0.06 and abs(B.std() - 2.0) < 0.05
 
 
-@pytest.mark.parametrize("depth,width", [(2, 64), (5, 256)])
-def test_gradient_matches_fp64_reference(torch_dev, depth, width):
+# n = 700: split-K weight gradients with the bias sums in their partials and a ragged
+# last chunk; n = 100: one k chunk (the bias sums written directly); n_out = 12: the
+# output layer through the GEMMs and column-sum kernels instead of its own kernels
+@pytest.mark.parametrize("depth,width,n_out,n", [(2, 64, 4, 700), (5, 256, 4, 700), (3, 128, 12, 700),
+                                                 (2, 64, 4, 100)])
+def test_gradient_matches_fp64_reference(torch_dev, depth, width, n_out, n):
     import torch
-    print(f"[gradient] depth={depth} width={width}", flush=True)
-    cfg, x, p, t = _small_case(21, 700, dict(n_param=8, n_freq=64, width=width, depth=depth, n_out=4))
+    print(f"[gradient] depth={depth} width={width} n_out={n_out} n={n}", flush=True)
+    cfg, x, p, t = _small_case(21, n, dict(n_param=8, n_freq=64, width=width, depth=depth, n_out=n_out))
     mlp = _mlp(**cfg, sigma=1.0, seed=5)
     B = mlp.frequencies().astype(np.float64)
     dx, dp, dt = (torch.from_numpy(a).to(torch_dev) for a in (x, p, t))
