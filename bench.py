@@ -100,6 +100,10 @@ def parse():
                     metavar=("WORKLOAD", "FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "COPY_MIB"),
                     help="write profiles/traffic_WORKLOAD.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE "
                          "databases of a bench run and of a --copy-calibration run")
+    ap.add_argument("--step-time-profile", action="store_true",
+                    help="per-region step time of the T4 ellipsoid along a run: 100 back-to-back regions of "
+                         "--steps steps from a fresh process, the same again from the initial state, then 40 "
+                         "regions each after 5 ms of idle")
     ap.add_argument("--mlp-train-timing", action="store_true",
                     help="time training steps of the surrogate network (width 256, depth 5, 16384 random "
                          "samples), fused forward against the layer-by-layer GEMMs")
@@ -292,6 +296,51 @@ def mlp_train_timing(args):
                     "gemm_TFLOPs": tm["gemm_flops"] / (tm["gemm_ms"] * 1e-3) / 1e12}
         log(f"[mlp] {key}: {out[key]}")
         m.close()
+    print(json.dumps(out), flush=True)
+
+
+def step_time_profile(args):
+    """How the time per step of a short timed region depends on the GPU's recent activity: regions
+    of --steps steps (each bracketed by device synchronisation, as in the timed run), back to back
+    from a fresh process, again from the same initial state once the GPU is busy, and with 5 ms
+    of idle before each region."""
+    import torch
+    from paper_2009_10400_amd import tled, workloads as W
+    p = W.ellipsoid_t4(args.elems)
+    stream = torch.cuda.Stream(device=0)
+    sim = tled.from_problem(p, device=0, stream=stream.cuda_stream, graph_steps=args.graph_steps)
+    blob = sim.get_state()
+    sim.prepare(args.steps)
+    torch.cuda.synchronize()
+    K = args.steps
+
+    def regions(n, idle=0.0):
+        us = []
+        for _ in range(n):
+            if idle:
+                time.sleep(idle)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sim.step(K)
+            torch.cuda.synchronize()
+            us.append(round(1e6 * (time.perf_counter() - t1) / K, 2))
+        return us
+
+    out = {"metric": "time per step of a timed region of K steps (us)", "workload": p.name, "elements": p.ne,
+           "K": K, "data": "synthetic"}
+    out["fresh_process"] = regions(100)
+    sim.set_state(blob)
+    out["again_from_initial_state"] = regions(100)
+    sim.set_state(blob)
+    out["idle_5ms_before_each"] = regions(40, idle=0.005)
+    t1 = time.perf_counter()
+    sim.step(2000)
+    torch.cuda.synchronize()
+    out["one_region_of_2000_steps"] = round(1e6 * (time.perf_counter() - t1) / 2000, 2)
+    for k in ("fresh_process", "again_from_initial_state", "idle_5ms_before_each"):
+        v = out[k]
+        log(f"[profile] {k}: first 5 {v[:5]}, median of the last half {float(np.median(v[len(v) // 2:])):.2f}")
+    sim.close()
     print(json.dumps(out), flush=True)
 
 
@@ -632,6 +681,9 @@ def main():
     if args.mlp_train_timing:
         mlp_train_timing(args)
         return
+    if args.step_time_profile:
+        step_time_profile(args)
+        return
     if args.counters_summary:
         counters_summary(*args.counters_summary)
         return
@@ -659,10 +711,12 @@ def main():
     sim.finalize()
     info = sim.info()
     log(f"[bench] finalize {time.time() - t:.1f}s info={info}")
+    # capture the hipGraphs the timed step(K) calls replay (set-up only: nothing runs) before the
+    # warm-up steps, so that no capture leaves the GPU idle between them and the timed regions (an
+    # idle GPU lowers its clock: `--step-time-profile` measures what idling costs a short region)
+    sim.prepare(args.steps)
     sim.step(args.warmup)
     sim.sync()
-    # capture the hipGraphs the timed step(K) calls replay (set-up only: nothing runs)
-    sim.prepare(args.steps)
     torch.cuda.synchronize()
     log("[bench] warmup done")
     # --repeats timed regions of exactly K steps each, every one bracketed by device
@@ -679,9 +733,9 @@ def main():
     value = p.ne / (ms_per_step * 1e-3)
     log(f"[bench] {len(reps)} timed regions of {args.steps} steps (ms/step): {[round(r, 5) for r in reps]}, "
         f"median {ms_per_step:.5f} -> {value:.4g} element-updates/s")
-    # context for short regions: every timed region, whatever its length, carries a fixed cost
-    # of tens of microseconds on the GPU (its own HIP events show it), which K = 20 spreads over
-    # few steps; one more region of at least 2000 steps gives the per-step time it approaches
+    # context for short regions: the first few hundred steps of a run cost more per step, and
+    # each region carries its own launch and synchronisation; one more region of at least 2000
+    # steps gives the per-step time a long run approaches
     steady = None
     if args.steps < 2000:
         n_long = 2000
