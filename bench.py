@@ -102,8 +102,9 @@ def parse():
                          "databases of a bench run and of a --copy-calibration run")
     ap.add_argument("--step-time-profile", action="store_true",
                     help="per-region step time of the T4 ellipsoid along a run: 100 back-to-back regions of "
-                         "--steps steps from a fresh process, the same again from the initial state, then 40 "
-                         "regions each after 5 ms of idle")
+                         "--steps steps from a fresh process, the same again from the initial state, 40 "
+                         "regions each after 5 ms of idle, one region of 2000 steps, then 30 regions from the "
+                         "initial state again")
     ap.add_argument("--mlp-train-timing", action="store_true",
                     help="time training steps of the surrogate network (width 256, depth 5, 16384 random "
                          "samples), fused forward against the layer-by-layer GEMMs")
@@ -337,7 +338,10 @@ def step_time_profile(args):
     sim.step(2000)
     torch.cuda.synchronize()
     out["one_region_of_2000_steps"] = round(1e6 * (time.perf_counter() - t1) / 2000, 2)
-    for k in ("fresh_process", "again_from_initial_state", "idle_5ms_before_each"):
+    sim.set_state(blob)
+    out["from_initial_state_after_that_region"] = regions(30)
+    for k in ("fresh_process", "again_from_initial_state", "idle_5ms_before_each",
+              "from_initial_state_after_that_region"):
         v = out[k]
         log(f"[profile] {k}: first 5 {v[:5]}, median of the last half {float(np.median(v[len(v) // 2:])):.2f}")
     sim.close()
