@@ -115,6 +115,19 @@ MUTATIONS = [
     ("conduction_sign",
      "double Tnew = T[a] + dt / Ca * (-Hc[a]", "double Tnew = T[a] + dt / Ca * (Hc[a]",
      [Q.test_transient_conduction_converges_to_linear_profile]),
+    # the H8 hourglass term (its coefficient is a reading; its arithmetic is pinned)
+    ("hourglass_coefficient_without_eighth",
+     "V0 * s / 8.0;", "V0 * s;",
+     [lambda: Q.test_hourglass_closed_form_on_a_cube(0.004)]),
+    ("hourglass_modulus_without_shear",
+     "khg = m->hg_coef * (m->kappa + 4.0 * m->mu / 3.0) * V0", "khg = m->hg_coef * m->kappa * V0",
+     [lambda: Q.test_hourglass_closed_form_on_a_cube(0.01)]),
+    ("hourglass_projection_sign",
+     "gam[8 * al + a] = h[al][a] - s;", "gam[8 * al + a] = h[al][a] + s;",
+     [Q.test_hourglass_vanishes_on_affine_fields]),
+    ("hourglass_energy_halved_twice",
+     "e_hg += 0.5 * khg *", "e_hg += 0.25 * khg *",
+     [lambda: Q.test_hourglass_closed_form_on_a_cube(0.004)]),
 ]
 
 

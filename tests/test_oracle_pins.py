@@ -301,6 +301,34 @@ def test_hourglass_vanishes_on_affine_fields():
     assert np.abs(f1.sum(0)).max() < 1e-12 * np.abs(f1).max()
 
 
+@pytest.mark.parametrize("L", [0.004, 0.01])
+def test_hourglass_closed_form_on_a_cube(L):
+    """The hourglass term as read for H8 elements (the paper only cites its source): on an
+    undistorted cube of side L the hourglass vectors reduce to the base vectors h (X^T h = 0),
+    every |dh_a/dX|^2 is 3/(16 L^2) at the centre, so k = 3 c (kappa + 4 mu / 3) L / 16, and the
+    mode u = a h e_i (which the one-point strain does not see) stores 32 k a^2 = 6 c (kappa +
+    4 mu / 3) L a^2 with nodal forces 8 k a h e_i.  Modes are orthogonal: energies add."""
+    c = 0.1
+    Xr = W.H8_CORNERS.astype(float) * L
+    xi, eta, zeta = (2 * W.H8_CORNERS.T - 1).astype(float)
+    modes = [xi * eta, eta * zeta, zeta * xi, xi * eta * zeta]
+    kk = 3 * c * (MAT["kappa"] + 4 * MAT["mu"] / 3) * L / 16
+    a = 1e-6
+    total_u, total_e = np.zeros((8, 3)), 0.0
+    for m, h in enumerate(modes):
+        for i in range(3):
+            ue = np.zeros((8, 3)); ue[:, i] = a * h
+            f, _, e = oracle.element(dict(MAT, hg_coef=c), Xr, ue, T0, [1, 0, 0])
+            assert e == pytest.approx(32 * kk * a * a, rel=1e-9)
+            fref = np.zeros((8, 3)); fref[:, i] = 8 * kk * a * h
+            assert np.abs(f - fref).max() <= 1e-9 * np.abs(fref).max()
+        # one mode per direction, summed: the energies add
+        total_u[:, m % 3] += (m + 1) * a * h
+        total_e += 32 * kk * ((m + 1) * a) ** 2
+    _, _, e = oracle.element(dict(MAT, hg_coef=c), Xr, total_u, T0, [1, 0, 0])
+    assert e == pytest.approx(total_e, rel=1e-9)
+
+
 def test_global_momentum_and_heat_conservation():
     """No fixed dofs, no perfusion: sum M v stays 0 and sum C T is conserved (sum_e of Eqs. 14, 23)."""
     X, conn, h = W.box_mesh("t4", 4, 0.02)
