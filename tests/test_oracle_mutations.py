@@ -115,6 +115,14 @@ MUTATIONS = [
     ("conduction_sign",
      "double Tnew = T[a] + dt / Ca * (-Hc[a]", "double Tnew = T[a] + dt / Ca * (Hc[a]",
      [Q.test_transient_conduction_converges_to_linear_profile]),
+    # the critical step (a reading): stable, and not needlessly small
+    ("critical_step_without_fibre",
+     "double cd = sqrt((m->kappa + 4.0 * m->mu / 3.0 + 4.0 * m->eta) / m->rho);",
+     "double cd = sqrt((m->kappa + 4.0 * m->mu / 3.0) / m->rho);",
+     [lambda: Q.test_critical_step_is_stable(4, 0.0)]),
+    ("critical_length_t4_without_three",
+     "return 3.0 * V0 / amax;", "return V0 / amax;",
+     [lambda: Q.test_critical_step_is_stable(4, 0.0)]),
     # the H8 hourglass term (its coefficient is a reading; its arithmetic is pinned)
     ("hourglass_coefficient_without_eighth",
      "V0 * s / 8.0;", "V0 * s;",

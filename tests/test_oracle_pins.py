@@ -432,6 +432,50 @@ def test_mass_invariants(kind, npe):
     assert np.all(V0 > 0)
 
 
+def _stability_limits(npe, jitter):
+    """Exact limits of a small box (2^3 cells, 8 mm): the undamped central-difference step 2/omega_max
+    with omega^2 the eigenvalues of M^-1 K, K the internal-force Jacobian at u = 0 by central
+    differences of the oracle's loads (elastic, fibre and hourglass stiffness included), and the
+    explicit heat step 2/lambda_max of C^-1 K_T likewise."""
+    X, conn, h = W.box_mesh("t4" if npe == 4 else "h8", 2, 0.008)
+    if jitter:
+        inner = np.all((X > 1e-9) & (X < 0.008 - 1e-9), axis=1)
+        X = X + jitter * h * np.random.default_rng(1).uniform(-1, 1, X.shape) * inner[:, None]
+    s = oracle.OracleSim(npe, X, conn, dict(MAT, hg_coef=0.1), dt=1e-5)
+    nn = X.shape[0]
+    T = np.full(nn, T0)
+    K = np.zeros((3 * nn, 3 * nn))
+    for j in range(3 * nn):
+        u = np.zeros((nn, 3)); u.flat[j] = 1e-9
+        Fp, _ = s.loads(u, T)
+        u.flat[j] = -1e-9
+        Fm, _ = s.loads(u, T)
+        K[:, j] = (Fp - Fm).ravel() / 2e-9
+    m = np.repeat(1 / np.sqrt(s.lumped()["M"]), 3)
+    A = m[:, None] * K * m[None, :]
+    w2 = np.linalg.eigvalsh(0.5 * (A + A.T)).max()
+    KT = np.zeros((nn, nn))
+    for j in range(nn):
+        Tp, Tm = T.copy(), T.copy()
+        Tp[j] += 1e-6; Tm[j] -= 1e-6
+        KT[:, j] = (s.loads(np.zeros((nn, 3)), Tp)[1] - s.loads(np.zeros((nn, 3)), Tm)[1]) / 2e-6
+    c = 1 / np.sqrt(MAT["rho"] * MAT["c"] * s.lumped()["Vl"])
+    B = c[:, None] * KT * c[None, :]
+    lt = np.linalg.eigvalsh(0.5 * (B + B.T)).max()
+    return s.critical_dt, 2 / np.sqrt(w2), 2 / lt
+
+
+@pytest.mark.parametrize("npe", [4, 8])
+@pytest.mark.parametrize("jitter", [0.0, 0.2])
+def test_critical_step_is_stable(npe, jitter):
+    """The critical step as read (min_e L_e / c_d, c_d with the fibre stiffness) against the exact
+    stability limits of the discrete system (Eq. 27 and the explicit heat update of Eq. 20): below
+    the undamped mechanical limit, within a factor of two of it, and far below the thermal one."""
+    dt_cr, dt_mech, dt_heat = _stability_limits(npe, jitter)
+    assert 0.5 * dt_mech <= dt_cr <= dt_mech
+    assert dt_cr < 1e-3 * dt_heat
+
+
 def test_c1_critical_step():
     """6000-tet cube (h = 4 mm): 0.8 * min L_e / c_d = 5.104e-4 s (Kuhn tet L = 3 V / A_max = h / sqrt 2)."""
     p = W.cube_t4()
