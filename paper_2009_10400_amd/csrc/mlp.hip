@@ -58,76 +58,129 @@ enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2, EPI_SILU_BACK = 3 };
 enum { LD_SCALAR = 0, LD_KVEC = 1, LD_RVEC = 2 };
 
 // One thread's share (8 values) of half h (k in [k0 + 32h, k0 + 32h + 32)) of a
-// 64 x 64 operand tile X(r, k) = X[r*sr + k*sk], rows r0.., zero outside r < R, k < ke.
+// 64 x 64 operand tile X(r, k) = X[r*sr + k*sk], rows r0.., zero outside r < R, k < ke,
+// packed two bfloat16 per 32-bit word (value i in the low half of word i/2 when even).
 struct TileRegs {
-    uint16_t v[8];
+    uint4 w;
 };
+
+__device__ inline uint4 pack8(const uint16_t (&e)[8]) {
+    return make_uint4(uint32_t(e[0]) | (uint32_t(e[1]) << 16), uint32_t(e[2]) | (uint32_t(e[3]) << 16),
+                      uint32_t(e[4]) | (uint32_t(e[5]) << 16), uint32_t(e[6]) | (uint32_t(e[7]) << 16));
+}
+
+// Value i of a thread's share, as a float.
+__device__ inline float tile_value(const TileRegs &q, int i) {
+    const uint32_t u = i < 2 ? q.w.x : i < 4 ? q.w.y : i < 6 ? q.w.z : q.w.w;
+    return bf2f(uint16_t((i & 1) ? (u >> 16) : (u & 0xffffu)));
+}
 
 template <int MODE>
 __device__ inline void tile_load(TileRegs &q, const uint16_t *__restrict__ X, long sr, long sk, int r0, int R,
                                  int k0, int ke, int t, int h) {
+    uint16_t e[8];
     if (MODE == LD_KVEC) {
         const int r = r0 + (t >> 2), k = k0 + 32 * h + (t & 3) * 8;
         if (r < R && k + 8 <= ke) {
-            const uint4 w = *reinterpret_cast<const uint4 *>(X + r * sr + k);
-            std::memcpy(q.v, &w, 16);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + k + i] : uint16_t(0);
+            q.w = *reinterpret_cast<const uint4 *>(X + r * sr + k);
+            return;
         }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = (r < R && k + i < ke) ? X[r * sr + k + i] : uint16_t(0);
     } else if (MODE == LD_RVEC) {
         const int k = k0 + 32 * h + (t >> 3), r = r0 + (t & 7) * 8;
         if (k < ke && r + 8 <= R) {
-            const uint4 w = *reinterpret_cast<const uint4 *>(X + k * sk + r);
-            std::memcpy(q.v, &w, 16);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q.v[i] = (k < ke && r + i < R) ? X[k * sk + r + i] : uint16_t(0);
+            q.w = *reinterpret_cast<const uint4 *>(X + k * sk + r);
+            return;
         }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = (k < ke && r + i < R) ? X[k * sk + r + i] : uint16_t(0);
     } else {
         const int r = r0 + (t >> 2), k = k0 + 32 * h + (t & 3) * 8;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) q.v[i] = (r < R && k + i < ke) ? X[r * sr + (k + i) * sk] : uint16_t(0);
+        for (int i = 0; i < 8; ++i) e[i] = (r < R && k + i < ke) ? X[r * sr + (k + i) * sk] : uint16_t(0);
     }
+    q.w = pack8(e);
 }
 
-// Stores a thread's share of half h into the LDS tile: S[r][k] (row pitch BKP), or,
-// for tiles read with rows contiguous, S[k][r] as loaded (one 16-byte store; the
-// MFMA fragments are then fetched with the transpose read, see frag()).
+// Stores a thread's share of half h of the 64-deep tile at k offset koff into an
+// LDS operand of row pitch P: S[r P + k], or, for tiles read with rows contiguous,
+// S[k P + r] as loaded (one 16-byte store either way; the MFMA fragments of a
+// k-major operand are then fetched with the transpose read, see frag()).
 template <int MODE>
-__device__ inline void tile_store(const TileRegs &q, uint16_t (*S)[BKP], int t, int h) {
-    static_assert(BM == BK && BN == BK, "a k-major tile reuses the r-major tile's array");
+__device__ inline void tile_store(const TileRegs &q, uint16_t *S, int P, int koff, int t, int h) {
     if (MODE == LD_RVEC) {
-        const int k = 32 * h + (t >> 3), r = (t & 7) * 8;
-        uint4 w;
-        std::memcpy(&w, q.v, 16);
-        *reinterpret_cast<uint4 *>(&S[k][r]) = w;
+        const int k = koff + 32 * h + (t >> 3), r = (t & 7) * 8;
+        *reinterpret_cast<uint4 *>(&S[k * P + r]) = q.w;
     } else {
-        const int r = t >> 2, k = 32 * h + (t & 3) * 8;
-        uint4 w;
-        std::memcpy(&w, q.v, 16);
-        *reinterpret_cast<uint4 *>(&S[r][k]) = w;
+        const int r = t >> 2, k = koff + 32 * h + (t & 3) * 8;
+        *reinterpret_cast<uint4 *>(&S[r * P + k]) = q.w;
     }
 }
 
-// The 16 x 32 MFMA operand fragment of rows r0..r0+15, k in [32h, 32h + 32), of an
-// LDS tile: lane l gets X(r0 + l%16, 32h + 8(l/16) + 0..7).  From an r-major tile
-// (S[r][k]) that is one 16-byte read.  From a k-major tile (S[k][r]) it takes two
-// ds_read_b64_tr_b16: each lane of a 16-lane group reads 4 consecutive values of
-// one k row, and the instruction hands lane i of the group value i%4 of lane
-// 4j + i/4's read as its value j; lane 4j + q therefore reads row k0 + j at
-// columns r0 + 4q.., which gives lane i the 4 k values of column r0 + i.
+// The 16 x 32 MFMA operand fragment of rows r0..r0+15, k in [k0, k0 + 32), of an
+// LDS operand of row pitch P: lane l gets X(r0 + l%16, k0 + 8(l/16) + 0..7).  From
+// an r-major operand (S[r P + k]) that is one 16-byte read.  From a k-major one
+// (S[k P + r]) it takes two ds_read_b64_tr_b16: each lane of a 16-lane group reads
+// 4 consecutive values of one k row, and the instruction hands lane i of the group
+// value i%4 of lane 4j + i/4's read as its value j; lane 4j + q therefore reads row
+// k + j at columns r0 + 4q.., which gives lane i the 4 k values of column r0 + i.
 template <int MODE>
-__device__ inline bf16x8 frag(const uint16_t (*S)[BKP], int r0, int h, int l) {
+__device__ inline bf16x8 frag(const uint16_t *S, int P, int r0, int k0, int l) {
     if (MODE == LD_RVEC) {
-        const int k = 32 * h + 8 * (l >> 4) + ((l & 15) >> 2), r = r0 + 4 * (l & 3);
-        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[k][r]));
-        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[k + 4][r]));
+        const int k = k0 + 8 * (l >> 4) + ((l & 15) >> 2), r = r0 + 4 * (l & 3);
+        const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[k * P + r]));
+        const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4 *)(&S[(k + 4) * P + r]));
         const i16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
         return __builtin_bit_cast(bf16x8, v);
     } else {
-        return *reinterpret_cast<const bf16x8 *>(&S[r0 + (l & 15)][32 * h + 8 * (l >> 4)]);
+        return *reinterpret_cast<const bf16x8 *>(&S[(r0 + (l & 15)) * P + k0 + 8 * (l >> 4)]);
     }
+}
+
+// COLS: thread t holds rows 8(t%8) + i of the A tile summed over its staged k; the 32
+// threads of a row group are combined in thread order into colsum[z M + m0 + ..].
+// red: 8 KB of LDS no longer read by the MFMA loop.
+__device__ inline void colsum_finish(const float (&cs)[8], float *red, int t, int m0, int M, float *colsum) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[(t >> 3) * 64 + 8 * (t & 7) + i] = cs[i];
+    __syncthreads();
+    if (t < 64 && m0 + t < M) {
+        float a = 0.f;
+        for (int g = 0; g < 32; ++g) a += red[g * 64 + t];
+        colsum[size_t(blockIdx.z) * M + m0 + t] = a;
+    }
+}
+
+// The epilogue of a wavefront's 32 x 32 output block (see gemm_kernel).
+template <int EPI>
+__device__ inline void gemm_epilogue(const f32x4 (&acc)[2][2], int m0, int n0, int wm, int wn, int l, int M, int N,
+                                     float *__restrict__ C, long scm, long scn, uint16_t *__restrict__ Act,
+                                     const float *__restrict__ bias) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * (l >> 4) + r;
+                const int n = n0 + wn + 16 * j + (l & 15);
+                if (m >= M || n >= N) continue;
+                float v = acc[i][j][r];
+                if (EPI == EPI_F32) {
+                    if (gridDim.z > 1) C[size_t(m) * N + n] = v;
+                    else C[m * scm + n * scn] = v;
+                } else if (EPI == EPI_BIAS_F32) {
+                    C[m * scm + n * scn] = v + bias[n];
+                } else if (EPI == EPI_SILU_BACK) {
+                    const float z = bias[size_t(m) * N + n], sg = sigmoidf_hw(z);
+                    Act[size_t(m) * N + n] = bf16_bits(v * sg * (1.0f + z * (1.0f - sg)));
+                } else {
+                    const float z = v + bias[n];
+                    C[m * scm + n * scn] = z;
+                    Act[size_t(m) * N + n] = bf16_bits(z * sigmoidf_hw(z));
+                }
+            }
 }
 
 // C = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (bfloat16 bits).
@@ -155,6 +208,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     long sbn, float *__restrict__ C, long scm, long scn, uint16_t *__restrict__ Act, const float *__restrict__ bias,
     int kchunk, float *__restrict__ colsum) {
     static_assert(!COLS || (EPI == EPI_F32 && AM == LD_RVEC), "column sums of an A tile staged along rows");
+    static_assert(BM == BK && BN == BK, "a k-major tile reuses the r-major tile's array");
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][BKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bt[2][BN][BKP];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -178,11 +232,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int h = 0; h < 2; ++h) {
             tile_load<AM>(qa[h], A, sam, sak, m0, M, kb, ke, t, h);
             tile_load<BMODE>(qb[h], B, sbn, sbk, n0, N, kb, ke, t, h);
-            tile_store<AM>(qa[h], As[0], t, h);
-            tile_store<BMODE>(qb[h], Bt[0], t, h);
+            tile_store<AM>(qa[h], &As[0][0][0], BKP, 0, t, h);
+            tile_store<BMODE>(qb[h], &Bt[0][0][0], BKP, 0, t, h);
             if (cols)
 #pragma unroll
-                for (int i = 0; i < 8; ++i) cs[i] += bf2f(qa[h].v[i]);
+                for (int i = 0; i < 8; ++i) cs[i] += tile_value(qa[h], i);
         }
     }
     __syncthreads();
@@ -201,10 +255,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             if (k0 + 32 * h >= ke) break;        // the same 32-deep MFMA steps as a 32-deep loop
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const bf16x8 a = frag<AM>(As[cur], wm + 16 * i, h, l);
+                const bf16x8 a = frag<AM>(&As[cur][0][0], BKP, wm + 16 * i, 32 * h, l);
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const bf16x8 b = frag<BMODE>(Bt[cur], wn + 16 * j, h, l);
+                    const bf16x8 b = frag<BMODE>(&Bt[cur][0][0], BKP, wn + 16 * j, 32 * h, l);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
                 }
             }
@@ -212,52 +266,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (more) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                tile_store<AM>(qa[h], As[cur ^ 1], t, h);
-                tile_store<BMODE>(qb[h], Bt[cur ^ 1], t, h);
+                tile_store<AM>(qa[h], &As[cur ^ 1][0][0], BKP, 0, t, h);
+                tile_store<BMODE>(qb[h], &Bt[cur ^ 1][0][0], BKP, 0, t, h);
                 if (cols)
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) cs[i] += bf2f(qa[h].v[i]);
+                    for (int i = 0; i < 8; ++i) cs[i] += tile_value(qa[h], i);
             }
         }
         __syncthreads();
     }
-    if (cols) {
-        // thread t holds rows 8(t%8) + i summed over k = 32h + t/8 of every tile;
-        // the LDS tiles are free after the loop's last barrier
-        float *red = reinterpret_cast<float *>(&As[0][0][0]);   // [32][64]
-#pragma unroll
-        for (int i = 0; i < 8; ++i) red[(t >> 3) * 64 + 8 * (t & 7) + i] = cs[i];
-        __syncthreads();
-        if (t < 64 && m0 + t < M) {
-            float a = 0.f;
-            for (int g = 0; g < 32; ++g) a += red[g * 64 + t];
-            colsum[size_t(blockIdx.z) * M + m0 + t] = a;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm + 16 * i + 4 * (l >> 4) + r;
-                const int n = n0 + wn + 16 * j + (l & 15);
-                if (m >= M || n >= N) continue;
-                float v = acc[i][j][r];
-                if (EPI == EPI_F32) {
-                    if (gridDim.z > 1) C[size_t(m) * N + n] = v;
-                    else C[m * scm + n * scn] = v;
-                } else if (EPI == EPI_BIAS_F32) {
-                    C[m * scm + n * scn] = v + bias[n];
-                } else if (EPI == EPI_SILU_BACK) {
-                    const float z = bias[size_t(m) * N + n], sg = sigmoidf_hw(z);
-                    Act[size_t(m) * N + n] = bf16_bits(v * sg * (1.0f + z * (1.0f - sg)));
-                } else {
-                    const float z = v + bias[n];
-                    C[m * scm + n * scn] = z;
-                    Act[size_t(m) * N + n] = bf16_bits(z * sigmoidf_hw(z));
-                }
-            }
+    if (cols) colsum_finish(cs, reinterpret_cast<float *>(&As[0][0][0]), t, m0, M, colsum);
+    gemm_epilogue<EPI>(acc, m0, n0, wm, wn, l, M, N, C, scm, scn, Act, bias);
 }
 
 // Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n); with
