@@ -114,9 +114,10 @@ def test_frequencies_are_gaussian():
 
 # n = 700: split-K weight gradients with the bias sums in their partials and a ragged
 # last chunk; n = 100: one k chunk (the bias sums written directly); n_out = 12: the
-# output layer through the GEMMs and column-sum kernels instead of its own kernels
+# output layer through the GEMMs and column-sum kernels instead of its own kernels; width 320:
+# the output-layer kernel's two column blocks and partial GEMM tiles (layer by layer)
 @pytest.mark.parametrize("depth,width,n_out,n", [(2, 64, 4, 700), (5, 256, 4, 700), (3, 128, 12, 700),
-                                                 (2, 64, 4, 100)])
+                                                 (2, 64, 4, 100), (2, 320, 4, 300)])
 def test_gradient_matches_fp64_reference(torch_dev, depth, width, n_out, n):
     import torch
     print(f"[gradient] depth={depth} width={width} n_out={n_out} n={n}", flush=True)
