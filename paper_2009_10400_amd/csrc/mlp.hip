@@ -139,8 +139,8 @@ __device__ inline bf16x8 frag(const uint16_t *S, int P, int r0, int k0, int l) {
 }
 
 // COLS: thread t holds rows 8(t%8) + i of the A tile summed over its staged k; the 32
-// threads of a row group are combined in thread order into colsum[z M + m0 + ..].
-// red: 8 KB of LDS no longer read by the MFMA loop.
+// threads of a row group are combined in thread order into colsum[m0 + ..] (colsum:
+// this k chunk's partials).  red: 8 KB of LDS no longer read by the MFMA loop.
 __device__ inline void colsum_finish(const float (&cs)[8], float *red, int t, int m0, int M, float *colsum) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) red[(t >> 3) * 64 + 8 * (t & 7) + i] = cs[i];
@@ -148,7 +148,7 @@ __device__ inline void colsum_finish(const float (&cs)[8], float *red, int t, in
     if (t < 64 && m0 + t < M) {
         float a = 0.f;
         for (int g = 0; g < 32; ++g) a += red[g * 64 + t];
-        colsum[size_t(blockIdx.z) * M + m0 + t] = a;
+        colsum[m0 + t] = a;
     }
 }
 
@@ -183,6 +183,21 @@ __device__ inline void gemm_epilogue(const f32x4 (&acc)[2][2], int m0, int n0, i
             }
 }
 
+// XCD-aware tile order.  The hardware hands workgroup H (x fastest, then y, then z)
+// to XCD H mod 8; with the tile count a multiple of 8, each XCD takes one contiguous
+// range of the tiles in that order instead, so the workgroups that share operand rows
+// (the column tiles of one row block; all tiles of one k chunk) run on the same XCD
+// and read them through its L2 once.  Only which workgroup computes a tile changes.
+constexpr int kNumXcd = 8;
+__device__ inline void tile_of_block(int &bx, int &by, int &bz) {
+    const int nx = int(gridDim.x), ny = int(gridDim.y), T = nx * ny * int(gridDim.z);
+    int H = int(blockIdx.x) + nx * (int(blockIdx.y) + ny * int(blockIdx.z));
+    if (T % kNumXcd == 0) H = (H % kNumXcd) * (T / kNumXcd) + H / kNumXcd;
+    bx = H % nx;
+    by = (H / nx) % ny;
+    bz = H / (nx * ny);
+}
+
 // C = A B with A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (bfloat16 bits).
 // 64x64 output tile per workgroup of four wavefronts, each wavefront 32x32 as
 // 2x2 MFMA 16x16x32 tiles.  Lane l of a 16x16x32 MFMA supplies A[l%16][8(l/16)..+7]
@@ -211,7 +226,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     static_assert(BM == BK && BN == BK, "a k-major tile reuses the r-major tile's array");
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][BKP];
     __shared__ __attribute__((aligned(16))) uint16_t Bt[2][BN][BKP];
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    int bx, by, bz;
+    tile_of_block(bx, by, bz);
+    const int m0 = by * BM, n0 = bx * BN;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
     f32x4 acc[2][2];
@@ -219,10 +236,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-    if (gridDim.z > 1) C += size_t(blockIdx.z) * M * N;
+    const int kb = bz * kchunk, ke = min(K, kb + kchunk);
+    if (gridDim.z > 1) C += size_t(bz) * M * N;
     const int ntiles = ke > kb ? (ke - kb + BK - 1) / BK : 0;
-    const bool cols = COLS && blockIdx.x == 0;
+    const bool cols = COLS && bx == 0;
     float cs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     TileRegs qa[2], qb[2];
     // double-buffered 64-deep k tiles: tile t + 1 is read from global memory into
@@ -275,7 +292,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         }
         __syncthreads();
     }
-    if (cols) colsum_finish(cs, reinterpret_cast<float *>(&As[0][0][0]), t, m0, M, colsum);
+    if (cols) colsum_finish(cs, reinterpret_cast<float *>(&As[0][0][0]), t, m0, M, colsum + size_t(bz) * M);
     gemm_epilogue<EPI>(acc, m0, n0, wm, wn, l, M, N, C, scm, scn, Act, bias);
 }
 
