@@ -215,8 +215,9 @@ __device__ inline void tile_of_block(int &bx, int &by, int &bz) {
 // gradient beside its weight gradient): each thread adds the 8 values it stages,
 // tile by tile in increasing k, and the 32 threads of a row group are combined in
 // thread order.
-// Four wavefronts per SIMD: the k loop waits on global memory, so occupancy is what
-// hides the latency (the accumulators live in VGPRs, no spills).
+// Four wavefronts per SIMD (four workgroups per CU, which is also what the 36.9 KB of
+// LDS allows): the k loop waits on global memory, so occupancy is what hides the
+// latency (64-68 VGPRs with the staged values packed two per register).
 template <int EPI, int AM, int BMODE, bool COLS = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void gemm_kernel(
     int M, int N, int K, const uint16_t *__restrict__ A, long sam, long sak, const uint16_t *__restrict__ B, long sbk,
