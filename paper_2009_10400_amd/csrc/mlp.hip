@@ -426,38 +426,34 @@ std::pair<long, long> out_grad_chunks(long n) {
 
 // dZ of the last hidden layer for n_out <= kOutMax: (dY W_O)(r, j) = sum_o dY(r, o) W_O(o, j)
 // in increasing o, through the SiLU at z(r, j) (the arithmetic of the GEMM epilogue).
-// Four columns per thread (W is a multiple of 64).
+// Eight columns per thread (W is a multiple of 64): 16-byte weight loads and dZ stores.
 __global__ void out_back_kernel(long n, int W, int no, const uint16_t *__restrict__ dY,
                                 const uint16_t *__restrict__ WO, const float *__restrict__ Z,
                                 uint16_t *__restrict__ dZ) {
     const long idx = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int q = W / 4;
+    const int q = W / 8;
     if (idx >= n * q) return;
     const long r = idx / q;
-    const int j = 4 * int(idx % q);
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    const int j = 8 * int(idx % q);
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int o = 0; o < kOutMax; ++o)
         if (o < no) {
             const float d = bf2f(dY[r * no + o]);
-            const uint2 wv = *reinterpret_cast<const uint2 *>(WO + size_t(o) * W + j);
-            v[0] += d * bf2f(uint16_t(wv.x & 0xffffu));
-            v[1] += d * bf2f(uint16_t(wv.x >> 16));
-            v[2] += d * bf2f(uint16_t(wv.y & 0xffffu));
-            v[3] += d * bf2f(uint16_t(wv.y >> 16));
-        }
-    const float4 z4 = *reinterpret_cast<const float4 *>(Z + r * W + j);
-    const float zz[4] = {z4.x, z4.y, z4.z, z4.w};
-    uint16_t h[4];
+            const TileRegs wv{*reinterpret_cast<const uint4 *>(WO + size_t(o) * W + j)};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float z = zz[i], sg = sigmoidf_hw(z);
-        h[i] = bf16_bits(v[i] * sg * (1.0f + z * (1.0f - sg)));
+            for (int c = 0; c < 8; ++c) v[c] += d * tile_value(wv, c);
+        }
+    const float4 za = *reinterpret_cast<const float4 *>(Z + r * W + j);
+    const float4 zb = *reinterpret_cast<const float4 *>(Z + r * W + j + 4);
+    const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+    uint16_t h[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float z = zz[c], sg = sigmoidf_hw(z);
+        h[c] = bf16_bits(v[c] * sg * (1.0f + z * (1.0f - sg)));
     }
-    uint2 o2;
-    o2.x = uint32_t(h[0]) | (uint32_t(h[1]) << 16);
-    o2.y = uint32_t(h[2]) | (uint32_t(h[3]) << 16);
-    *reinterpret_cast<uint2 *>(dZ + r * W + j) = o2;
+    *reinterpret_cast<uint4 *>(dZ + r * W + j) = pack8(h);
 }
 
 // Features of sample i: [sin(2 pi B x_i), cos(2 pi B x_i), p_i, 0 ...] as bfloat16 (row of K0).
@@ -1170,7 +1166,7 @@ tled_status backward(tled_mlp *s, long n, const float *target, float *loss) {
         hipLaunchKernelGGL(parts_reduce_kernel, dim3(unsigned((L + 15) / 16)), dim3(kThreads), 0, s->stream, int(nc),
                            L, s->d_cpart, s->d_g + O.w_off);
         // dZ of the last hidden layer = (dY W_O) through its SiLU
-        hipLaunchKernelGGL(out_back_kernel, dim3(blocks(n * (W / 4))), dim3(kThreads), 0, s->stream, n, W, no,
+        hipLaunchKernelGGL(out_back_kernel, dim3(blocks(n * (W / 8))), dim3(kThreads), 0, s->stream, n, W, no,
                            s->d_dy, s->d_wb + O.w_off, s->d_z[D - 1], dz);
         MCHK(s, hipGetLastError());
     } else {
