@@ -183,6 +183,48 @@ __device__ inline void gemm_epilogue(const f32x4 (&acc)[2][2], int m0, int n0, i
             }
 }
 
+// EPI_SILU_BACK through LDS: the workgroup's 64 x 64 FP32 products go to LDS, then
+// each thread takes 16 consecutive columns of one row, so the pre-activations are read
+// and dZ written in 16-byte vectors (the arithmetic of gemm_epilogue, element by
+// element).  tile: at least 64 x 68 floats of LDS that the k loop no longer reads.
+// (Split-K partials written the same way measured slower than gemm_epilogue's.)
+__device__ inline void silu_back_epilogue(const f32x4 (&acc)[2][2], float *tile, int m0, int n0, int wm, int wn,
+                                          int l, int t, int M, int N, uint16_t *__restrict__ Act,
+                                          const float *__restrict__ Z) {
+    constexpr int TP = BN + 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[(wm + 16 * i + 4 * (l >> 4) + r) * TP + wn + 16 * j + (l & 15)] = acc[i][j][r];
+    __syncthreads();
+    const int row = t >> 2, c0 = 16 * (t & 3), m = m0 + row;
+    if (m >= M) return;
+#pragma unroll
+    for (int q = 0; q < 16; q += 8) {
+        const int n = n0 + c0 + q;
+        const float *v = tile + row * TP + c0 + q;
+        if (N % 8 == 0 && n + 8 <= N) {
+            const float4 za = *reinterpret_cast<const float4 *>(Z + size_t(m) * N + n);
+            const float4 zb = *reinterpret_cast<const float4 *>(Z + size_t(m) * N + n + 4);
+            const float zz[8] = {za.x, za.y, za.z, za.w, zb.x, zb.y, zb.z, zb.w};
+            uint16_t h[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float z = zz[c], sg = sigmoidf_hw(z);
+                h[c] = bf16_bits(v[c] * sg * (1.0f + z * (1.0f - sg)));
+            }
+            *reinterpret_cast<uint4 *>(Act + size_t(m) * N + n) = pack8(h);
+        } else {
+            for (int c = 0; c < 8 && n + c < N; ++c) {
+                const float z = Z[size_t(m) * N + n + c], sg = sigmoidf_hw(z);
+                Act[size_t(m) * N + n + c] = bf16_bits(v[c] * sg * (1.0f + z * (1.0f - sg)));
+            }
+        }
+    }
+}
+
 // XCD-aware tile order.  The hardware hands workgroup H (x fastest, then y, then z)
 // to XCD H mod 8; with the tile count a multiple of 8, each XCD takes one contiguous
 // range of the tiles in that order instead, so the workgroups that share operand rows
@@ -294,7 +336,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         __syncthreads();
     }
     if (cols) colsum_finish(cs, reinterpret_cast<float *>(&As[0][0][0]), t, m0, M, colsum + size_t(bz) * M);
-    gemm_epilogue<EPI>(acc, m0, n0, wm, wn, l, M, N, C, scm, scn, Act, bias);
+    if constexpr (EPI == EPI_SILU_BACK) {
+        static_assert(sizeof(As) >= sizeof(float) * BM * (BN + 4), "the FP32 tile fits in the A tiles' LDS");
+        silu_back_epilogue(acc, reinterpret_cast<float *>(&As[0][0][0]), m0, n0, wm, wn, l, t, M, N, Act, bias);
+    } else {
+        gemm_epilogue<EPI>(acc, m0, n0, wm, wn, l, M, N, C, scm, scn, Act, bias);
+    }
 }
 
 // Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n); with
