@@ -345,25 +345,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 // Fixed-order sum of split-K partials (nz x M x N, row-major) into C(m, n); with
-// bout, threads past M x N sum the column-sum partials (nz x M) into bout[m].
-__global__ void splitk_reduce_kernel(int nz, int M, int N, const float *__restrict__ part, float *__restrict__ C,
-                                     long scm, long scn, const float *__restrict__ bpart, float *__restrict__ bout) {
-    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    const long MN = long(M) * N;
-    if (i >= MN) {
-        if (!bout || i >= MN + M) return;
-        const long m = i - MN;
-        float s = 0.f;
-#pragma unroll 8
-        for (int z = 0; z < nz; ++z) s += bpart[size_t(z) * M + m];
-        bout[m] = s;
-        return;
-    }
+// bout, the elements past M x N are the column-sum partials (nz x M), summed into
+// bout[m].  A block takes 64 elements; wavefront w adds partials w, w + 4, ... in
+// order (64 consecutive elements per load), and the four sums are combined as
+// (s0 + s1) + (s2 + s3).
+__global__ __launch_bounds__(kThreads) void splitk_reduce_kernel(int nz, int M, int N, const float *__restrict__ part,
+                                                                 float *__restrict__ C, long scm, long scn,
+                                                                 const float *__restrict__ bpart,
+                                                                 float *__restrict__ bout) {
+    __shared__ float sh[4][64];
+    const long MN = long(M) * N, E = MN + (bout ? M : 0);
+    const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
+    const long i = long(blockIdx.x) * 64 + c;
     float s = 0.f;
+    if (i < MN) {
 #pragma unroll 8
-    for (int z = 0; z < nz; ++z) s += part[size_t(z) * M * N + i];   // loads in flight, additions in order
-    const long m = i / N, n = i % N;
-    C[m * scm + n * scn] = s;
+        for (int z = w; z < nz; z += 4) s += part[size_t(z) * MN + i];   // loads in flight, additions in order
+    } else if (i < E) {
+#pragma unroll 8
+        for (int z = w; z < nz; z += 4) s += bpart[size_t(z) * M + (i - MN)];
+    }
+    sh[w][c] = s;
+    __syncthreads();
+    if (w == 0 && i < E) {
+        const float v = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+        if (i < MN) {
+            const long m = i / N, n = i % N;
+            C[m * scm + n * scn] = v;
+        } else {
+            bout[i - MN] = v;
+        }
+    }
 }
 
 // Output layer's gradient for n_out <= kOutMax, one pass over the last hidden
@@ -1078,8 +1090,8 @@ tled_status gemm(tled_mlp *s, int M, int N, int K, const uint16_t *A, long sam, 
     else TLED_GEMM_LAUNCH(LD_SCALAR, LD_SCALAR, false);
 #undef TLED_GEMM_LAUNCH
     if (nz > 1)
-        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks(long(M) * N + (colsum ? M : 0))), dim3(kThreads), 0,
-                           s->stream, nz, M, N, split, C, scm, scn, cpart, colsum);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(unsigned((long(M) * N + (colsum ? M : 0) + 63) / 64)),
+                           dim3(kThreads), 0, s->stream, nz, M, N, split, C, scm, scn, cpart, colsum);
     MCHK(s, hipGetLastError());
     if (timed) {
         MCHK(s, hipEventRecord(e1, s->stream));
