@@ -636,6 +636,7 @@ __global__ void to_bf16_kernel(long n, const float *__restrict__ x, uint16_t *__
 // three waves per SIMD (152 VGPRs for width 256, no spills): at millions of
 // samples the extra wave hides more of the weight-load latency.
 constexpr int kFusedRows = 64;
+constexpr int kTrainWaves = 8;   // wavefronts per workgroup of the training forward (widths >= 128)
 constexpr int kFusedMaxDepth = 8;
 struct NetOffsets {
     long w[kFusedMaxDepth + 1];
@@ -695,8 +696,8 @@ __device__ __forceinline__ void fused_layer_k(f32x4 (&acc)[4][NT], const uint16_
 
 // TRAIN: also stores the features, pre-activations and activations (TrainStore)
 // for the backward pass.
-template <int W, bool TRAIN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(long n, const float *__restrict__ x,
+template <int W, bool TRAIN, int NW = 4>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(long n, const float *__restrict__ x,
                                                                  const float *__restrict__ p,
                                                                  const float *__restrict__ Bf, int nf, int np,
                                                                  int K0, int depth, int nout,
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const int P = (K0 > W ? K0 : W) + 8;          // LDS row pitch (elements)
     const long r0 = long(blockIdx.x) * kFusedRows;
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    for (int idx = t; idx < kFusedRows * K0; idx += kThreads) {
+    for (int idx = t; idx < kFusedRows * K0; idx += 64 * NW) {
         const int row = idx / K0, j = idx % K0;
         const long i = r0 + row;
         float v = 0.f;
@@ -725,8 +726,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
         if (TRAIN && i < n) ts.x0[i * K0 + j] = bits;
     }
     __syncthreads();
-    constexpr int NT = W / 64;                     // 16-column tiles per wavefront
-    const int nb = w * (W / 4);
+    constexpr int NT = W / (16 * NW);              // 16-column tiles per wavefront
+    static_assert(NT >= 1, "at least one 16-unit tile per wavefront");
+    const int nb = w * (W / NW);
     for (int layer = 0; layer < depth; ++layer) {
         const uint16_t *Wl = wb + off.w[layer];
         f32x4 acc[4][NT];
@@ -763,7 +765,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
         }
         __syncthreads();
     }
-    // output layer: rows [16w, 16w + 16), up to four 16-column tiles
+    // output layer: rows [16w, 16w + 16) for the first four wavefronts, up to four 16-column tiles
+    if (w >= 4) return;
     const uint16_t *Wo = wb + off.w[depth];
     const float *bo = wf + off.b[depth];
     f32x4 acc[4];
@@ -1133,18 +1136,18 @@ tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float 
         MCHK(s, hipEventCreate(&e1));
         MCHK(s, hipEventRecord(e0, s->stream));
     }
-#define TLED_FUSED(WIDTH, TR)                                                                               \
-    hipLaunchKernelGGL((fused_forward_kernel<WIDTH, TR>), dim3(grid), dim3(kThreads), lds, s->stream, n,    \
+#define TLED_FUSED(WIDTH, TR, NW)                                                                           \
+    hipLaunchKernelGGL((fused_forward_kernel<WIDTH, TR, NW>), dim3(grid), dim3(64 * NW), lds, s->stream, n,  \
                        coords, params, s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->cfg.depth,         \
                        s->cfg.n_out, s->d_wb, s->d_w, off, out, ts ? *ts : TrainStore{})
     if (ts) {
-        if (s->cfg.width == 64) TLED_FUSED(64, true);
-        else if (s->cfg.width == 128) TLED_FUSED(128, true);
-        else TLED_FUSED(256, true);
+        if (s->cfg.width == 64) TLED_FUSED(64, true, 4);
+        else if (s->cfg.width == 128) TLED_FUSED(128, true, kTrainWaves);
+        else TLED_FUSED(256, true, kTrainWaves);
     } else {
-        if (s->cfg.width == 64) TLED_FUSED(64, false);
-        else if (s->cfg.width == 128) TLED_FUSED(128, false);
-        else TLED_FUSED(256, false);
+        if (s->cfg.width == 64) TLED_FUSED(64, false, 4);
+        else if (s->cfg.width == 128) TLED_FUSED(128, false, 4);
+        else TLED_FUSED(256, false, 4);
     }
 #undef TLED_FUSED
     MCHK(s, hipGetLastError());
