@@ -636,7 +636,6 @@ __global__ void to_bf16_kernel(long n, const float *__restrict__ x, uint16_t *__
 // three waves per SIMD (152 VGPRs for width 256, no spills): at millions of
 // samples the extra wave hides more of the weight-load latency.
 constexpr int kFusedRows = 64;
-constexpr int kTrainWaves = 8;   // wavefronts per workgroup of the training forward (widths >= 128)
 constexpr int kFusedMaxDepth = 8;
 struct NetOffsets {
     long w[kFusedMaxDepth + 1];
@@ -915,6 +914,7 @@ tled_status resolve_scratch(int device) {
 
 struct tled_mlp {
     int device = 0;
+    int cus = 256;                     // compute units of the device
     float *d_static_split = nullptr;   // this device's `scratch` (resolved at creation)
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -1140,14 +1140,17 @@ tled_status fused_forward(tled_mlp *s, long n, const float *coords, const float 
     hipLaunchKernelGGL((fused_forward_kernel<WIDTH, TR, NW>), dim3(grid), dim3(64 * NW), lds, s->stream, n,  \
                        coords, params, s->d_freq, s->cfg.n_freq, s->cfg.n_param, s->K0, s->cfg.depth,         \
                        s->cfg.n_out, s->d_wb, s->d_w, off, out, ts ? *ts : TrainStore{})
+    // fewer than two workgroups per CU: eight wavefronts each (measured faster at 16k
+    // samples, slower at 1M, same bits either way)
+    const bool wide = long(grid) < 2L * s->cus;
     if (ts) {
         if (s->cfg.width == 64) TLED_FUSED(64, true, 4);
-        else if (s->cfg.width == 128) TLED_FUSED(128, true, kTrainWaves);
-        else TLED_FUSED(256, true, kTrainWaves);
+        else if (s->cfg.width == 128) { if (wide) TLED_FUSED(128, true, 8); else TLED_FUSED(128, true, 4); }
+        else { if (wide) TLED_FUSED(256, true, 8); else TLED_FUSED(256, true, 4); }
     } else {
         if (s->cfg.width == 64) TLED_FUSED(64, false, 4);
-        else if (s->cfg.width == 128) TLED_FUSED(128, false, 4);
-        else TLED_FUSED(256, false, 4);
+        else if (s->cfg.width == 128) { if (wide) TLED_FUSED(128, false, 8); else TLED_FUSED(128, false, 4); }
+        else { if (wide) TLED_FUSED(256, false, 8); else TLED_FUSED(256, false, 4); }
     }
 #undef TLED_FUSED
     MCHK(s, hipGetLastError());
@@ -1293,6 +1296,10 @@ tled_status tled_mlp_create(tled_mlp **out, int device, const tled_mlp_config *c
     tled_mlp *s = new (std::nothrow) tled_mlp();
     if (!s) return TLED_E_OOM;
     s->device = device;
+    if (hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        delete s;
+        return TLED_E_HIP;
+    }
     {
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         s->d_static_split = g_scratch_addr[device];

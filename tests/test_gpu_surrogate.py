@@ -88,8 +88,9 @@ def test_forward_matches_reference(torch_dev, n, layerwise):
     assert np.abs(y - yr).max() <= 2e-2 * scale, (np.abs(y - yr).max(), scale)
 
 
+# n = 40000 and 70001: 625 and 1094 workgroups, four wavefronts each (eight below two per CU)
 @pytest.mark.parametrize("width,depth,n_out,n", [(64, 2, 4, 1000), (256, 5, 4, 4097), (128, 3, 20, 77),
-                                                  (256, 1, 1, 1)])
+                                                  (256, 1, 1, 1), (256, 5, 4, 40000), (128, 2, 4, 70001)])
 def test_fused_inference_equals_layerwise(torch_dev, width, depth, n_out, n):
     """The fused whole-network kernel and the layer-by-layer GEMMs give the same bits."""
     import torch
@@ -172,7 +173,7 @@ def test_training_reduces_loss_and_is_deterministic(torch_dev):
     assert np.array_equal(a.params(), b.params())
 
 
-@pytest.mark.parametrize("width,depth,n", [(64, 2, 1000), (256, 5, 4097), (128, 3, 77)])
+@pytest.mark.parametrize("width,depth,n", [(64, 2, 1000), (256, 5, 4097), (128, 3, 77), (256, 2, 40000)])
 def test_fused_training_forward_equals_layerwise(torch_dev, width, depth, n):
     """Training steps whose forward pass is the fused kernel (storing the features, every
     pre-activation and activation for the backward pass) leave the same parameters, bit for bit,
